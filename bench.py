@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Benchmark: CTIS EM reconstruction of one synthetic frame on one MI355X.
+
+One step = one full EM solve of the workload (the datacube reset to all ones,
+then the configuration's iteration count of fused forward+ratio and
+adjoint+update kernels), with the plan and the frame already resident in GPU
+memory.  The JSON line reports EM iterations/s (the headline), voxel updates/s,
+the roofline position of the dominant kernel (HIP-event durations of every
+launch, measured in a second timed pass over the same steps), and the FP64
+oracle's rate on the host cores over a bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--config 2]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "EM iterations/s + voxel-updates/s vs HBM roofline; batched frames/s vs plain"
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
+FP32_VALU_PEAK_TFLOPS = 157.3    # MI355X vector FP32 (counts packed FP32 FMA)
+FP32_VALU_UNPACKED_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2006_01573_amd", "csrc", "kernels.hip")
+
+
+def progress(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_sha() -> str:
+    with open(KERNEL_SOURCE, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def measured_traffic(config_id: int, kernel: str):
+    """HBM bytes per launch from committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    counters, if they were taken on the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    e = d.get("workloads", {}).get(str(config_id), {}).get(kernel)
+    if not e:
+        return None
+    return float(e["bytes_per_launch"])
+
+
+def cpu_baseline(case, g_host: np.ndarray, iters_per_step: int, seconds: float):
+    """The FP64 oracle (explicit H, OpenMP) on the host cores: EM iterations
+    from all ones in chunks until `seconds` have passed.  Assembly excluded."""
+    import oracle
+    progress("cpu baseline: assembling the explicit H")
+    o = oracle.Oracle.from_case(case)
+    chunk = 10
+    done = 0
+    f = None
+    t0 = time.perf_counter()
+    while True:
+        f = o.em(g_host, chunk, f0=f)
+        done += chunk
+        el = time.perf_counter() - t0
+        if el >= seconds or done >= 100_000:
+            break
+    rate = done / el
+    return {"value": rate, "unit": "EM iterations/s", "cores": o.threads, "kind": "oracle",
+            "sample": f"{done} EM iterations of the same frame from all ones ({el:.1f} s, FP64 explicit "
+                      f"sparse H, assembly excluded); one step of {iters_per_step} iterations would take "
+                      f"{iters_per_step / rate:.3f} s"}
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3])
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
+              "the path would shard by frame or by wavelength across GPUs, which is not built here.",
+              file=sys.stderr)
+        return 2
+    if args.steps < 1 or args.warmup < 0:
+        print("bench.py: --steps must be >= 1 and --warmup >= 0", file=sys.stderr)
+        return 2
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        return 1
+    from paper_2006_01573_amd import ctis, workloads as W
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    case = W.make_case(args.config)
+    cfg = case.cfg
+    geo = case.geometry
+    K = cfg.iters
+    progress(f"workload {cfg.name}: plan")
+    plan = ctis.Plan.from_case(case)
+    info = plan.info
+    # the frame: Poisson noise on H f_true, formed with the library's own forward
+    f_true = torch.from_numpy(case.f_true.astype(np.float32)).to(dev)
+    clean = plan.forward(f_true).double().cpu().numpy()
+    g_host = case.noisy(clean)
+    g = torch.from_numpy(g_host).to(dev)
+    f = torch.empty(plan.shape_f, dtype=torch.float32, device=dev)
+    ws = plan.workspace()
+    torch.cuda.synchronize()
+
+    def step():
+        f.fill_(1.0)
+        plan.em(g, K, f=f, workspace=ws)
+
+    progress(f"warmup {args.warmup} steps")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    progress(f"timing {args.steps} steps of {K} EM iterations")
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms = e0.elapsed_time(e1)
+    sec = ms / 1e3
+    it_s = args.steps * K / sec
+    f_out = f.clone()
+    if not torch.isfinite(f_out).all() or (f_out < 0).any():
+        print("bench.py: EM produced a negative or non-finite value", file=sys.stderr)
+        return 1
+
+    # per-kernel durations (HIP events around every launch, same stream)
+    progress("per-kernel timing pass")
+    fw_ms = ad_ms = 0.0
+    for _ in range(args.steps):
+        f.fill_(1.0)
+        a_, b_ = plan.em_timed(g, K, f, ws)
+        fw_ms += a_
+        ad_ms += b_
+    launches = args.steps * K
+    avg = {"forward_ratio": fw_ms / launches * 1e-3, "adjoint_update": ad_ms / launches * 1e-3}
+    m, n_supp = info.m, info.n_support
+    bytes_ = {"forward_ratio": 4 * (m + 2 * n_supp), "adjoint_update": 4 * (2 * m + n_supp)}
+    flops_ = {k: 2 * info.ell * info.nnz for k in bytes_}
+    dom = max(avg, key=avg.get)
+    t_hbm = bytes_[dom] / (HBM_PEAK_GBS * 1e9)
+    t_alu = flops_[dom] / (FP32_VALU_PEAK_TFLOPS * 1e12)
+    traffic = measured_traffic(args.config, dom)
+    if t_hbm >= t_alu:
+        achieved = bytes_[dom] / avg[dom] / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic}
+    else:
+        achieved = flops_[dom] / avg[dom] / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP32_VALU_PEAK_TFLOPS, "traffic": traffic,
+                "frac_of_unpacked_fp32": achieved / FP32_VALU_UNPACKED_TFLOPS}
+    roof.update({"kernel": dom, "avg_launch_us": avg[dom] * 1e6,
+                 "algorithmic_bytes_per_launch": bytes_[dom], "algorithmic_flop_per_launch": flops_[dom],
+                 "other_kernel": {k: {"avg_launch_us": avg[k] * 1e6,
+                                      "achieved_GBps": bytes_[k] / avg[k] / 1e9}
+                                  for k in avg if k != dom}})
+
+    line = {
+        "metric": METRIC,
+        "value": it_s,
+        "unit": "EM iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": cfg.name, "a": geo.a, "alpha": geo.alpha, "w": geo.w,
+                   "gamma": geo.gamma, "xi": geo.xi, "m": m, "n": geo.n, "n_support": n_supp,
+                   "nnz": info.nnz, "box": info.box, "em_iters_per_step": K,
+                   "start": "all ones", "noise": f"Poisson, {cfg.noise} {cfg.photons:g}"},
+        "voxel_updates_per_s": it_s * m,
+        "frames_per_s": args.steps / sec,
+        "wall_s": wall,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(case, g_host, K, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+    plan.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

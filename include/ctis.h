@@ -1,0 +1,213 @@
+/*
+ * ctis.h -- C ABI of the MI355X CTIS EM reconstruction library (libctis.so).
+ *
+ * The library reconstructs a hyperspectral datacube f from one computed-
+ * tomographic-imaging-spectrometer frame g by the expectation-maximisation
+ * iteration of White, Bell & Haygood (Sec. 2 eq. (em)):
+ *
+ *     f <- (f / h) . H^T (g / (H f)),      h_j = sum_i H_ij,
+ *
+ * where the n x m system matrix H is never stored.  Under the paper's spatial
+ * shift-invariance (Sec. 2, calibration paragraph) every column of wavelength
+ * block s is the calibration image c_s shifted by the voxel's field-stop
+ * position; Sec. 3 writes this as H_s = C_s E (eq. (decomposition)), C_s the
+ * n x n circulant with first column c_s and E the zero-padding embedding of
+ * the a x alpha field stop into the gamma x xi focal plane array (FPA).
+ * The library evaluates H f and H^T r directly as sparse gathers over the
+ * nonzeros of each c_s (the paper evaluates them with FFTs; both give the
+ * same operator).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  Sizes:   n = gamma * xi FPA pixels, ell = a * alpha field-stop pixels,
+ *           m = ell * w voxels.  n and m must fit in int32.
+ *  Layout:  the paper's column-major vectorisation (Sec. 2; Sec. 3 index map).
+ *           Voxel (x, y, s), x < a, y < alpha, s < w, is f[x + a*y + ell*s]
+ *           (a row-major (w, alpha, a) array).  FPA pixel (r, c), r < gamma,
+ *           c < xi, is g[r + gamma*c] (a row-major (xi, gamma) array).
+ *  Shift:   the shift of Sec. 3 is cyclic over the whole vectorised FPA of
+ *           length n (an n x n circulant), so a shifted image that runs past
+ *           the last FPA row continues at row 0 of the next FPA column, and
+ *           past the last pixel at pixel 0.  The library reproduces this
+ *           exactly; calibration layouts that never reach an FPA edge are the
+ *           same computation.
+ *  Numbers: float32 storage, float32 arithmetic and accumulation.
+ *  Memory:  f, g, r, z and the workspace are DEVICE pointers on the plan's
+ *           HIP device, contiguous, 4-byte aligned, owned by the caller, and
+ *           must stay valid until the work queued on `stream` completes.
+ *           Inputs and outputs must not overlap (except f in ctis_em_iterate,
+ *           which is updated in place).  Inputs must be finite.
+ *  Streams: `stream` is a hipStream_t (NULL = the legacy default stream).
+ *           Calls queue work and return; HIP faults surface at the caller's
+ *           next synchronisation.  A plan is immutable after creation: calls
+ *           on different streams may share it when their outputs and
+ *           workspaces differ.
+ *  Errors:  every call returns a ctis_status; none aborts or prints.
+ *           ctis_last_error() gives a description of the last failure on the
+ *           calling thread.
+ */
+#ifndef CTIS_H
+#define CTIS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CTIS_OK = 0,
+    CTIS_E_ARG = 1,         /* null pointer, bad size or flag, wrong device   */
+    CTIS_E_INDEX = 2,       /* calibration index outside [0, n)               */
+    CTIS_E_VALUE = 3,       /* non-finite calibration value                   */
+    CTIS_E_TOO_LARGE = 4,   /* n, m or a table size does not fit in int32     */
+    CTIS_E_NOMEM = 5,       /* host or device allocation failed               */
+    CTIS_E_HIP = 6,         /* a HIP runtime call or kernel launch failed     */
+    CTIS_E_NEGATIVE = 7,    /* EM needs nonnegative calibration values        */
+    CTIS_E_WORKSPACE = 8    /* workspace pointer null or too small            */
+} ctis_status;
+
+typedef struct ctis_plan ctis_plan;
+
+/* ctis_plan_create flags */
+#define CTIS_PLAN_HOST_ONLY 0x1u        /* build the tables on the host only (no
+                                           device memory); for inspection --
+                                           compute calls on it return CTIS_E_ARG */
+#define CTIS_PLAN_BOX(b) (((uint32_t)(b) & 0xFu) << 8)
+                                        /* force the calibration box side B in
+                                           1..8 (0 = chosen by the plan)         */
+
+typedef struct {
+    int32_t a, alpha, w, gamma, xi;
+    int64_t n, ell, m;
+    int64_t nnz;             /* calibration nonzeros after merging duplicates
+                                and dropping exact zeros                        */
+    int64_t n_support;       /* FPA pixels whose row of H is not empty          */
+    int32_t box;             /* side B of the dense boxes the nonzeros are
+                                grouped into                                    */
+    int32_t n_boxes;
+    int32_t tile_fast, tile_slow;   /* FPA / field-stop tile (pixels)           */
+    int32_t n_tiles;         /* FPA tiles                                       */
+    int32_t n_active_tiles;  /* FPA tiles that meet the image of some box       */
+    int64_t n_items;         /* (FPA tile, box) pairs of the forward work list  */
+    size_t workspace_bytes;  /* device workspace ctis_em_iterate needs          */
+    int32_t nonnegative;     /* 1 if every calibration value is >= 0            */
+    int32_t device;          /* HIP device of the plan, -1 if host-only         */
+    int32_t waves_forward;   /* wavefronts per forward workgroup                */
+    int32_t waves_adjoint;   /* wavefronts per adjoint workgroup                */
+} ctis_plan_info;
+
+/*
+ * Create a plan: the calibration images and geometry, validated, grouped and
+ * uploaded to the current HIP device.
+ *
+ *   a, alpha      field stop (Sec. 2: a x alpha), 1 <= a <= gamma, 1 <= alpha <= xi
+ *   w             number of wavelengths (calibration images), >= 1
+ *   gamma, xi     FPA size (Sec. 2: gamma x xi)
+ *   lambda_ptr    HOST int64[w+1]: entries of wavelength s are
+ *                 [lambda_ptr[s], lambda_ptr[s+1]); lambda_ptr[0] = 0,
+ *                 non-decreasing
+ *   fpa_index     HOST int32[lambda_ptr[w]]: FPA index r + gamma*c of the
+ *                 entry in the calibration image of field-stop pixel (0, 0)
+ *                 (the first column c_s of H_s, Sec. 3)
+ *   value         HOST float[lambda_ptr[w]]: its value; duplicates add up,
+ *                 exact zeros are dropped; any sign is accepted, but
+ *                 ctis_em_iterate needs all values >= 0
+ *   flags         CTIS_PLAN_* bits
+ *
+ * The caller may free its arrays when the call returns.  Errors:
+ * CTIS_E_ARG (sizes, pointers, lambda_ptr, flags), CTIS_E_INDEX, CTIS_E_VALUE,
+ * CTIS_E_TOO_LARGE, CTIS_E_NOMEM, CTIS_E_HIP.  *out is NULL on failure.
+ */
+ctis_status ctis_plan_create(ctis_plan **out, int32_t a, int32_t alpha, int32_t w,
+                             int32_t gamma, int32_t xi, const int64_t *lambda_ptr,
+                             const int32_t *fpa_index, const float *value,
+                             uint32_t flags);
+
+/* Free a plan and its device tables (after the work using it has completed).
+ * NULL is accepted. */
+void ctis_plan_destroy(ctis_plan *plan);
+
+/* Sizes and layout decisions of a plan (see ctis_plan_info). */
+ctis_status ctis_plan_get_info(const ctis_plan *plan, ctis_plan_info *info);
+
+/* HOST float[w]: the column sums h_j = sum_i H_ij (Sec. 2, below eq. (em)),
+ * which are equal within a wavelength block (column sums of a circulant):
+ * h for every voxel of wavelength s is the sum of the values of c_s. */
+ctis_status ctis_plan_lambda_sums(const ctis_plan *plan, float *h_out);
+
+/*
+ * Inspection of the plan's grouping (host copies).  Boxes: box k belongs to
+ * wavelength box_lambda[k]; its B x B values sit at FPA positions
+ * (box_rc[2k] + dr, box_rc[2k+1] + dc), value box_values[k*B*B + dc*B + dr].
+ * Work list: FPA tile t (fast index t % ceil(gamma/tile_fast)) lists the boxes
+ * item_box[tile_ptr[t] .. tile_ptr[t+1]) whose shifted field-stop image meets
+ * it.  Array sizes come from ctis_plan_info (n_boxes, n_tiles, n_items).
+ * Any output pointer may be NULL to skip it.
+ */
+ctis_status ctis_plan_export_boxes(const ctis_plan *plan, int32_t *box_lambda,
+                                   int32_t *box_rc, float *box_values);
+ctis_status ctis_plan_export_worklist(const ctis_plan *plan, int32_t *tile_ptr,
+                                      int32_t *item_box);
+
+/*
+ * Forward projection g_out = H f (Sec. 2 eq. (linear); Sec. 3 eq. (vs_linear):
+ * g = sum_s C_s E f_s).
+ *   f      DEVICE float[m], read
+ *   g_out  DEVICE float[n], written everywhere (0 where no voxel projects)
+ */
+ctis_status ctis_forward(const ctis_plan *plan, const float *f, float *g_out, void *stream);
+
+/*
+ * Back projection z_out = H^T r (Sec. 3 eq. (Htu): the transposed circulants
+ * followed by the transposed index map).
+ *   r      DEVICE float[n], read (every pixel any voxel projects to, and the
+ *          zero-valued padding around the calibration nonzeros, must be finite)
+ *   z_out  DEVICE float[m], written
+ */
+ctis_status ctis_adjoint(const ctis_plan *plan, const float *r, float *z_out, void *stream);
+
+/*
+ * iters EM iterations in place (Sec. 2 eq. (em); the per-iteration steps of
+ * the paper's Sec. 3 algorithm: g_k = H f, u = g / g_k, zeta = H^T u,
+ * f = (f . zeta) / h), fused into two kernels per iteration:
+ *   forward + ratio:  u_i = g_i / (H f)_i, or 0 where (H f)_i <= 0;
+ *   adjoint + update: f_j = f_j * (H^T u)_j / h_j, or 0 where h_j == 0.
+ *
+ *   g          DEVICE float[n], the measured frame, >= 0 (not checked)
+ *   f          DEVICE float[m], in: start (the paper starts from all ones),
+ *              out: f after `iters` updates; iters = 0 leaves f unchanged
+ *   workspace  DEVICE, >= info.workspace_bytes, 256-byte aligned; its
+ *              contents are scratch
+ * Errors: CTIS_E_NEGATIVE if a calibration value is negative, CTIS_E_WORKSPACE,
+ * CTIS_E_ARG, CTIS_E_HIP.
+ */
+ctis_status ctis_em_iterate(const ctis_plan *plan, const float *g, float *f, int32_t iters,
+                            void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * ctis_em_iterate with per-kernel timing, for benchmarking: HIP events are
+ * recorded on `stream` before and after every launch, the call waits for the
+ * work to finish, and ms_forward / ms_adjoint (HOST, may be NULL) receive the
+ * summed durations in milliseconds of the `iters` forward+ratio and
+ * adjoint+update launches.  Same arguments and errors as ctis_em_iterate.
+ */
+ctis_status ctis_em_iterate_timed(const ctis_plan *plan, const float *g, float *f, int32_t iters,
+                                  void *workspace, size_t workspace_bytes, void *stream,
+                                  float *ms_forward, float *ms_adjoint);
+
+/* Static description of a status code. */
+const char *ctis_status_str(ctis_status status);
+
+/* Description of the last failure on the calling thread ("" if none). */
+const char *ctis_last_error(void);
+
+/* Library version, "major.minor.patch". */
+const char *ctis_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CTIS_H */

@@ -1,0 +1,299 @@
+// C ABI of libctis: argument checking, plan lifetime and the stream-ordered
+// drivers.  The arithmetic is in kernels.hip.
+#include <hip/hip_runtime_api.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ctis_internal.h"
+
+namespace ctis {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+ctis_status fail(ctis_status st, const std::string &msg) {
+    g_last_error = msg;
+    return st;
+}
+
+namespace {
+
+ctis_status check_device(const ctis_plan *p) {
+    if (p->device < 0) return fail(CTIS_E_ARG, "plan was created host-only");
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(CTIS_E_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev != p->device)
+        return fail(CTIS_E_ARG, "current HIP device " + std::to_string(dev) + " differs from the plan's device " +
+                                    std::to_string(p->device));
+    return CTIS_OK;
+}
+
+bool aligned4(const void *ptr) { return ((uintptr_t)ptr & 3u) == 0; }
+
+bool overlaps(const void *x, size_t xb, const void *y, size_t yb) {
+    const char *a = (const char *)x, *b = (const char *)y;
+    return a < b + yb && b < a + xb;
+}
+
+ctis_status launch_status(int err, const char *what) {
+    if (err != 0)
+        return fail(CTIS_E_HIP, std::string(what) + ": " + hipGetErrorString((hipError_t)err));
+    return CTIS_OK;
+}
+
+}  // namespace
+}  // namespace ctis
+
+using namespace ctis;
+
+extern "C" {
+
+const char *ctis_version(void) { return "0.1.0"; }
+
+const char *ctis_status_str(ctis_status st) {
+    switch (st) {
+        case CTIS_OK: return "ok";
+        case CTIS_E_ARG: return "invalid argument";
+        case CTIS_E_INDEX: return "calibration index out of range";
+        case CTIS_E_VALUE: return "non-finite calibration value";
+        case CTIS_E_TOO_LARGE: return "size exceeds the supported range";
+        case CTIS_E_NOMEM: return "out of memory";
+        case CTIS_E_HIP: return "HIP runtime error";
+        case CTIS_E_NEGATIVE: return "EM needs nonnegative calibration values";
+        case CTIS_E_WORKSPACE: return "workspace missing or too small";
+    }
+    return "unknown status";
+}
+
+const char *ctis_last_error(void) { return g_last_error.c_str(); }
+
+ctis_status ctis_plan_create(ctis_plan **out, int32_t a, int32_t alpha, int32_t w, int32_t gamma, int32_t xi,
+                             const int64_t *lambda_ptr, const int32_t *fpa_index, const float *value,
+                             uint32_t flags) {
+    g_last_error.clear();
+    if (!out) return fail(CTIS_E_ARG, "out is NULL");
+    *out = nullptr;
+    const uint32_t known = CTIS_PLAN_HOST_ONLY | CTIS_PLAN_BOX(0xF);
+    if (flags & ~known) return fail(CTIS_E_ARG, "unknown flag bits");
+    const int forced_box = (int)((flags >> 8) & 0xFu);
+    if (forced_box > kMaxBox) return fail(CTIS_E_ARG, "forced box side must be in 1..8");
+    if (a < 1 || alpha < 1 || w < 1 || gamma < 1 || xi < 1)
+        return fail(CTIS_E_ARG, "a, alpha, w, gamma, xi must all be >= 1");
+    if (a > gamma || alpha > xi) return fail(CTIS_E_ARG, "the field stop must fit on the FPA (a <= gamma, alpha <= xi)");
+    const int64_t n = (int64_t)gamma * xi, ell = (int64_t)a * alpha, m = ell * w;
+    if (n > INT32_MAX - 4096 || m > INT32_MAX - 4096)
+        return fail(CTIS_E_TOO_LARGE, "n = gamma*xi and m = a*alpha*w must fit in int32");
+    if (!lambda_ptr) return fail(CTIS_E_ARG, "lambda_ptr is NULL");
+    if (lambda_ptr[0] != 0) return fail(CTIS_E_ARG, "lambda_ptr[0] must be 0");
+    for (int32_t s = 0; s < w; ++s)
+        if (lambda_ptr[s + 1] < lambda_ptr[s]) return fail(CTIS_E_ARG, "lambda_ptr must be non-decreasing");
+    const int64_t total = lambda_ptr[w];
+    if (total > INT32_MAX) return fail(CTIS_E_TOO_LARGE, "too many calibration entries");
+    if (total > 0 && (!fpa_index || !value)) return fail(CTIS_E_ARG, "fpa_index or value is NULL");
+    for (int64_t t = 0; t < total; ++t) {
+        if (fpa_index[t] < 0 || (int64_t)fpa_index[t] >= n)
+            return fail(CTIS_E_INDEX, "fpa_index[" + std::to_string(t) + "] = " + std::to_string(fpa_index[t]) +
+                                          " is outside [0, n)");
+        if (!std::isfinite(value[t])) return fail(CTIS_E_VALUE, "value[" + std::to_string(t) + "] is not finite");
+    }
+
+    ctis_plan *p = new (std::nothrow) ctis_plan();
+    if (!p) return fail(CTIS_E_NOMEM, "plan allocation");
+    p->a = a;
+    p->alpha = alpha;
+    p->w = w;
+    p->gamma = gamma;
+    p->xi = xi;
+    p->n = n;
+    p->ell = ell;
+    p->m = m;
+    ctis_status st;
+    try {
+        st = build_host_tables(p, lambda_ptr, fpa_index, value, forced_box);
+    } catch (const std::bad_alloc &) {
+        st = fail(CTIS_E_NOMEM, "host allocation while building the plan");
+    }
+    if (st != CTIS_OK) {
+        delete p;
+        return st;
+    }
+    if (!(flags & CTIS_PLAN_HOST_ONLY)) {
+        int dev = -1;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) {
+            delete p;
+            return fail(CTIS_E_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+        }
+        p->device = dev;
+        st = upload_tables(p);
+        if (st != CTIS_OK) {
+            delete p;
+            return st;
+        }
+    }
+    *out = p;
+    return CTIS_OK;
+}
+
+void ctis_plan_destroy(ctis_plan *p) {
+    if (!p) return;
+    if (p->dev_mem) (void)hipFree(p->dev_mem);
+    delete p;
+}
+
+ctis_status ctis_plan_get_info(const ctis_plan *p, ctis_plan_info *info) {
+    if (!p || !info) return fail(CTIS_E_ARG, "plan or info is NULL");
+    std::memset(info, 0, sizeof(*info));
+    info->a = p->a;
+    info->alpha = p->alpha;
+    info->w = p->w;
+    info->gamma = p->gamma;
+    info->xi = p->xi;
+    info->n = p->n;
+    info->ell = p->ell;
+    info->m = p->m;
+    info->nnz = p->ht.nnz;
+    info->n_support = p->ht.n_support;
+    info->box = p->ht.B;
+    info->n_boxes = (int32_t)p->ht.box_lambda.size();
+    info->tile_fast = kTileFast;
+    info->tile_slow = kTileSlow;
+    info->n_tiles = p->ht.n_tiles;
+    info->n_active_tiles = p->ht.n_active;
+    info->n_items = (int64_t)p->ht.item_box.size();
+    info->workspace_bytes = p->workspace_bytes;
+    info->nonnegative = p->ht.nonneg ? 1 : 0;
+    info->device = p->device;
+    info->waves_forward = p->waves_fwd;
+    info->waves_adjoint = p->waves_adj;
+    return CTIS_OK;
+}
+
+ctis_status ctis_plan_lambda_sums(const ctis_plan *p, float *h_out) {
+    if (!p || !h_out) return fail(CTIS_E_ARG, "plan or h_out is NULL");
+    std::memcpy(h_out, p->ht.h.data(), sizeof(float) * p->ht.h.size());
+    return CTIS_OK;
+}
+
+ctis_status ctis_plan_export_boxes(const ctis_plan *p, int32_t *box_lambda, int32_t *box_rc, float *box_values) {
+    if (!p) return fail(CTIS_E_ARG, "plan is NULL");
+    const auto &T = p->ht;
+    if (box_lambda) std::memcpy(box_lambda, T.box_lambda.data(), T.box_lambda.size() * 4);
+    if (box_rc) std::memcpy(box_rc, T.box_rc.data(), T.box_rc.size() * 4);
+    if (box_values) std::memcpy(box_values, T.box_w.data(), T.box_w.size() * 4);
+    return CTIS_OK;
+}
+
+ctis_status ctis_plan_export_worklist(const ctis_plan *p, int32_t *tile_ptr, int32_t *item_box) {
+    if (!p) return fail(CTIS_E_ARG, "plan is NULL");
+    const auto &T = p->ht;
+    if (tile_ptr) std::memcpy(tile_ptr, T.tile_item_ptr.data(), T.tile_item_ptr.size() * 4);
+    if (item_box) std::memcpy(item_box, T.item_box.data(), T.item_box.size() * 4);
+    return CTIS_OK;
+}
+
+ctis_status ctis_forward(const ctis_plan *p, const float *f, float *g_out, void *stream) {
+    if (!p) return fail(CTIS_E_ARG, "plan is NULL");
+    if (!f || !g_out) return fail(CTIS_E_ARG, "f or g_out is NULL");
+    if (!aligned4(f) || !aligned4(g_out)) return fail(CTIS_E_ARG, "f and g_out must be 4-byte aligned");
+    if (overlaps(f, (size_t)p->m * 4, g_out, (size_t)p->n * 4)) return fail(CTIS_E_ARG, "f and g_out overlap");
+    ctis_status st = check_device(p);
+    if (st != CTIS_OK) return st;
+    return launch_status(launch_forward(p, f, nullptr, g_out, false, stream), "forward launch");
+}
+
+ctis_status ctis_adjoint(const ctis_plan *p, const float *r, float *z_out, void *stream) {
+    if (!p) return fail(CTIS_E_ARG, "plan is NULL");
+    if (!r || !z_out) return fail(CTIS_E_ARG, "r or z_out is NULL");
+    if (!aligned4(r) || !aligned4(z_out)) return fail(CTIS_E_ARG, "r and z_out must be 4-byte aligned");
+    if (overlaps(r, (size_t)p->n * 4, z_out, (size_t)p->m * 4)) return fail(CTIS_E_ARG, "r and z_out overlap");
+    ctis_status st = check_device(p);
+    if (st != CTIS_OK) return st;
+    return launch_status(launch_adjoint(p, r, nullptr, z_out, false, stream), "adjoint launch");
+}
+
+namespace {
+ctis_status em_check(const ctis_plan *p, const float *g, float *f, int32_t iters, void *workspace,
+                     size_t workspace_bytes) {
+    if (!p) return fail(CTIS_E_ARG, "plan is NULL");
+    if (!g || !f) return fail(CTIS_E_ARG, "g or f is NULL");
+    if (iters < 0) return fail(CTIS_E_ARG, "iters must be >= 0");
+    if (!aligned4(g) || !aligned4(f)) return fail(CTIS_E_ARG, "g and f must be 4-byte aligned");
+    if (!p->ht.nonneg) return fail(CTIS_E_NEGATIVE, "the plan has a negative calibration value");
+    if (!workspace || workspace_bytes < p->workspace_bytes)
+        return fail(CTIS_E_WORKSPACE, "workspace needs " + std::to_string(p->workspace_bytes) + " bytes");
+    if (((uintptr_t)workspace & 255u) != 0) return fail(CTIS_E_WORKSPACE, "workspace must be 256-byte aligned");
+    if (overlaps(g, (size_t)p->n * 4, f, (size_t)p->m * 4) ||
+        overlaps(workspace, p->workspace_bytes, f, (size_t)p->m * 4) ||
+        overlaps(workspace, p->workspace_bytes, g, (size_t)p->n * 4))
+        return fail(CTIS_E_ARG, "g, f and the workspace must not overlap");
+    return check_device(p);
+}
+}  // namespace
+
+ctis_status ctis_em_iterate(const ctis_plan *p, const float *g, float *f, int32_t iters, void *workspace,
+                            size_t workspace_bytes, void *stream) {
+    ctis_status st = em_check(p, g, f, iters, workspace, workspace_bytes);
+    if (st != CTIS_OK) return st;
+    float *u = (float *)workspace;
+    for (int32_t k = 0; k < iters; ++k) {
+        st = launch_status(launch_forward(p, f, g, u, true, stream), "forward+ratio launch");
+        if (st != CTIS_OK) return st;
+        st = launch_status(launch_adjoint(p, u, f, f, true, stream), "adjoint+update launch");
+        if (st != CTIS_OK) return st;
+    }
+    return CTIS_OK;
+}
+
+ctis_status ctis_em_iterate_timed(const ctis_plan *p, const float *g, float *f, int32_t iters, void *workspace,
+                                  size_t workspace_bytes, void *stream, float *ms_forward, float *ms_adjoint) {
+    ctis_status st = em_check(p, g, f, iters, workspace, workspace_bytes);
+    if (st != CTIS_OK) return st;
+    hipStream_t hs = (hipStream_t)stream;
+    std::vector<hipEvent_t> ev((size_t)2 * iters + 1, nullptr);
+    auto cleanup = [&]() {
+        for (auto e : ev)
+            if (e) (void)hipEventDestroy(e);
+    };
+    for (auto &e : ev) {
+        hipError_t he = hipEventCreate(&e);
+        if (he != hipSuccess) {
+            cleanup();
+            return fail(CTIS_E_HIP, std::string("hipEventCreate: ") + hipGetErrorString(he));
+        }
+    }
+    float *u = (float *)workspace;
+    hipError_t he = hipEventRecord(ev[0], hs);
+    for (int32_t k = 0; k < iters && he == hipSuccess && st == CTIS_OK; ++k) {
+        st = launch_status(launch_forward(p, f, g, u, true, stream), "forward+ratio launch");
+        if (st == CTIS_OK) he = hipEventRecord(ev[(size_t)2 * k + 1], hs);
+        if (st == CTIS_OK && he == hipSuccess)
+            st = launch_status(launch_adjoint(p, u, f, f, true, stream), "adjoint+update launch");
+        if (st == CTIS_OK && he == hipSuccess) he = hipEventRecord(ev[(size_t)2 * k + 2], hs);
+    }
+    if (st == CTIS_OK && he == hipSuccess) he = hipEventSynchronize(ev.back());
+    double fw = 0.0, ad = 0.0;
+    for (int32_t k = 0; k < iters && st == CTIS_OK && he == hipSuccess; ++k) {
+        float t1 = 0.0f, t2 = 0.0f;
+        he = hipEventElapsedTime(&t1, ev[(size_t)2 * k], ev[(size_t)2 * k + 1]);
+        if (he == hipSuccess) he = hipEventElapsedTime(&t2, ev[(size_t)2 * k + 1], ev[(size_t)2 * k + 2]);
+        fw += t1;
+        ad += t2;
+    }
+    cleanup();
+    if (st != CTIS_OK) return st;
+    if (he != hipSuccess) return fail(CTIS_E_HIP, std::string("HIP event: ") + hipGetErrorString(he));
+    if (ms_forward) *ms_forward = (float)fw;
+    if (ms_adjoint) *ms_adjoint = (float)ad;
+    return CTIS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,373 @@
+// Host side of a plan: validation, merging of the calibration entries,
+// grouping of each wavelength's nonzeros into dense B x B boxes, support
+// statistics, the forward work list, and the upload of the tables.
+//
+// The operator is the paper's: column j = (x, y, s) of H is the calibration
+// image c_s shifted cyclically by q = x + gamma*y over the vectorised FPA
+// (Sec. 2 calibration + shift-invariance; Sec. 3 H_s = C_s E and its index
+// map).  Grouping the nonzeros into boxes does not change the operator: a box
+// anchored at FPA position (rA, cA) holds the entries at (rA + dr, cA + dc),
+// and the 1-D index of such an entry is exactly rA + dr + gamma*(cA + dc), so
+// the kernels' cyclic address arithmetic stays the paper's.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <unordered_set>
+
+#include "ctis_internal.h"
+
+namespace ctis {
+
+namespace {
+
+struct Entry {
+    int64_t idx;
+    int32_t r, c;
+    float v;
+};
+
+struct Dsu {
+    std::vector<int32_t> p;
+    explicit Dsu(size_t n) : p(n) { std::iota(p.begin(), p.end(), 0); }
+    int32_t find(int32_t x) {
+        while (p[x] != x) {
+            p[x] = p[p[x]];
+            x = p[x];
+        }
+        return x;
+    }
+    void unite(int32_t a, int32_t b) {
+        a = find(a);
+        b = find(b);
+        if (a != b) p[std::max(a, b)] = std::min(a, b);
+    }
+};
+
+struct Component {
+    int32_t rmin, rmax, cmin, cmax;
+    std::vector<int32_t> members;   // indices into the wavelength's entry list
+};
+
+// 8-connected components of one wavelength's nonzero positions (decoded 2-D
+// FPA coordinates; no wrap -- grouping is a layout choice only).
+std::vector<Component> components(const std::vector<Entry> &e, int32_t gamma, int32_t xi) {
+    const int32_t k = (int32_t)e.size();
+    Dsu d(k);
+    // entries are sorted by 1-D index: binary search for neighbours
+    auto find_idx = [&](int64_t idx) -> int32_t {
+        auto it = std::lower_bound(e.begin(), e.end(), idx,
+                                   [](const Entry &a, int64_t v) { return a.idx < v; });
+        if (it != e.end() && it->idx == idx) return (int32_t)(it - e.begin());
+        return -1;
+    };
+    for (int32_t t = 0; t < k; ++t) {
+        for (int dc = -1; dc <= 1; ++dc)
+            for (int dr = -1; dr <= 1; ++dr) {
+                if (!dr && !dc) continue;
+                int32_t r = e[t].r + dr, c = e[t].c + dc;
+                if (r < 0 || r >= gamma || c < 0 || c >= xi) continue;
+                int32_t o = find_idx((int64_t)r + (int64_t)gamma * c);
+                if (o >= 0) d.unite(t, o);
+            }
+    }
+    std::vector<int32_t> root_to_comp(k, -1);
+    std::vector<Component> out;
+    for (int32_t t = 0; t < k; ++t) {
+        int32_t rt = d.find(t);
+        if (root_to_comp[rt] < 0) {
+            root_to_comp[rt] = (int32_t)out.size();
+            out.push_back(Component{e[t].r, e[t].r, e[t].c, e[t].c, {}});
+        }
+        Component &cp = out[root_to_comp[rt]];
+        cp.rmin = std::min(cp.rmin, e[t].r);
+        cp.rmax = std::max(cp.rmax, e[t].r);
+        cp.cmin = std::min(cp.cmin, e[t].c);
+        cp.cmax = std::max(cp.cmax, e[t].c);
+        cp.members.push_back(t);
+    }
+    return out;
+}
+
+// distinct B x B cells (aligned at the component's bounding-box corner) that
+// hold at least one member, as (cell_r, cell_c) pairs in ascending order
+std::vector<std::pair<int32_t, int32_t>> cells(const Component &cp, const std::vector<Entry> &e, int B) {
+    std::vector<std::pair<int32_t, int32_t>> v;
+    v.reserve(cp.members.size());
+    for (int32_t t : cp.members) v.emplace_back((e[t].r - cp.rmin) / B, (e[t].c - cp.cmin) / B);
+    std::sort(v.begin(), v.end(), [](auto a, auto b) {
+        return a.second != b.second ? a.second < b.second : a.first < b.first;
+    });
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+    return v;
+}
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// count of set entries of the circular sliding OR along a sequence
+// get(k), k in [0, len), window `win` ending at k (k - win + 1 .. k, mod len)
+template <class Get, class Set>
+void circular_window_or(int64_t len, int64_t win, Get get, Set set) {
+    int64_t cnt = 0;
+    for (int64_t x = 0; x < win; ++x) cnt += get(((0 - x) % len + len) % len);
+    set(0, cnt > 0);
+    for (int64_t k = 1; k < len; ++k) {
+        cnt += get(k);
+        cnt -= get(((k - win) % len + len) % len);
+        set(k, cnt > 0);
+    }
+}
+
+}  // namespace
+
+ctis_status build_host_tables(ctis_plan *p, const int64_t *lambda_ptr, const int32_t *fpa_index,
+                              const float *value, int forced_box) {
+    HostTables &T = p->ht;
+    const int32_t w = p->w, gamma = p->gamma, xi = p->xi, a = p->a, alpha = p->alpha;
+    const int64_t n = p->n;
+
+    // -- 1. merge duplicates (sum in double), drop exact zeros ------------------
+    std::vector<std::vector<Entry>> ent(w);
+    T.nonneg = true;
+    T.nnz = 0;
+    for (int32_t s = 0; s < w; ++s) {
+        const int64_t b = lambda_ptr[s], e = lambda_ptr[s + 1];
+        std::vector<std::pair<int64_t, int64_t>> order;   // (index, position)
+        order.reserve((size_t)(e - b));
+        for (int64_t t = b; t < e; ++t) order.emplace_back((int64_t)fpa_index[t], t);
+        std::sort(order.begin(), order.end());
+        auto &out = ent[s];
+        for (size_t k = 0; k < order.size();) {
+            size_t k2 = k;
+            double acc = 0.0;
+            while (k2 < order.size() && order[k2].first == order[k].first) {
+                acc += (double)value[order[k2].second];
+                ++k2;
+            }
+            const float v = (float)acc;
+            if (v != 0.0f) {
+                const int64_t idx = order[k].first;
+                out.push_back(Entry{idx, (int32_t)(idx % gamma), (int32_t)(idx / gamma), v});
+                if (v < 0.0f) T.nonneg = false;
+            }
+            k = k2;
+        }
+        T.nnz += (int64_t)out.size();
+    }
+
+    // -- 2. components and the box side B --------------------------------------
+    std::vector<std::vector<Component>> comps(w);
+    for (int32_t s = 0; s < w; ++s) comps[s] = components(ent[s], gamma, xi);
+    int B = forced_box;
+    if (B == 0) {
+        double best = 0.0;
+        for (int cand = 1; cand <= kMaxBox; ++cand) {
+            int64_t nb = 0;
+            for (int32_t s = 0; s < w; ++s)
+                for (const auto &cp : comps[s]) nb += (int64_t)cells(cp, ent[s], cand).size();
+            // per box and output: B*B multiply-adds plus staging of its window,
+            // which costs about as much as 12 multiply-adds per output
+            const double cost = (double)nb * (double)(cand * cand + 12);
+            if (B == 0 || cost < best) {
+                best = cost;
+                B = cand;
+            }
+        }
+    }
+    T.B = B;
+
+    // -- 3. boxes (per wavelength, sorted by anchor index) ----------------------
+    T.box_rc.clear();
+    T.box_lambda.clear();
+    T.box_w.clear();
+    T.box_wf.clear();
+    T.lambda_box_ptr.assign((size_t)w + 1, 0);
+    const int BB = B * B;
+    for (int32_t s = 0; s < w; ++s) {
+        struct Box {
+            int32_t r, c;
+            std::vector<float> v;
+        };
+        std::vector<Box> boxes;
+        for (const auto &cp : comps[s]) {
+            auto cl = cells(cp, ent[s], B);
+            const size_t base = boxes.size();
+            for (auto [ci, cj] : cl) boxes.push_back(Box{cp.rmin + B * ci, cp.cmin + B * cj,
+                                                          std::vector<float>((size_t)BB, 0.0f)});
+            for (int32_t t : cp.members) {
+                const int32_t ci = (ent[s][t].r - cp.rmin) / B, cj = (ent[s][t].c - cp.cmin) / B;
+                auto it = std::lower_bound(cl.begin(), cl.end(), std::make_pair(ci, cj), [](auto x, auto y) {
+                    return x.second != y.second ? x.second < y.second : x.first < y.first;
+                });
+                Box &bx = boxes[base + (size_t)(it - cl.begin())];
+                bx.v[(size_t)((ent[s][t].c - bx.c) * B + (ent[s][t].r - bx.r))] = ent[s][t].v;
+            }
+        }
+        std::sort(boxes.begin(), boxes.end(), [&](const Box &x, const Box &y) {
+            return (int64_t)x.r + (int64_t)gamma * x.c < (int64_t)y.r + (int64_t)gamma * y.c;
+        });
+        for (const auto &bx : boxes) {
+            T.box_rc.push_back(bx.r);
+            T.box_rc.push_back(bx.c);
+            T.box_lambda.push_back(s);
+            for (int k = 0; k < BB; ++k) T.box_w.push_back(bx.v[(size_t)k]);
+            for (int dc = 0; dc < B; ++dc)
+                for (int dr = 0; dr < B; ++dr)
+                    T.box_wf.push_back(bx.v[(size_t)((B - 1 - dc) * B + (B - 1 - dr))]);
+        }
+        if ((int64_t)T.box_lambda.size() > INT32_MAX)
+            return fail(CTIS_E_TOO_LARGE, "too many calibration boxes");
+        T.lambda_box_ptr[(size_t)s + 1] = (int32_t)T.box_lambda.size();
+    }
+    const int32_t nb = (int32_t)T.box_lambda.size();
+
+    // -- 4. column sums per wavelength (sum of c_s, in double) ------------------
+    T.h.assign((size_t)w, 0.0f);
+    for (int32_t s = 0; s < w; ++s) {
+        double acc = 0.0;
+        for (const auto &e : ent[s]) acc += (double)e.v;
+        T.h[(size_t)s] = (float)acc;
+    }
+
+    // -- 5. support: FPA pixels in the image of some nonzero --------------------
+    {
+        std::vector<uint8_t> M((size_t)n, 0), D1((size_t)n, 0), D2((size_t)n, 0);
+        for (int32_t s = 0; s < w; ++s)
+            for (const auto &e : ent[s]) M[(size_t)e.idx] = 1;
+        // shift along the vectorised FPA by x in [0, a)
+        circular_window_or(n, a, [&](int64_t k) { return (int64_t)M[(size_t)k]; },
+                           [&](int64_t k, bool v) { D1[(size_t)k] = v; });
+        // shift by gamma*y, y in [0, alpha): a circular window along each residue class
+        for (int64_t rho = 0; rho < gamma; ++rho)
+            circular_window_or(xi, alpha, [&](int64_t k) { return (int64_t)D1[(size_t)(rho + gamma * k)]; },
+                               [&](int64_t k, bool v) { D2[(size_t)(rho + gamma * k)] = v; });
+        int64_t cnt = 0;
+        for (int64_t i = 0; i < n; ++i) cnt += D2[(size_t)i];
+        T.n_support = cnt;
+    }
+
+    // -- 6. forward work list: FPA tiles met by each box's dilated image --------
+    const int64_t ntr = ceil_div(gamma, kTileFast), ntc = ceil_div(xi, kTileSlow);
+    if (ntr * ntc > INT32_MAX) return fail(CTIS_E_TOO_LARGE, "too many FPA tiles");
+    T.ntr = (int32_t)ntr;
+    T.ntc = (int32_t)ntc;
+    T.n_tiles = (int32_t)(ntr * ntc);
+    std::vector<int32_t> stamp((size_t)T.n_tiles, -1);
+    std::vector<std::pair<int32_t, int32_t>> pairs;   // (tile, box)
+    const int64_t L0 = (int64_t)a + B - 1, rows = (int64_t)alpha + B - 1;
+    for (int32_t b = 0; b < nb; ++b) {
+        const int32_t rA = T.box_rc[2 * (size_t)b], cA = T.box_rc[2 * (size_t)b + 1];
+        for (int64_t Y = 0; Y < rows; ++Y) {
+            // pixels (A + X + gamma*Y) mod n, X in [0, L0): a run along the fast
+            // axis starting at (rA, cA + Y), continuing in the next FPA column
+            int64_t r = rA, c = (cA + Y) % xi, L = L0;
+            while (L > 0) {
+                const int64_t seg = std::min<int64_t>(L, gamma - r);
+                const int64_t tc = c / kTileSlow;
+                for (int64_t tr = r / kTileFast; tr <= (r + seg - 1) / kTileFast; ++tr) {
+                    const int32_t tile = (int32_t)(tr + ntr * tc);
+                    if (stamp[(size_t)tile] != b) {
+                        stamp[(size_t)tile] = b;
+                        pairs.emplace_back(tile, b);
+                    }
+                }
+                L -= seg;
+                r = 0;
+                c = (c + 1) % xi;
+            }
+        }
+    }
+    if ((int64_t)pairs.size() > INT32_MAX) return fail(CTIS_E_TOO_LARGE, "forward work list too long");
+    std::sort(pairs.begin(), pairs.end());
+    T.tile_item_ptr.assign((size_t)T.n_tiles + 1, 0);
+    T.item_box.resize(pairs.size());
+    for (size_t k = 0; k < pairs.size(); ++k) {
+        T.tile_item_ptr[(size_t)pairs[k].first + 1]++;
+        T.item_box[k] = pairs[k].second;
+    }
+    for (int32_t t = 0; t < T.n_tiles; ++t) T.tile_item_ptr[(size_t)t + 1] += T.tile_item_ptr[(size_t)t];
+    T.tile_order.resize((size_t)T.n_tiles);
+    std::iota(T.tile_order.begin(), T.tile_order.end(), 0);
+    auto count = [&](int32_t t) { return T.tile_item_ptr[(size_t)t + 1] - T.tile_item_ptr[(size_t)t]; };
+    std::stable_sort(T.tile_order.begin(), T.tile_order.end(),
+                     [&](int32_t x, int32_t y) { return count(x) > count(y); });
+    T.n_active = 0;
+    for (int32_t t = 0; t < T.n_tiles; ++t) T.n_active += count(t) > 0;
+
+    // -- 7. field-stop tiling of the back projection ----------------------------
+    T.nbx = (int32_t)ceil_div(a, kTileFast);
+    T.nby = (int32_t)ceil_div(alpha, kTileSlow);
+    if ((int64_t)T.nbx * T.nby * w > INT32_MAX) return fail(CTIS_E_TOO_LARGE, "too many field-stop tiles");
+
+    // -- kernel parameters ---------------------------------------------------------
+    KParams &k = p->kp;
+    k.a = a;
+    k.alpha = alpha;
+    k.w = w;
+    k.gamma = gamma;
+    k.xi = xi;
+    k.ell = (int32_t)p->ell;
+    k.n = (int32_t)n;
+    k.ntr = T.ntr;
+    k.nbx = T.nbx;
+    k.nby = T.nby;
+    p->workspace_bytes = ((size_t)n * sizeof(float) + 255) & ~(size_t)255;
+    int32_t max_boxes = 0;
+    for (int32_t s = 0; s < w; ++s)
+        max_boxes = std::max(max_boxes, T.lambda_box_ptr[(size_t)s + 1] - T.lambda_box_ptr[(size_t)s]);
+    p->waves_fwd = 4;
+    p->waves_adj = std::max(1, std::min(4, max_boxes));
+    return CTIS_OK;
+}
+
+ctis_status upload_tables(ctis_plan *p) {
+    const HostTables &T = p->ht;
+    struct Part {
+        const void *src;
+        size_t bytes;
+        size_t off;
+    };
+    std::vector<Part> parts = {
+        {T.box_rc.data(), T.box_rc.size() * 4, 0},
+        {T.box_lambda.data(), T.box_lambda.size() * 4, 0},
+        {T.box_w.data(), T.box_w.size() * 4, 0},
+        {T.box_wf.data(), T.box_wf.size() * 4, 0},
+        {T.lambda_box_ptr.data(), T.lambda_box_ptr.size() * 4, 0},
+        {T.h.data(), T.h.size() * 4, 0},
+        {T.tile_order.data(), T.tile_order.size() * 4, 0},
+        {T.tile_item_ptr.data(), T.tile_item_ptr.size() * 4, 0},
+        {T.item_box.data(), T.item_box.size() * 4, 0},
+    };
+    size_t total = 0;
+    for (auto &pt : parts) {
+        pt.off = total;
+        total += (std::max<size_t>(pt.bytes, 4) + 255) & ~(size_t)255;
+    }
+    void *mem = nullptr;
+    hipError_t e = hipMalloc(&mem, total);
+    if (e != hipSuccess) return fail(CTIS_E_NOMEM, std::string("hipMalloc of plan tables: ") + hipGetErrorString(e));
+    for (const auto &pt : parts) {
+        if (!pt.bytes) continue;
+        e = hipMemcpy((char *)mem + pt.off, pt.src, pt.bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(mem);
+            return fail(CTIS_E_HIP, std::string("hipMemcpy of plan tables: ") + hipGetErrorString(e));
+        }
+    }
+    p->dev_mem = mem;
+    auto at = [&](int k) { return (const void *)((const char *)mem + parts[(size_t)k].off); };
+    p->dt.box_rc = (const int32_t *)at(0);
+    p->dt.box_lambda = (const int32_t *)at(1);
+    p->dt.box_w = (const float *)at(2);
+    p->dt.box_wf = (const float *)at(3);
+    p->dt.lambda_box_ptr = (const int32_t *)at(4);
+    p->dt.h = (const float *)at(5);
+    p->dt.tile_order = (const int32_t *)at(6);
+    p->dt.tile_item_ptr = (const int32_t *)at(7);
+    p->dt.item_box = (const int32_t *)at(8);
+    return CTIS_OK;
+}
+
+}  // namespace ctis

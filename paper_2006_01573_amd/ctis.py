@@ -1,0 +1,321 @@
+"""ctypes binding of libctis (the C ABI in include/ctis.h).
+
+Argument marshalling only: torch tensors provide device memory and the HIP
+stream (``torch.cuda.current_stream()``); every arithmetic step runs in the
+library's HIP kernels.  There is no fallback: if libctis.so is missing or the
+GPU is absent, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libctis.so")
+
+CTIS_PLAN_HOST_ONLY = 0x1
+
+STATUS_NAMES = {0: "CTIS_OK", 1: "CTIS_E_ARG", 2: "CTIS_E_INDEX", 3: "CTIS_E_VALUE",
+                4: "CTIS_E_TOO_LARGE", 5: "CTIS_E_NOMEM", 6: "CTIS_E_HIP",
+                7: "CTIS_E_NEGATIVE", 8: "CTIS_E_WORKSPACE"}
+
+# every function include/ctis.h declares
+EXPORTED = ["ctis_plan_create", "ctis_plan_destroy", "ctis_plan_get_info",
+            "ctis_plan_lambda_sums", "ctis_plan_export_boxes", "ctis_plan_export_worklist",
+            "ctis_forward", "ctis_adjoint", "ctis_em_iterate", "ctis_em_iterate_timed", "ctis_status_str",
+            "ctis_last_error", "ctis_version"]
+
+
+def CTIS_PLAN_BOX(b: int) -> int:
+    return (int(b) & 0xF) << 8
+
+
+class CtisError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        self.status = status
+        self.name = STATUS_NAMES.get(status, str(status))
+        super().__init__(f"{where}: {self.name}: {detail}")
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_int32), ("alpha", ctypes.c_int32), ("w", ctypes.c_int32),
+                ("gamma", ctypes.c_int32), ("xi", ctypes.c_int32),
+                ("n", ctypes.c_int64), ("ell", ctypes.c_int64), ("m", ctypes.c_int64),
+                ("nnz", ctypes.c_int64), ("n_support", ctypes.c_int64),
+                ("box", ctypes.c_int32), ("n_boxes", ctypes.c_int32),
+                ("tile_fast", ctypes.c_int32), ("tile_slow", ctypes.c_int32),
+                ("n_tiles", ctypes.c_int32), ("n_active_tiles", ctypes.c_int32),
+                ("n_items", ctypes.c_int64), ("workspace_bytes", ctypes.c_size_t),
+                ("nonnegative", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("waves_forward", ctypes.c_int32), ("waves_adjoint", ctypes.c_int32)]
+
+
+@dataclasses.dataclass(frozen=True)
+class PlanInfo:
+    a: int
+    alpha: int
+    w: int
+    gamma: int
+    xi: int
+    n: int
+    ell: int
+    m: int
+    nnz: int
+    n_support: int
+    box: int
+    n_boxes: int
+    tile_fast: int
+    tile_slow: int
+    n_tiles: int
+    n_active_tiles: int
+    n_items: int
+    workspace_bytes: int
+    nonnegative: bool
+    device: int
+    waves_forward: int
+    waves_adjoint: int
+
+
+_lock = threading.Lock()
+_lib = None
+
+
+def load_library(path: str | None = None):
+    """Load libctis.so (built by ``paper_2006_01573_amd.build``)."""
+    global _lib
+    with _lock:
+        if _lib is not None and path is None:
+            return _lib
+        p = path or LIB_PATH
+        if not os.path.exists(p):
+            raise ImportError(f"{p} is missing: build it with `python -m paper_2006_01573_amd.build`")
+        L = ctypes.CDLL(p)
+        vp = ctypes.c_void_p
+        i32, i64, u32, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_size_t
+        st = ctypes.c_int
+        L.ctis_plan_create.argtypes = [ctypes.POINTER(vp), i32, i32, i32, i32, i32, vp, vp, vp, u32]
+        L.ctis_plan_create.restype = st
+        L.ctis_plan_destroy.argtypes = [vp]
+        L.ctis_plan_destroy.restype = None
+        L.ctis_plan_get_info.argtypes = [vp, ctypes.POINTER(_Info)]
+        L.ctis_plan_get_info.restype = st
+        L.ctis_plan_lambda_sums.argtypes = [vp, vp]
+        L.ctis_plan_lambda_sums.restype = st
+        L.ctis_plan_export_boxes.argtypes = [vp, vp, vp, vp]
+        L.ctis_plan_export_boxes.restype = st
+        L.ctis_plan_export_worklist.argtypes = [vp, vp, vp]
+        L.ctis_plan_export_worklist.restype = st
+        L.ctis_forward.argtypes = [vp, vp, vp, vp]
+        L.ctis_forward.restype = st
+        L.ctis_adjoint.argtypes = [vp, vp, vp, vp]
+        L.ctis_adjoint.restype = st
+        L.ctis_em_iterate.argtypes = [vp, vp, vp, i32, vp, sz, vp]
+        L.ctis_em_iterate.restype = st
+        L.ctis_em_iterate_timed.argtypes = [vp, vp, vp, i32, vp, sz, vp, ctypes.POINTER(ctypes.c_float),
+                                            ctypes.POINTER(ctypes.c_float)]
+        L.ctis_em_iterate_timed.restype = st
+        L.ctis_status_str.argtypes = [st]
+        L.ctis_status_str.restype = ctypes.c_char_p
+        L.ctis_last_error.argtypes = []
+        L.ctis_last_error.restype = ctypes.c_char_p
+        L.ctis_version.argtypes = []
+        L.ctis_version.restype = ctypes.c_char_p
+        if path is None:
+            _lib = L
+        return L
+
+
+def _check(L, status: int, where: str):
+    if status != 0:
+        raise CtisError(status, where, L.ctis_last_error().decode(errors="replace"))
+
+
+def _ptr(arr: np.ndarray):
+    return ctypes.c_void_p(arr.ctypes.data) if arr.size else None
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(torch, device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Plan:
+    """One geometry and one set of calibration images, on the current GPU.
+
+    ``lambda_ptr``/``fpa_index``/``value`` describe the calibration image of
+    field-stop pixel (0, 0) for every wavelength as COO (see include/ctis.h).
+    """
+
+    def __init__(self, a, alpha, w, gamma, xi, lambda_ptr, fpa_index, value, *,
+                 box: int = 0, host_only: bool = False, device=None):
+        self._L = load_library()
+        self._handle = None
+        ptr = np.ascontiguousarray(lambda_ptr, dtype=np.int64)
+        idx = np.ascontiguousarray(fpa_index, dtype=np.int32)
+        val = np.ascontiguousarray(value, dtype=np.float32)
+        if ptr.ndim != 1 or ptr.size != int(w) + 1:
+            raise ValueError("lambda_ptr must have w+1 entries")
+        if ptr.size and ptr[-1] > min(idx.size, val.size):
+            raise ValueError("fpa_index/value shorter than lambda_ptr[w]")
+        flags = CTIS_PLAN_BOX(box) | (CTIS_PLAN_HOST_ONLY if host_only else 0)
+        self.device = None
+        if not host_only:
+            torch = _torch()
+            if not torch.cuda.is_available():
+                raise RuntimeError("no GPU visible: a device plan needs an MI355X (use host_only=True to inspect)")
+            self.device = torch.device("cuda", torch.cuda.current_device() if device is None
+                                       else torch.device(device).index or 0)
+            torch.cuda.set_device(self.device)
+        h = ctypes.c_void_p()
+        st = self._L.ctis_plan_create(ctypes.byref(h), int(a), int(alpha), int(w), int(gamma), int(xi),
+                                      _ptr(ptr), _ptr(idx), _ptr(val), flags)
+        _check(self._L, st, "ctis_plan_create")
+        self._handle = h
+        self.info = self._info()
+        self.shape_f = (self.info.w, self.info.alpha, self.info.a)
+        self.shape_g = (self.info.xi, self.info.gamma)
+
+    @classmethod
+    def from_case(cls, case, **kw):
+        g = case.geometry
+        return cls(g.a, g.alpha, g.w, g.gamma, g.xi, case.lambda_ptr, case.fpa_index, case.value, **kw)
+
+    # -- lifetime -----------------------------------------------------------------
+    def close(self):
+        if self._handle:
+            if self.device is not None:
+                _torch().cuda.synchronize(self.device)
+            self._L.ctis_plan_destroy(self._handle)
+            self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- inspection -----------------------------------------------------------------
+    def _info(self) -> PlanInfo:
+        inf = _Info()
+        _check(self._L, self._L.ctis_plan_get_info(self._handle, ctypes.byref(inf)), "ctis_plan_get_info")
+        d = {k: getattr(inf, k) for k, _ in _Info._fields_}
+        d["nonnegative"] = bool(d["nonnegative"])
+        return PlanInfo(**d)
+
+    def lambda_sums(self) -> np.ndarray:
+        out = np.empty(self.info.w, np.float32)
+        _check(self._L, self._L.ctis_plan_lambda_sums(self._handle, _ptr(out)), "ctis_plan_lambda_sums")
+        return out
+
+    def boxes(self):
+        """(box_lambda[nb], box_rc[nb, 2], box_values[nb, B, B] indexed [k, dc, dr])."""
+        nb, B = self.info.n_boxes, self.info.box
+        lam = np.empty(nb, np.int32)
+        rc = np.empty(2 * nb, np.int32)
+        vals = np.empty(nb * B * B, np.float32)
+        _check(self._L, self._L.ctis_plan_export_boxes(self._handle, _ptr(lam), _ptr(rc), _ptr(vals)),
+               "ctis_plan_export_boxes")
+        return lam, rc.reshape(nb, 2), vals.reshape(nb, B, B)
+
+    def worklist(self):
+        """(tile_ptr[n_tiles+1], item_box[n_items])."""
+        tp = np.empty(self.info.n_tiles + 1, np.int32)
+        ib = np.empty(self.info.n_items, np.int32)
+        _check(self._L, self._L.ctis_plan_export_worklist(self._handle, _ptr(tp), _ptr(ib)),
+               "ctis_plan_export_worklist")
+        return tp, ib
+
+    # -- compute ----------------------------------------------------------------------
+    def _need_device(self):
+        if self.device is None:
+            raise RuntimeError("host-only plan: no compute")
+        if not self._handle:
+            raise RuntimeError("plan is closed")
+
+    def _dev_tensor(self, x, numel, name):
+        torch = _torch()
+        if not isinstance(x, torch.Tensor):
+            x = torch.as_tensor(np.asarray(x, dtype=np.float32))
+        x = x.to(device=self.device, dtype=torch.float32)
+        if x.numel() != numel:
+            raise ValueError(f"{name} must have {numel} elements, got {x.numel()}")
+        return x.contiguous()
+
+    def forward(self, f, out=None):
+        """g = H f.  f: (w, alpha, a) float32 on the plan's GPU -> (xi, gamma)."""
+        self._need_device()
+        torch = _torch()
+        f = self._dev_tensor(f, self.info.m, "f")
+        if out is None:
+            out = torch.empty(self.shape_g, dtype=torch.float32, device=self.device)
+        st = self._L.ctis_forward(self._handle, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                  _stream(torch, self.device))
+        _check(self._L, st, "ctis_forward")
+        return out
+
+    def adjoint(self, r, out=None):
+        """z = H^T r.  r: (xi, gamma) float32 on the plan's GPU -> (w, alpha, a)."""
+        self._need_device()
+        torch = _torch()
+        r = self._dev_tensor(r, self.info.n, "r")
+        if out is None:
+            out = torch.empty(self.shape_f, dtype=torch.float32, device=self.device)
+        st = self._L.ctis_adjoint(self._handle, ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                  _stream(torch, self.device))
+        _check(self._L, st, "ctis_adjoint")
+        return out
+
+    def workspace(self):
+        torch = _torch()
+        nbytes = self.info.workspace_bytes
+        return torch.empty(max(nbytes // 4, 64), dtype=torch.float32, device=self.device)
+
+    def em_timed(self, g, iters: int, f, workspace):
+        """EM in place on ``f`` with per-kernel HIP-event timing; waits for the
+        work.  Returns (ms of all forward+ratio launches, ms of all
+        adjoint+update launches)."""
+        self._need_device()
+        torch = _torch()
+        fw = ctypes.c_float()
+        ad = ctypes.c_float()
+        st = self._L.ctis_em_iterate_timed(self._handle, ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(f.data_ptr()),
+                                           int(iters), ctypes.c_void_p(workspace.data_ptr()),
+                                           workspace.numel() * workspace.element_size(), _stream(torch, self.device),
+                                           ctypes.byref(fw), ctypes.byref(ad))
+        _check(self._L, st, "ctis_em_iterate_timed")
+        return fw.value, ad.value
+
+    def em(self, g, iters: int, f0=None, f=None, workspace=None):
+        """EM iterations.  Returns f after ``iters`` updates of f0 (default ones).
+        If ``f`` is given it is updated in place (and returned)."""
+        self._need_device()
+        torch = _torch()
+        g = self._dev_tensor(g, self.info.n, "g")
+        if f is None:
+            if f0 is None:
+                f = torch.ones(self.shape_f, dtype=torch.float32, device=self.device)
+            else:
+                f = self._dev_tensor(f0, self.info.m, "f0").clone()
+        elif not (f.is_contiguous() and f.dtype == torch.float32 and f.device == self.device):
+            raise ValueError("f must be a contiguous float32 tensor on the plan's device")
+        if workspace is None:
+            workspace = self.workspace()
+        st = self._L.ctis_em_iterate(self._handle, ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(f.data_ptr()),
+                                     int(iters), ctypes.c_void_p(workspace.data_ptr()),
+                                     workspace.numel() * workspace.element_size(), _stream(torch, self.device))
+        _check(self._L, st, "ctis_em_iterate")
+        return f

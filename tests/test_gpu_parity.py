@@ -1,0 +1,263 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances: relative L2 <= 1e-5 for one projection, <= 1e-4 after the full
+iteration count of a configuration, float32 arithmetic on the GPU.  Inputs are
+the same float32 values on both sides; the oracle promotes them to double.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2006_01573_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+PROJ_TOL = 1e-5
+EM_TOL = 1e-4
+
+
+def rel_l2(x, ref):
+    x = np.asarray(x, np.float64).ravel()
+    ref = np.asarray(ref, np.float64).ravel()
+    den = np.linalg.norm(ref)
+    return np.linalg.norm(x - ref) / (den if den > 0 else 1.0)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU tests need a visible MI355X"
+    return _t
+
+
+@pytest.fixture(scope="module")
+def ctis(torch):
+    from paper_2006_01573_amd import ctis as _c
+    _c.load_library()
+    return _c
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_plan(ctis, geo, ptr, idx, val, box=0):
+    return ctis.Plan(geo.a, geo.alpha, geo.w, geo.gamma, geo.xi, ptr, idx, val, box=box)
+
+
+def oracle_for(oracle_mod, geo, ptr, idx, val, **kw):
+    return oracle_mod.Oracle(geo.a, geo.alpha, geo.w, geo.gamma, geo.xi, ptr, idx, val, **kw)
+
+
+def check_projections(torch, ctis, oracle_mod, geo, ptr, idx, val, seed, box=0, signed=False):
+    log(f"projections geo={geo} nnz={idx.size} box={box} seed={seed}")
+    p = gpu_plan(ctis, geo, ptr, idx, val, box=box)
+    o = oracle_for(oracle_mod, geo, ptr, idx, val)
+    rng = np.random.default_rng(seed)
+    f = rng.random(geo.m).astype(np.float32)
+    r = rng.random(geo.n).astype(np.float32)
+    if signed:
+        f -= 0.5
+        r -= 0.5
+    g_gpu = p.forward(torch.from_numpy(f).cuda()).cpu().numpy()
+    z_gpu = p.adjoint(torch.from_numpy(r).cuda()).cpu().numpy()
+    g_ref = o.forward(f)
+    z_ref = o.adjoint(r)
+    eg, ez = rel_l2(g_gpu, g_ref), rel_l2(z_gpu, z_ref)
+    # pixels no voxel projects to are exactly zero
+    _, rows, _ = o.csc()
+    off = np.ones(geo.n, bool)
+    off[rows] = False
+    assert np.all(g_gpu.ravel()[off] == 0.0)
+    assert eg <= PROJ_TOL, f"forward rel-L2 {eg:.3e}"
+    assert ez <= PROJ_TOL, f"adjoint rel-L2 {ez:.3e}"
+    return p, o
+
+
+EDGE = [
+    ("c1-geometry-random", W.Geometry(16, 16, 8, 128, 128), 40, False),
+    ("wrap-odd", W.Geometry(5, 7, 3, 13, 11), 9, False),
+    ("tiny-fpa", W.Geometry(3, 2, 2, 5, 4), 6, False),            # FPA far smaller than a tile
+    ("single-pixel", W.Geometry(1, 1, 4, 37, 29), 8, True),
+    ("a=gamma", W.Geometry(70, 3, 2, 70, 41), 10, True),          # field stop fills FPA columns
+    ("alpha=xi", W.Geometry(9, 33, 2, 67, 33), 10, True),
+    ("ragged", W.Geometry(67, 19, 3, 203, 77), 25, True),         # several tiles + ragged tails
+    ("wide", W.Geometry(130, 17, 2, 131, 64), 12, True),          # x tiles, gamma odd
+]
+
+
+@pytest.mark.parametrize("name,geo,nnz,clustered", EDGE, ids=[e[0] for e in EDGE])
+def test_projection_parity_edge_cases(torch, ctis, oracle_mod, name, geo, nnz, clustered):
+    rng = np.random.default_rng(abs(hash(name)) % 99991)
+    ptr, idx, val = W.random_kernels(geo, nnz, rng, clustered=clustered, nonneg=False)
+    check_projections(torch, ctis, oracle_mod, geo, ptr, idx, val, seed=1, signed=True)
+
+
+@pytest.mark.parametrize("box", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_projection_parity_every_box_size(torch, ctis, oracle_mod, box):
+    geo = W.Geometry(21, 9, 3, 97, 61)
+    rng = np.random.default_rng(100 + box)
+    ptr, idx, val = W.random_kernels(geo, 30, rng, clustered=True)
+    check_projections(torch, ctis, oracle_mod, geo, ptr, idx, val, seed=box, box=box)
+
+
+def test_empty_and_zero_wavelengths(torch, ctis, oracle_mod):
+    geo = W.Geometry(8, 5, 3, 40, 30)
+    # wavelength 1 has no entries, wavelength 2 only an explicit zero
+    ptr = np.array([0, 3, 3, 4], np.int64)
+    idx = np.array([5, 6, 200, 17], np.int32)
+    val = np.array([1.0, 0.5, 0.25, 0.0], np.float32)
+    p, o = check_projections(torch, ctis, oracle_mod, geo, ptr, idx, val, seed=7)
+    g = torch.rand(geo.xi, geo.gamma, device="cuda")
+    f = p.em(g, 3).cpu().numpy()
+    ref = o.em(g.cpu().numpy(), 3)
+    assert np.all(f[1] == 0) and np.all(f[2] == 0)
+    assert rel_l2(f, ref) <= EM_TOL
+    # no calibration entries at all
+    p0 = gpu_plan(ctis, geo, np.zeros(4, np.int64), np.zeros(0, np.int32), np.zeros(0, np.float32))
+    assert p0.info.n_active_tiles == 0
+    assert torch.count_nonzero(p0.forward(torch.rand(p0.shape_f, device="cuda"))).item() == 0
+    assert torch.count_nonzero(p0.adjoint(torch.rand(p0.shape_g, device="cuda"))).item() == 0
+    assert torch.count_nonzero(p0.em(g, 2)).item() == 0
+
+
+@pytest.fixture(scope="module")
+def c1(torch, ctis, oracle_mod):
+    case = W.make_case(1)
+    o = oracle_mod.Oracle.from_case(case)
+    g = case.noisy(o.forward(case.f_true.ravel()))
+    p = ctis.Plan.from_case(case)
+    return case, o, p, g
+
+
+def test_c1_projections(torch, c1):
+    case, o, p, _ = c1
+    f = case.f_true.astype(np.float32)
+    g_gpu = p.forward(torch.from_numpy(f).cuda()).cpu().numpy()
+    assert rel_l2(g_gpu, o.forward(f)) <= PROJ_TOL
+    r = np.random.default_rng(3).random(case.geometry.n).astype(np.float32)
+    z_gpu = p.adjoint(torch.from_numpy(r).cuda()).cpu().numpy()
+    assert rel_l2(z_gpu, o.adjoint(r)) <= PROJ_TOL
+
+
+def test_c1_em_parity_and_invariants(torch, c1):
+    case, o, p, g = c1
+    K = case.cfg.iters
+    log(f"c1 EM K={K}")
+    f_gpu = p.em(torch.from_numpy(g).cuda(), K).cpu().numpy()
+    f_ref = o.em(g, K)
+    e = rel_l2(f_gpu, f_ref)
+    log(f"c1 EM rel-L2 {e:.3e}")
+    assert e <= EM_TOL
+    assert np.all(f_gpu >= 0)
+    h = np.repeat(p.lambda_sums().astype(np.float64), case.geometry.ell)
+    flux = (h * f_gpu.ravel().astype(np.float64)).sum()
+    np.testing.assert_allclose(flux, g.astype(np.float64).sum(), rtol=1e-5)
+
+
+def test_adjoint_identity_gpu(torch, c1):
+    case, o, p, _ = c1
+    rng = np.random.default_rng(9)
+    f = torch.from_numpy(rng.random(case.geometry.m).astype(np.float32) - 0.5).cuda()
+    r = torch.from_numpy(rng.random(case.geometry.n).astype(np.float32) - 0.5).cuda()
+    lhs = (p.forward(f).double() * r.view(p.shape_g).double()).sum().item()
+    rhs = (f.view(p.shape_f).double() * p.adjoint(r).double()).sum().item()
+    scale = (p.forward(f.abs()).double() * r.abs().view(p.shape_g).double()).sum().item()
+    assert abs(lhs - rhs) <= 1e-5 * scale
+
+
+def test_fixed_point_noiseless_gpu(torch, c1, oracle_mod):
+    case, o, p, _ = c1
+    ft = (case.f_true + 1e-2).astype(np.float32)
+    g = o.forward(ft).astype(np.float32)
+    f = p.em(torch.from_numpy(g).cuda(), 20, f0=torch.from_numpy(ft).cuda()).cpu().numpy()
+    assert rel_l2(f, ft) <= 1e-4
+
+
+def test_determinism_and_resume(torch, c1):
+    case, o, p, g = c1
+    gd = torch.from_numpy(g).cuda()
+    a = p.em(gd, 12)
+    b = p.em(gd, 12)
+    assert torch.equal(a, b)
+    c = p.em(gd, 5)
+    c = p.em(gd, 7, f=c)
+    assert torch.equal(a, c)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        d = p.em(gd, 12)
+    s.synchronize()
+    assert torch.equal(a, d)
+    f = torch.rand(p.shape_f, device="cuda")
+    assert torch.equal(p.forward(f), p.forward(f))
+
+
+def test_gpu_error_paths(torch, ctis, c1):
+    case, o, p, g = c1
+    gd = torch.from_numpy(g).cuda()
+    with pytest.raises(ValueError):
+        p.forward(torch.zeros(5, device="cuda"))
+    small = torch.empty(16, device="cuda")
+    with pytest.raises(ctis.CtisError) as ei:
+        p.em(gd, 1, workspace=small)
+    assert ei.value.status == 8
+    neg = ctis.Plan(4, 4, 1, 16, 16, np.array([0, 2], np.int64), np.array([0, 3], np.int32),
+                    np.array([1.0, -1.0], np.float32))
+    with pytest.raises(ctis.CtisError) as ei:
+        neg.em(torch.ones(16, 16, device="cuda"), 1)
+    assert ei.value.status == 7
+    # projections accept negative calibration values
+    neg.forward(torch.ones(neg.shape_f, device="cuda"))
+    torch.cuda.synchronize()
+
+
+@pytest.fixture(scope="module")
+def c2(torch, ctis, oracle_mod):
+    case = W.make_case(2)
+    o = oracle_mod.Oracle.from_case(case)
+    g = case.noisy(o.forward(case.f_true.ravel()))
+    p = ctis.Plan.from_case(case)
+    return case, o, p, g
+
+
+def test_c2_projections(torch, c2):
+    case, o, p, _ = c2
+    f = case.f_true.astype(np.float32)
+    assert rel_l2(p.forward(torch.from_numpy(f).cuda()).cpu().numpy(), o.forward(f)) <= PROJ_TOL
+    r = np.random.default_rng(4).random(case.geometry.n).astype(np.float32)
+    assert rel_l2(p.adjoint(torch.from_numpy(r).cuda()).cpu().numpy(), o.adjoint(r)) <= PROJ_TOL
+
+
+def test_c2_em_full_iterations(torch, c2):
+    """The benchmark's workload and launch configuration: 100 iterations."""
+    case, o, p, g = c2
+    K = case.cfg.iters
+    log(f"c2 EM K={K}")
+    f_gpu = p.em(torch.from_numpy(g).cuda(), K).cpu().numpy()
+    f_ref = o.em(g, K)
+    e = rel_l2(f_gpu, f_ref)
+    log(f"c2 EM rel-L2 {e:.3e}")
+    assert e <= EM_TOL
+    assert np.all(f_gpu >= 0)
+
+
+def test_c3_sampled_projections(torch, ctis, oracle_mod):
+    """Full-size c3 projections on the GPU, checked on sampled pixels and
+    voxels that the oracle evaluates one by one from the definition."""
+    case = W.make_case(3)
+    geo = case.geometry
+    log("c3 sampled projections")
+    p = ctis.Plan.from_case(case)
+    ok = oracle_mod.Oracle.from_case(case, assemble=False)
+    rng = np.random.default_rng(33)
+    f = case.f_true.astype(np.float32)
+    g_gpu = p.forward(torch.from_numpy(f).cuda()).cpu().numpy().ravel()
+    rows = rng.choice(geo.n, 3000, replace=False)
+    rows = np.concatenate([rows, np.flatnonzero(g_gpu)[::997]])
+    assert rel_l2(g_gpu[rows], ok.forward_rows(f, rows)) <= PROJ_TOL
+    r = rng.random(geo.n).astype(np.float32)
+    z_gpu = p.adjoint(torch.from_numpy(r).cuda()).cpu().numpy().ravel()
+    cols = rng.choice(geo.m, 3000, replace=False)
+    assert rel_l2(z_gpu[cols], ok.adjoint_cols(r, cols)) <= PROJ_TOL
