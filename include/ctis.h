@@ -20,7 +20,7 @@
  * Conventions shared by every call
  * --------------------------------
  *  Sizes:   n = gamma * xi FPA pixels, ell = a * alpha field-stop pixels,
- *           m = ell * w voxels.  n and m must fit in int32.
+ *           m = ell * w voxels; n and ell below 2^29, m below 2^31.
  *  Layout:  the paper's column-major vectorisation (Sec. 2; Sec. 3 index map).
  *           Voxel (x, y, s), x < a, y < alpha, s < w, is f[x + a*y + ell*s]
  *           (a row-major (w, alpha, a) array).  FPA pixel (r, c), r < gamma,
@@ -61,7 +61,7 @@ typedef enum {
     CTIS_E_ARG = 1,         /* null pointer, bad size or flag, wrong device   */
     CTIS_E_INDEX = 2,       /* calibration index outside [0, n)               */
     CTIS_E_VALUE = 3,       /* non-finite calibration value                   */
-    CTIS_E_TOO_LARGE = 4,   /* n, m or a table size does not fit in int32     */
+    CTIS_E_TOO_LARGE = 4,   /* n, ell, m or a table size beyond the limits    */
     CTIS_E_NOMEM = 5,       /* host or device allocation failed               */
     CTIS_E_HIP = 6,         /* a HIP runtime call or kernel launch failed     */
     CTIS_E_NEGATIVE = 7,    /* EM needs nonnegative calibration values        */
@@ -187,15 +187,24 @@ ctis_status ctis_em_iterate(const ctis_plan *plan, const float *g, float *f, int
                             void *workspace, size_t workspace_bytes, void *stream);
 
 /*
- * ctis_em_iterate with per-kernel timing, for benchmarking: HIP events are
- * recorded on `stream` before and after every launch, the call waits for the
- * work to finish, and ms_forward / ms_adjoint (HOST, may be NULL) receive the
- * summed durations in milliseconds of the `iters` forward+ratio and
- * adjoint+update launches.  Same arguments and errors as ctis_em_iterate.
+ * The two fused kernels of one EM iteration, for callers that schedule the
+ * iteration themselves (ctis_em_iterate is these two calls, iters times):
+ *
+ *   ctis_em_forward_ratio:  u_i = g_i / (H f)_i, or 0 where (H f)_i <= 0, for
+ *       every pixel of an FPA tile that meets the image of some calibration
+ *       nonzero; the other pixels of u are not written (the back projection
+ *       never reads them).
+ *       f DEVICE float[m] (read), g DEVICE float[n] (read), u DEVICE float[n]
+ *       (written as described).
+ *   ctis_em_adjoint_update: f_out_j = f_in_j * (H^T u)_j / h_j, or 0 where
+ *       h_j == 0.  u as left by ctis_em_forward_ratio; f_out may equal f_in
+ *       (in place) but must not overlap it otherwise.
+ * Errors: CTIS_E_NEGATIVE if a calibration value is negative, CTIS_E_ARG.
  */
-ctis_status ctis_em_iterate_timed(const ctis_plan *plan, const float *g, float *f, int32_t iters,
-                                  void *workspace, size_t workspace_bytes, void *stream,
-                                  float *ms_forward, float *ms_adjoint);
+ctis_status ctis_em_forward_ratio(const ctis_plan *plan, const float *f, const float *g, float *u,
+                                  void *stream);
+ctis_status ctis_em_adjoint_update(const ctis_plan *plan, const float *u, const float *f_in, float *f_out,
+                                   void *stream);
 
 /* Static description of a status code. */
 const char *ctis_status_str(ctis_status status);

@@ -1,7 +1,5 @@
 // C ABI of libctis: argument checking, plan lifetime and the stream-ordered
 // drivers.  The arithmetic is in kernels.hip.
-#include <hip/hip_runtime_api.h>
-
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -89,8 +87,8 @@ ctis_status ctis_plan_create(ctis_plan **out, int32_t a, int32_t alpha, int32_t 
         return fail(CTIS_E_ARG, "a, alpha, w, gamma, xi must all be >= 1");
     if (a > gamma || alpha > xi) return fail(CTIS_E_ARG, "the field stop must fit on the FPA (a <= gamma, alpha <= xi)");
     const int64_t n = (int64_t)gamma * xi, ell = (int64_t)a * alpha, m = ell * w;
-    if (n > INT32_MAX - 4096 || m > INT32_MAX - 4096)
-        return fail(CTIS_E_TOO_LARGE, "n = gamma*xi and m = a*alpha*w must fit in int32");
+    if (n > kMaxPixels || ell > kMaxPixels || m > INT32_MAX - 4096)
+        return fail(CTIS_E_TOO_LARGE, "n = gamma*xi and a*alpha must be below 2^29, m = a*alpha*w below 2^31");
     if (!lambda_ptr) return fail(CTIS_E_ARG, "lambda_ptr is NULL");
     if (lambda_ptr[0] != 0) return fail(CTIS_E_ARG, "lambda_ptr[0] must be 0");
     for (int32_t s = 0; s < w; ++s)
@@ -253,47 +251,31 @@ ctis_status ctis_em_iterate(const ctis_plan *p, const float *g, float *f, int32_
     return CTIS_OK;
 }
 
-ctis_status ctis_em_iterate_timed(const ctis_plan *p, const float *g, float *f, int32_t iters, void *workspace,
-                                  size_t workspace_bytes, void *stream, float *ms_forward, float *ms_adjoint) {
-    ctis_status st = em_check(p, g, f, iters, workspace, workspace_bytes);
+ctis_status ctis_em_forward_ratio(const ctis_plan *p, const float *f, const float *g, float *u, void *stream) {
+    if (!p) return fail(CTIS_E_ARG, "plan is NULL");
+    if (!f || !g || !u) return fail(CTIS_E_ARG, "f, g or u is NULL");
+    if (!aligned4(f) || !aligned4(g) || !aligned4(u)) return fail(CTIS_E_ARG, "f, g and u must be 4-byte aligned");
+    if (!p->ht.nonneg) return fail(CTIS_E_NEGATIVE, "the plan has a negative calibration value");
+    if (overlaps(u, (size_t)p->n * 4, f, (size_t)p->m * 4) || overlaps(u, (size_t)p->n * 4, g, (size_t)p->n * 4))
+        return fail(CTIS_E_ARG, "u must not overlap f or g");
+    ctis_status st = check_device(p);
     if (st != CTIS_OK) return st;
-    hipStream_t hs = (hipStream_t)stream;
-    std::vector<hipEvent_t> ev((size_t)2 * iters + 1, nullptr);
-    auto cleanup = [&]() {
-        for (auto e : ev)
-            if (e) (void)hipEventDestroy(e);
-    };
-    for (auto &e : ev) {
-        hipError_t he = hipEventCreate(&e);
-        if (he != hipSuccess) {
-            cleanup();
-            return fail(CTIS_E_HIP, std::string("hipEventCreate: ") + hipGetErrorString(he));
-        }
-    }
-    float *u = (float *)workspace;
-    hipError_t he = hipEventRecord(ev[0], hs);
-    for (int32_t k = 0; k < iters && he == hipSuccess && st == CTIS_OK; ++k) {
-        st = launch_status(launch_forward(p, f, g, u, true, stream), "forward+ratio launch");
-        if (st == CTIS_OK) he = hipEventRecord(ev[(size_t)2 * k + 1], hs);
-        if (st == CTIS_OK && he == hipSuccess)
-            st = launch_status(launch_adjoint(p, u, f, f, true, stream), "adjoint+update launch");
-        if (st == CTIS_OK && he == hipSuccess) he = hipEventRecord(ev[(size_t)2 * k + 2], hs);
-    }
-    if (st == CTIS_OK && he == hipSuccess) he = hipEventSynchronize(ev.back());
-    double fw = 0.0, ad = 0.0;
-    for (int32_t k = 0; k < iters && st == CTIS_OK && he == hipSuccess; ++k) {
-        float t1 = 0.0f, t2 = 0.0f;
-        he = hipEventElapsedTime(&t1, ev[(size_t)2 * k], ev[(size_t)2 * k + 1]);
-        if (he == hipSuccess) he = hipEventElapsedTime(&t2, ev[(size_t)2 * k + 1], ev[(size_t)2 * k + 2]);
-        fw += t1;
-        ad += t2;
-    }
-    cleanup();
+    return launch_status(launch_forward(p, f, g, u, true, stream), "forward+ratio launch");
+}
+
+ctis_status ctis_em_adjoint_update(const ctis_plan *p, const float *u, const float *f_in, float *f_out,
+                                   void *stream) {
+    if (!p) return fail(CTIS_E_ARG, "plan is NULL");
+    if (!u || !f_in || !f_out) return fail(CTIS_E_ARG, "u, f_in or f_out is NULL");
+    if (!aligned4(u) || !aligned4(f_in) || !aligned4(f_out))
+        return fail(CTIS_E_ARG, "u, f_in and f_out must be 4-byte aligned");
+    if (!p->ht.nonneg) return fail(CTIS_E_NEGATIVE, "the plan has a negative calibration value");
+    const size_t mb = (size_t)p->m * 4;
+    if (f_in != f_out && overlaps(f_in, mb, f_out, mb)) return fail(CTIS_E_ARG, "f_in and f_out overlap");
+    if (overlaps(u, (size_t)p->n * 4, f_out, mb)) return fail(CTIS_E_ARG, "u and f_out overlap");
+    ctis_status st = check_device(p);
     if (st != CTIS_OK) return st;
-    if (he != hipSuccess) return fail(CTIS_E_HIP, std::string("HIP event: ") + hipGetErrorString(he));
-    if (ms_forward) *ms_forward = (float)fw;
-    if (ms_adjoint) *ms_adjoint = (float)ad;
-    return CTIS_OK;
+    return launch_status(launch_adjoint(p, u, f_in, f_out, true, stream), "adjoint+update launch");
 }
 
 }  // extern "C"

@@ -9,6 +9,11 @@
 
 #include "ctis.h"
 
+#ifndef __HIP_PLATFORM_AMD__
+#define __HIP_PLATFORM_AMD__
+#endif
+#include <hip/hip_runtime_api.h>
+
 namespace ctis {
 
 // Tile shape of both kernels: a wavefront covers 64 x 16 outputs (fast x slow
@@ -16,18 +21,22 @@ namespace ctis {
 constexpr int kTileFast = 64;
 constexpr int kTileSlow = 16;
 constexpr int kMaxBox = 8;
+// 32-bit buffer offsets (in bytes) address the FPA and one wavelength block
+constexpr int64_t kMaxPixels = (int64_t(1) << 29) - 1;
 
 // Device-side tables of a plan (one allocation, pointers into it).
+// Work records are int4 (X, Y, s, box); box = -1 ends a list.
 struct DevTables {
-    const int32_t *box_rc;          // 2*nb: anchor (r, c) of each box
-    const int32_t *box_lambda;      // nb
-    const float *box_w;             // nb*B*B, [dc*B + dr]
-    const float *box_wf;            // nb*B*B, flipped: [(B-1-dc)*B + (B-1-dr)]
-    const int32_t *lambda_box_ptr;  // w+1
-    const float *h;                 // w
-    const int32_t *tile_order;      // n_tiles: active tiles (heaviest first), then the rest
-    const int32_t *tile_item_ptr;   // n_tiles+1, indexed by tile id
-    const int32_t *item_box;        // n_items
+    const int32_t *unit_tile;   // n_tiles: FPA tile of each forward workgroup (active
+                                //   tiles, heaviest first, then the empty ones)
+    const int4 *fwd_items;      // n_tiles * fwd_stride: per workgroup, its (tile, box)
+                                //   items with X, Y = the window origin
+                                //   (r0 - (B-1) - rA, c0 - (B-1) - cA)
+    const int4 *adj_items;      // w * adj_stride: per wavelength, its boxes with
+                                //   X, Y = the anchor (rA, cA)
+    const float *box_w;         // nb*B*B, [dc*B + dr]
+    const float *box_wf;        // nb*B*B, flipped: [(B-1-dc)*B + (B-1-dr)]
+    const float *h;             // w: column sums per wavelength
 };
 
 // Scalar kernel parameters (passed by value).
@@ -36,6 +45,8 @@ struct KParams {
     int32_t ell, n;
     int32_t ntr;        // FPA tiles along the fast axis
     int32_t nbx, nby;   // field-stop tiles along x and y
+    int32_t fwd_stride; // records per forward workgroup (max boxes on one FPA tile)
+    int32_t adj_stride; // records per wavelength (max boxes of one wavelength)
 };
 
 struct HostTables {
@@ -75,6 +86,8 @@ ctis_status build_host_tables(ctis_plan *p, const int64_t *lambda_ptr, const int
 ctis_status upload_tables(ctis_plan *p);
 
 // kernel launchers (kernels.hip); return hipError_t as int
+int max_waves(int box);
+int min_waves();
 int launch_forward(const ctis_plan *p, const float *f, const float *g, float *out, bool em_ratio,
                    void *stream);
 int launch_adjoint(const ctis_plan *p, const float *u, const float *fin, float *out, bool em_update,

@@ -6,10 +6,13 @@
 // Both are atomic-free gathers over dense B x B boxes of calibration
 // nonzeros.  A wavefront owns a 64 x 16 output tile (fast x slow axis) with a
 // 4 x 4 register micro-tile per lane, stages the (64+B-1) x (16+B-1) input
-// window a box needs into its own LDS region, and correlates it with the
-// box's values, which are wave-uniform and come through scalar loads.  The
-// waves of a workgroup split the boxes of one tile and meet in an LDS
-// reduction in a fixed order, so results are deterministic.
+// window of one box into its own LDS region, and correlates it with the box's
+// values, which are wave-uniform and arrive through scalar loads.  Each wave
+// keeps the next box's window in flight in registers while it computes the
+// current one.  The waves of a workgroup split the boxes of one tile and meet
+// in an LDS reduction in a fixed order (deterministic results); the reduced
+// tile leaves row by row, so every epilogue load and store is a contiguous
+// 256-byte wavefront access.
 //
 //   forward  (one workgroup per FPA tile, the tile's boxes from the work list):
 //     ghat(r, c) = sum_box sum_{dr,dc} v[dr,dc] * fE((r - rA - dr) + gamma*(c - cA - dc) mod n)
@@ -20,8 +23,13 @@
 //
 // The window loaders evaluate the 1-D address modulo n with a row/column
 // decomposition, which is exact for the paper's cyclic shift over the whole
-// vectorised FPA, including shifts that run past an FPA edge.
+// vectorised FPA, including shifts that run past an FPA edge.  Window slots
+// outside the field stop (forward) or outside the dilated field stop
+// (adjoint) are fetched with an out-of-range buffer offset, which the buffer
+// unit returns as 0.
 #include <hip/hip_runtime.h>
+
+#include <mutex>
 
 #include "ctis_internal.h"
 
@@ -30,6 +38,10 @@ namespace {
 
 constexpr int TX = kTileFast;
 constexpr int TY = kTileSlow;
+constexpr int kMinWaves = 4;                     // so that a wave owns <= 4 epilogue rows
+constexpr int kRowsPerWave = TY / kMinWaves;
+constexpr unsigned kOutOfRange = 0x80000000u;   // buffer offset past num_records -> 0
+constexpr int kRsrcWord3 = 0x00020000;           // raw 32-bit buffer, gfx9 family
 
 template <int B>
 struct Win {
@@ -39,11 +51,29 @@ struct Win {
     static constexpr int REG = SXP * SY;           // floats per wavefront region
     static constexpr int NR = 4 + B - 1;           // row segment a lane reads
     static constexpr int NV = (NR + 3) / 4;        // float4 reads per segment
-    static_assert(REG >= 1024, "the reduction reuses 1024 floats per wave");
+    static constexpr int E = B - 1;                // window columns beyond the 64 lanes
+    static constexpr int NXT = (E * SY + 63) / 64; // extra slots per lane
+    static constexpr int WREG = REG + 64;          // region incl. the box values (<= 64)
+    static constexpr int MAXW = B <= 6 ? 16 : 8;   // waves per workgroup (VGPR budget)
+    static_assert(REG >= TX * TY, "the reduction reuses 1024 floats per wave");
+    static_assert(REG % 4 == 0 && B * B <= 64, "box values sit 16-byte aligned after the window");
     static_assert(4 * (TX / 4 - 1) + 4 * NV <= SXP, "segment reads stay inside the row");
 };
 
-// floor division / modulo for b > 0
+// One window in flight, in registers: window column `lane`, this lane's
+// slots of the extra columns, and (lanes < B*B) one of the box's values.
+template <int B>
+struct Pending {
+    float v[Win<B>::SY];
+    float x[Win<B>::NXT > 0 ? Win<B>::NXT : 1];
+    float wt;
+};
+
+// Work records: int4 (X, Y, s, box); box < 0 ends a list.
+__device__ __forceinline__ int4 record(const int4 *__restrict__ list, int k, int stride) {
+    return k < stride ? list[k] : make_int4(0, 0, 0, -1);
+}
+
 __device__ __forceinline__ void floor_divmod(int x, int b, int &q, int &r) {
     q = x / b;
     r = x - q * b;
@@ -55,10 +85,30 @@ __device__ __forceinline__ void floor_divmod(int x, int b, int &q, int &r) {
 
 __device__ __forceinline__ int step_mod(int y, int m) { return (y + 1 == m) ? 0 : y + 1; }
 
-// Decode the fast-axis part of a 1-D FPA address for this lane's window
-// column X = Xs + col: returns xm = X mod gamma and the slow-axis index
-// y = (Ys + X div gamma) mod xi (both floor semantics).
-__device__ __forceinline__ void decode_column(const KParams &p, int Xs, int Ys, int col, int &xm, int &y) {
+// The lanes of a wavefront hand data to each other through LDS (a window and
+// its box values written by some lanes, read by others).  The hardware runs a
+// wavefront's LDS instructions in order; this fence pair keeps the compiler
+// from moving LDS loads or stores across the hand-off (without it, a load of
+// data another lane wrote may legally be hoisted out of the item loop).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const float *base, int nfloats) {
+    return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, nfloats * 4, kRsrcWord3);
+}
+
+// raw 32-bit buffer load, reinterpreted as float (the builtin returns the bits)
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
+// 1-D FPA address (Xs + col) + gamma*(Ys + row) mod n, for row = 0:
+// xm = (Xs + col) mod gamma, y = (Ys + (Xs + col) div gamma) mod xi.
+// Xs, Ys are wave-uniform (scalar divisions), col is per lane.
+__device__ __forceinline__ void decode(const KParams &p, int Xs, int Ys, int col, int &xm, int &y) {
     int q0, r0;
     floor_divmod(Xs, p.gamma, q0, r0);
     int yq, y0;
@@ -71,82 +121,103 @@ __device__ __forceinline__ void decode_column(const KParams &p, int Xs, int Ys, 
     }
 }
 
-// Forward window: slot (xx, yy) <- fE((Xs + xx) + gamma*(Ys + yy) mod n).
 template <int B>
-__device__ __forceinline__ void stage_forward(float *S, const float *__restrict__ fs, const KParams &p, int Xs,
-                                              int Ys, int lane) {
+__device__ __forceinline__ void load_values(Pending<B> &pd, const float *__restrict__ wtab, int box, int lane) {
+    pd.wt = 0.0f;
+    if (lane < B * B) pd.wt = wtab[(size_t)box * (B * B) + lane];
+}
+
+// Forward window of one (tile, box) item, rec = (Xs, Ys, s, box):
+// slot (xx, yy) <- fE((Xs + xx) + gamma*(Ys + yy) mod n).
+template <int B>
+__device__ __forceinline__ void load_forward(Pending<B> &pd, const float *f, const float *__restrict__ wtab,
+                                             const KParams &p, int4 rec, int lane) {
     using Wn = Win<B>;
+    const __amdgpu_buffer_rsrc_t fr = rsrc(f + (size_t)rec.z * p.ell, p.ell);
+    const int Xs = rec.x, Ys = rec.y;
     {
         int xm, y;
-        decode_column(p, Xs, Ys, lane, xm, y);
+        decode(p, Xs, Ys, lane, xm, y);
         const bool vx = xm < p.a;
-        float v[Wn::SY];
 #pragma unroll
         for (int yy = 0; yy < Wn::SY; ++yy) {
             const bool ok = vx && (y < p.alpha);
-            const float t = fs[ok ? xm + p.a * y : 0];
-            v[yy] = ok ? t : 0.0f;
+            pd.v[yy] = bload(fr, ok ? (unsigned)(xm + p.a * y) * 4u : kOutOfRange);
             y = step_mod(y, p.xi);
         }
-#pragma unroll
-        for (int yy = 0; yy < Wn::SY; ++yy) S[yy * Wn::SXP + lane] = v[yy];
     }
-    if constexpr (B > 1) {
-        constexpr int E = B - 1;
-        for (int k = lane; k < E * Wn::SY; k += 64) {
-            const int e = k % E, yy = k / E;
+#pragma unroll
+    for (int t = 0; t < Wn::NXT; ++t) {
+        const int k = lane + 64 * t;
+        unsigned off = kOutOfRange;
+        if (k < Wn::E * Wn::SY) {
+            const int e = k % Wn::E, yy = k / Wn::E;
             int xm, y;
-            decode_column(p, Xs, Ys, TX + e, xm, y);
+            decode(p, Xs, Ys, TX + e, xm, y);
             y += yy;
             while (y >= p.xi) y -= p.xi;
-            const bool ok = (xm < p.a) && (y < p.alpha);
-            const float t = fs[ok ? xm + p.a * y : 0];
-            S[yy * Wn::SXP + TX + e] = ok ? t : 0.0f;
+            if (xm < p.a && y < p.alpha) off = (unsigned)(xm + p.a * y) * 4u;
         }
+        pd.x[t] = bload(fr, off);
     }
+    load_values<B>(pd, wtab, rec.w, lane);
 }
 
-// Adjoint window: slot (xx, yy) <- u((Xs + xx) + gamma*(Ys + yy) mod n) for
-// xx < xlim, yy < ylim (the dilated field stop), else 0.
+// Adjoint window of one (field-stop tile, box) pair: slot (xx, yy) <-
+// u((Xs + xx) + gamma*(Ys + yy) mod n).  Slots past the dilated field stop
+// (xx >= a + B - 1 - x0 or yy >= alpha + B - 1 - y0) only ever meet output
+// voxels outside the field stop, which are never written, so they need no
+// masking; their addresses are still reduced mod n and stay in bounds.
 template <int B>
-__device__ __forceinline__ void stage_adjoint(float *S, const float *__restrict__ u, const KParams &p, int Xs,
-                                              int Ys, int xlim, int ylim, int lane) {
+__device__ __forceinline__ void load_adjoint(Pending<B> &pd, __amdgpu_buffer_rsrc_t ur,
+                                             const float *__restrict__ wtab, const KParams &p, int Xs, int Ys,
+                                             int box, int lane) {
     using Wn = Win<B>;
     {
         int xm, y;
-        decode_column(p, Xs, Ys, lane, xm, y);
-        const bool vx = lane < xlim;
-        float v[Wn::SY];
+        decode(p, Xs, Ys, lane, xm, y);
 #pragma unroll
         for (int yy = 0; yy < Wn::SY; ++yy) {
-            const bool ok = vx && (yy < ylim);
-            const float t = u[ok ? xm + p.gamma * y : 0];
-            v[yy] = ok ? t : 0.0f;
+            pd.v[yy] = bload(ur, (unsigned)(xm + p.gamma * y) * 4u);
             y = step_mod(y, p.xi);
         }
-#pragma unroll
-        for (int yy = 0; yy < Wn::SY; ++yy) S[yy * Wn::SXP + lane] = v[yy];
     }
-    if constexpr (B > 1) {
-        constexpr int E = B - 1;
-        for (int k = lane; k < E * Wn::SY; k += 64) {
-            const int e = k % E, yy = k / E;
+#pragma unroll
+    for (int t = 0; t < Wn::NXT; ++t) {
+        const int k = lane + 64 * t;
+        unsigned off = kOutOfRange;
+        if (k < Wn::E * Wn::SY) {
+            const int e = k % Wn::E, yy = k / Wn::E;
             int xm, y;
-            decode_column(p, Xs, Ys, TX + e, xm, y);
+            decode(p, Xs, Ys, TX + e, xm, y);
             y += yy;
             while (y >= p.xi) y -= p.xi;
-            const bool ok = (TX + e < xlim) && (yy < ylim);
-            const float t = u[ok ? xm + p.gamma * y : 0];
-            S[yy * Wn::SXP + TX + e] = ok ? t : 0.0f;
+            off = (unsigned)(xm + p.gamma * y) * 4u;
         }
+        pd.x[t] = bload(ur, off);
     }
+    load_values<B>(pd, wtab, box, lane);
+}
+
+// Window into S[0, REG), box values into S[REG, REG + B*B).
+template <int B>
+__device__ __forceinline__ void store_window(float *S, const Pending<B> &pd, int lane) {
+    using Wn = Win<B>;
+#pragma unroll
+    for (int yy = 0; yy < Wn::SY; ++yy) S[yy * Wn::SXP + lane] = pd.v[yy];
+#pragma unroll
+    for (int t = 0; t < Wn::NXT; ++t) {
+        const int k = lane + 64 * t;
+        if (k < Wn::E * Wn::SY) S[(k / Wn::E) * Wn::SXP + TX + k % Wn::E] = pd.x[t];
+    }
+    if (lane < B * B) S[Wn::REG + lane] = pd.wt;
 }
 
 // acc[k][q] += sum_{i,j < B} W[j*B + i] * S[(4ly + k + j) * SXP + 4lx + q + i]
 template <int B>
-__device__ __forceinline__ void correlate(float (&acc)[4][4], const float *S, int lx, int ly,
-                                          const float *__restrict__ W) {
+__device__ __forceinline__ void correlate(float (&acc)[4][4], const float *S, int lx, int ly) {
     using Wn = Win<B>;
+    const float *W = S + Wn::REG;
 #pragma unroll
     for (int row = 0; row < Wn::NR; ++row) {
         float seg[4 * Wn::NV];
@@ -173,99 +244,93 @@ __device__ __forceinline__ void correlate(float (&acc)[4][4], const float *S, in
     }
 }
 
-// Sum the other waves' accumulators into wave 0 (fixed order).  Returns false
-// on waves other than 0, which then have nothing left to do.
-__device__ __forceinline__ bool reduce_waves(float (&acc)[4][4], float *lds, int wv, int nw, int lane) {
-    if (nw == 1) return true;
+// Park every wave's 4x4 micro-tiles in LDS as a 16 x 64 row-major tile
+// (region `wv`), so that rows can then be summed over the waves in a fixed order.
+__device__ __forceinline__ void park_tile(const float (&acc)[4][4], float *lds, int wv, int lx, int ly) {
+    __syncthreads();   // every wave is done with its window region
+    float *P = lds + wv * (TX * TY);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        *reinterpret_cast<float4 *>(P + (4 * ly + k) * TX + 4 * lx) =
+            make_float4(acc[k][0], acc[k][1], acc[k][2], acc[k][3]);
     __syncthreads();
-    if (wv > 0) {
-        float *R = lds + (wv - 1) * 1024;
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) R[(k * 4 + q) * 64 + lane] = acc[k][q];
-    }
-    __syncthreads();
-    if (wv != 0) return false;
-    for (int w2 = 1; w2 < nw; ++w2) {
-        const float *R = lds + (w2 - 1) * 1024;
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) acc[k][q] += R[(k * 4 + q) * 64 + lane];
-    }
-    return true;
 }
 
+__device__ __forceinline__ float row_sum(const float *lds, int nw, int row, int lane) {
+    float v = 0.0f;
+    for (int w2 = 0; w2 < nw; ++w2) v += lds[w2 * (TX * TY) + row * TX + lane];
+    return v;
+}
+
+// Wave `wv` of `nw` owns output rows wv, wv + nw, ... of the tile (at most TY).
+#define FOR_OWN_ROWS(j, row)                                  \
+    _Pragma("unroll") for (int j = 0; j < kRowsPerWave; ++j)  \
+        if (const int row = wv + j * nw; row < TY)
+
 template <int B>
-__global__ void __launch_bounds__(256) k_forward(const KParams p, const int32_t *__restrict__ tile_order,
-                                                 const int32_t *__restrict__ tile_item_ptr,
-                                                 const int32_t *__restrict__ item_box,
-                                                 const int32_t *__restrict__ box_rc,
-                                                 const int32_t *__restrict__ box_lambda,
-                                                 const float *__restrict__ box_wf, const float *__restrict__ f,
-                                                 const float *__restrict__ g, float *__restrict__ out, int em,
-                                                 int vec) {
+__global__ void __launch_bounds__(64 * Win<B>::MAXW) k_forward(const KParams p, const int32_t *__restrict__ unit_tile,
+                                                  const int4 *__restrict__ items, const float *__restrict__ box_wf,
+                                                  const float *__restrict__ f, const float *__restrict__ g,
+                                                  float *__restrict__ out, int em) {
     using Wn = Win<B>;
     extern __shared__ float4 lds4[];
     float *lds = reinterpret_cast<float *>(lds4);
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nw = blockDim.x >> 6;
-    const int tile = tile_order[blockIdx.x];
+    const int stride = p.fwd_stride;
+    const int4 *list = items + (size_t)blockIdx.x * stride;
+    int k = wv;
+    int4 rec0 = record(list, k, stride);
+    int4 rec1 = record(list, k + nw, stride);
+    const int tile = unit_tile[blockIdx.x];
     const int r0 = (tile % p.ntr) * TX, c0 = (tile / p.ntr) * TY;
-    const int it0 = tile_item_ptr[tile], it1 = tile_item_ptr[tile + 1];
-    float *S = lds + wv * Wn::REG;
+    float *S = lds + wv * Wn::WREG;
     const int lx = lane & 15, ly = lane >> 4;
+    const int r = r0 + lane;
+
+    // operands of the epilogue, fetched up front
+    float gpre[kRowsPerWave];
+    FOR_OWN_ROWS(j, row) {
+        const int c = c0 + row;
+        gpre[j] = (em && r < p.gamma && c < p.xi) ? g[(size_t)r + (size_t)p.gamma * c] : 0.0f;
+    }
 
     float acc[4][4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[k][q] = 0.0f;
+        for (int q = 0; q < 4; ++q) acc[a][q] = 0.0f;
 
-    for (int it = it0 + wv; it < it1; it += nw) {
-        const int b = __builtin_amdgcn_readfirstlane(item_box[it]);
-        const int rA = box_rc[2 * b], cA = box_rc[2 * b + 1];
-        const int s = box_lambda[b];
-        stage_forward<B>(S, f + (size_t)s * p.ell, p, r0 - (B - 1) - rA, c0 - (B - 1) - cA, lane);
-        correlate<B>(acc, S, lx, ly, box_wf + (size_t)b * (B * B));
+    Pending<B> pd;
+    if (rec0.w >= 0) load_forward<B>(pd, f, box_wf, p, rec0, lane);
+    while (rec0.w >= 0) {
+        store_window<B>(S, pd, lane);
+        wave_lds_sync();
+        k += nw;
+        const int4 rec2 = record(list, k + nw, stride);
+        if (rec1.w >= 0) load_forward<B>(pd, f, box_wf, p, rec1, lane);
+        correlate<B>(acc, S, lx, ly);
+        wave_lds_sync();
+        rec0 = rec1;
+        rec1 = rec2;
     }
-    if (!reduce_waves(acc, lds, wv, nw, lane)) return;
 
-    const int rb = r0 + 4 * lx;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int c = c0 + 4 * ly + k;
-        if (c >= p.xi) continue;
-        const size_t base = (size_t)rb + (size_t)p.gamma * c;
-        if (vec && rb + 3 < p.gamma) {
-            float4 v = make_float4(acc[k][0], acc[k][1], acc[k][2], acc[k][3]);
-            if (em) {
-                const float4 gv = *reinterpret_cast<const float4 *>(g + base);
-                v.x = v.x > 0.0f ? gv.x / v.x : 0.0f;
-                v.y = v.y > 0.0f ? gv.y / v.y : 0.0f;
-                v.z = v.z > 0.0f ? gv.z / v.z : 0.0f;
-                v.w = v.w > 0.0f ? gv.w / v.w : 0.0f;
-            }
-            *reinterpret_cast<float4 *>(out + base) = v;
-        } else {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (rb + q >= p.gamma) continue;
-                float v = acc[k][q];
-                if (em) v = v > 0.0f ? g[base + q] / v : 0.0f;
-                out[base + q] = v;
-            }
+    park_tile(acc, lds, wv, lx, ly);
+    FOR_OWN_ROWS(j, row) {
+        const int c = c0 + row;
+        float v = row_sum(lds, nw, row, lane);
+        if (r < p.gamma && c < p.xi) {
+            if (em) v = v > 0.0f ? gpre[j] / v : 0.0f;
+            out[(size_t)r + (size_t)p.gamma * c] = v;
         }
     }
 }
 
 template <int B>
-__global__ void __launch_bounds__(256) k_adjoint(const KParams p, const int32_t *__restrict__ lambda_box_ptr,
-                                                 const int32_t *__restrict__ box_rc, const float *__restrict__ box_w,
-                                                 const float *__restrict__ hsum, const float *__restrict__ u,
-                                                 const float *fin, float *out, int em, int vec) {
+__global__ void __launch_bounds__(64 * Win<B>::MAXW) k_adjoint(const KParams p, const int4 *__restrict__ items,
+                                                  const float *__restrict__ box_w, const float *__restrict__ hsum,
+                                                  const float *__restrict__ u, const float *fin, float *out, int em) {
     using Wn = Win<B>;
     extern __shared__ float4 lds4[];
     float *lds = reinterpret_cast<float *>(lds4);
@@ -274,67 +339,82 @@ __global__ void __launch_bounds__(256) k_adjoint(const KParams p, const int32_t 
     const int nw = blockDim.x >> 6;
     const int per = p.nbx * p.nby;
     const int s = blockIdx.x / per, vt = blockIdx.x - s * per;
+    const int stride = p.adj_stride;
+    const int4 *list = items + (size_t)s * stride;
+    int k = wv;
+    int4 rec0 = record(list, k, stride);
+    int4 rec1 = record(list, k + nw, stride);
     const int x0 = (vt % p.nbx) * TX, y0 = (vt / p.nbx) * TY;
-    const int b0 = lambda_box_ptr[s], b1 = lambda_box_ptr[s + 1];
-    const int xlim = p.a + B - 1 - x0, ylim = p.alpha + B - 1 - y0;
-    float *S = lds + wv * Wn::REG;
+    float *S = lds + wv * Wn::WREG;
     const int lx = lane & 15, ly = lane >> 4;
+    const __amdgpu_buffer_rsrc_t ur = rsrc(u, p.n);
+    const int x = x0 + lane;
+    const size_t sb = (size_t)s * p.ell;
+
+    float fpre[kRowsPerWave];
+    FOR_OWN_ROWS(j, row) {
+        const int y = y0 + row;
+        fpre[j] = (em && x < p.a && y < p.alpha) ? fin[sb + (size_t)x + (size_t)p.a * y] : 0.0f;
+    }
+    const float hs = hsum[s];
 
     float acc[4][4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[k][q] = 0.0f;
+        for (int q = 0; q < 4; ++q) acc[a][q] = 0.0f;
 
-    for (int b = b0 + wv; b < b1; b += nw) {
-        const int rA = box_rc[2 * b], cA = box_rc[2 * b + 1];
-        stage_adjoint<B>(S, u, p, rA + x0, cA + y0, xlim, ylim, lane);
-        correlate<B>(acc, S, lx, ly, box_w + (size_t)b * (B * B));
+    Pending<B> pd;
+    if (rec0.w >= 0) load_adjoint<B>(pd, ur, box_w, p, rec0.x + x0, rec0.y + y0, rec0.w, lane);
+    while (rec0.w >= 0) {
+        store_window<B>(S, pd, lane);
+        wave_lds_sync();
+        k += nw;
+        const int4 rec2 = record(list, k + nw, stride);
+        if (rec1.w >= 0) load_adjoint<B>(pd, ur, box_w, p, rec1.x + x0, rec1.y + y0, rec1.w, lane);
+        correlate<B>(acc, S, lx, ly);
+        wave_lds_sync();
+        rec0 = rec1;
+        rec1 = rec2;
     }
-    if (!reduce_waves(acc, lds, wv, nw, lane)) return;
 
-    const float hs = hsum[s];
-    const int xb = x0 + 4 * lx;
-    const size_t sb = (size_t)s * p.ell;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int y = y0 + 4 * ly + k;
-        if (y >= p.alpha) continue;
-        const size_t base = sb + (size_t)xb + (size_t)p.a * y;
-        if (vec && xb + 3 < p.a) {
-            float4 v = make_float4(acc[k][0], acc[k][1], acc[k][2], acc[k][3]);
-            if (em) {
-                const float4 fv = *reinterpret_cast<const float4 *>(fin + base);
-                v.x = hs != 0.0f ? (fv.x * v.x) / hs : 0.0f;
-                v.y = hs != 0.0f ? (fv.y * v.y) / hs : 0.0f;
-                v.z = hs != 0.0f ? (fv.z * v.z) / hs : 0.0f;
-                v.w = hs != 0.0f ? (fv.w * v.w) / hs : 0.0f;
-            }
-            *reinterpret_cast<float4 *>(out + base) = v;
-        } else {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (xb + q >= p.a) continue;
-                float v = acc[k][q];
-                if (em) v = hs != 0.0f ? (fin[base + q] * v) / hs : 0.0f;
-                out[base + q] = v;
-            }
+    park_tile(acc, lds, wv, lx, ly);
+    FOR_OWN_ROWS(j, row) {
+        const int y = y0 + row;
+        float v = row_sum(lds, nw, row, lane);
+        if (x < p.a && y < p.alpha) {
+            if (em) v = hs != 0.0f ? (fpre[j] * v) / hs : 0.0f;
+            out[sb + (size_t)x + (size_t)p.a * y] = v;
         }
     }
 }
 
-bool aligned16(const void *ptr) { return ptr == nullptr || ((uintptr_t)ptr & 15u) == 0; }
+template <int B>
+int enable_large_lds() {
+    static std::once_flag once;
+    static hipError_t err = hipSuccess;
+    std::call_once(once, []() {
+        const int bytes = Win<B>::MAXW * Win<B>::WREG * (int)sizeof(float);
+        err = hipFuncSetAttribute((const void *)k_forward<B>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (err == hipSuccess)
+            err = hipFuncSetAttribute((const void *)k_adjoint<B>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    });
+    return (int)err;
+}
 
 template <int B>
 int forward_B(const ctis_plan *pl, const float *f, const float *g, float *out, bool em, hipStream_t st) {
     const int nwg = em ? pl->ht.n_active : pl->ht.n_tiles;
     if (nwg == 0) return 0;
     const int nw = pl->waves_fwd;
-    const size_t lds = (size_t)nw * Win<B>::REG * sizeof(float);
-    const int vec = (pl->gamma % 4 == 0) && aligned16(out) && aligned16(g);
+    const size_t lds = (size_t)nw * Win<B>::WREG * sizeof(float);
+    if (lds > 65536) {
+        const int e = enable_large_lds<B>();
+        if (e) return e;
+    }
     const DevTables &t = pl->dt;
-    hipLaunchKernelGGL(k_forward<B>, dim3(nwg), dim3(64 * nw), lds, st, pl->kp, t.tile_order, t.tile_item_ptr,
-                       t.item_box, t.box_rc, t.box_lambda, t.box_wf, f, g, out, em ? 1 : 0, vec);
+    hipLaunchKernelGGL(k_forward<B>, dim3(nwg), dim3(64 * nw), lds, st, pl->kp, t.unit_tile, t.fwd_items, t.box_wf,
+                       f, g, out, em ? 1 : 0);
     return (int)hipGetLastError();
 }
 
@@ -342,15 +422,21 @@ template <int B>
 int adjoint_B(const ctis_plan *pl, const float *u, const float *fin, float *out, bool em, hipStream_t st) {
     const int nwg = pl->kp.nbx * pl->kp.nby * pl->w;
     const int nw = pl->waves_adj;
-    const size_t lds = (size_t)nw * Win<B>::REG * sizeof(float);
-    const int vec = (pl->a % 4 == 0) && aligned16(out) && aligned16(fin);
+    const size_t lds = (size_t)nw * Win<B>::WREG * sizeof(float);
+    if (lds > 65536) {
+        const int e = enable_large_lds<B>();
+        if (e) return e;
+    }
     const DevTables &t = pl->dt;
-    hipLaunchKernelGGL(k_adjoint<B>, dim3(nwg), dim3(64 * nw), lds, st, pl->kp, t.lambda_box_ptr, t.box_rc, t.box_w,
-                       t.h, u, fin, out, em ? 1 : 0, vec);
+    hipLaunchKernelGGL(k_adjoint<B>, dim3(nwg), dim3(64 * nw), lds, st, pl->kp, t.adj_items, t.box_w, t.h, u, fin,
+                       out, em ? 1 : 0);
     return (int)hipGetLastError();
 }
 
 }  // namespace
+
+int max_waves(int B) { return B <= 6 ? Win<1>::MAXW : Win<8>::MAXW; }
+int min_waves() { return kMinWaves; }
 
 int launch_forward(const ctis_plan *p, const float *f, const float *g, float *out, bool em, void *stream) {
     hipStream_t st = (hipStream_t)stream;

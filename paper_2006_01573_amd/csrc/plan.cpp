@@ -9,8 +9,6 @@
 // anchored at FPA position (rA, cA) holds the entries at (rA + dr, cA + dc),
 // and the 1-D index of such an entry is exactly rA + dr + gamma*(cA + dc), so
 // the kernels' cyclic address arithmetic stays the paper's.
-#include <hip/hip_runtime_api.h>
-
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -314,11 +312,19 @@ ctis_status build_host_tables(ctis_plan *p, const int64_t *lambda_ptr, const int
     k.nbx = T.nbx;
     k.nby = T.nby;
     p->workspace_bytes = ((size_t)n * sizeof(float) + 255) & ~(size_t)255;
-    int32_t max_boxes = 0;
+    int32_t max_boxes = 0, max_items = 0;
     for (int32_t s = 0; s < w; ++s)
         max_boxes = std::max(max_boxes, T.lambda_box_ptr[(size_t)s + 1] - T.lambda_box_ptr[(size_t)s]);
-    p->waves_fwd = 4;
-    p->waves_adj = std::max(1, std::min(4, max_boxes));
+    for (int32_t t = 0; t < T.n_tiles; ++t) max_items = std::max(max_items, count(t));
+    // one wavefront per two boxes of the heaviest tile: each wave then has a
+    // second window in flight while it computes the first
+    auto waves_for = [&](int32_t work) { return std::max(min_waves(), std::min(max_waves(B), (work + 1) / 2)); };
+    p->waves_fwd = waves_for(max_items);
+    p->waves_adj = waves_for(max_boxes);
+    if ((int64_t)max_items * T.n_tiles > INT32_MAX / 4 || (int64_t)max_boxes * w > INT32_MAX / 4)
+        return fail(CTIS_E_TOO_LARGE, "work tables too large");
+    k.fwd_stride = std::max(1, max_items);
+    k.adj_stride = std::max(1, max_boxes);
     return CTIS_OK;
 }
 
@@ -329,16 +335,51 @@ ctis_status upload_tables(ctis_plan *p) {
         size_t bytes;
         size_t off;
     };
+    const int B = T.B;
+    const int32_t fs = p->kp.fwd_stride, as = p->kp.adj_stride;
+    // forward: one list per workgroup, in launch order
+    std::vector<int32_t> fwd((size_t)4 * T.n_tiles * fs, 0);
+    for (int32_t u = 0; u < T.n_tiles; ++u) {
+        const int32_t tile = T.tile_order[(size_t)u];
+        const int32_t r0 = (tile % T.ntr) * kTileFast, c0 = (tile / T.ntr) * kTileSlow;
+        const int32_t b0 = T.tile_item_ptr[(size_t)tile], b1 = T.tile_item_ptr[(size_t)tile + 1];
+        for (int32_t k = 0; k < fs; ++k) {
+            int32_t *rec = &fwd[(size_t)4 * ((size_t)u * fs + k)];
+            if (b0 + k < b1) {
+                const int32_t b = T.item_box[(size_t)(b0 + k)];
+                rec[0] = r0 - (B - 1) - T.box_rc[2 * (size_t)b];
+                rec[1] = c0 - (B - 1) - T.box_rc[2 * (size_t)b + 1];
+                rec[2] = T.box_lambda[(size_t)b];
+                rec[3] = b;
+            } else {
+                rec[3] = -1;
+            }
+        }
+    }
+    // adjoint: one list per wavelength
+    std::vector<int32_t> adj((size_t)4 * p->w * as, 0);
+    for (int32_t s = 0; s < p->w; ++s) {
+        const int32_t b0 = T.lambda_box_ptr[(size_t)s], b1 = T.lambda_box_ptr[(size_t)s + 1];
+        for (int32_t k = 0; k < as; ++k) {
+            int32_t *rec = &adj[(size_t)4 * ((size_t)s * as + k)];
+            if (b0 + k < b1) {
+                const int32_t b = b0 + k;
+                rec[0] = T.box_rc[2 * (size_t)b];
+                rec[1] = T.box_rc[2 * (size_t)b + 1];
+                rec[2] = s;
+                rec[3] = b;
+            } else {
+                rec[3] = -1;
+            }
+        }
+    }
     std::vector<Part> parts = {
-        {T.box_rc.data(), T.box_rc.size() * 4, 0},
-        {T.box_lambda.data(), T.box_lambda.size() * 4, 0},
+        {T.tile_order.data(), T.tile_order.size() * 4, 0},
+        {fwd.data(), fwd.size() * 4, 0},
+        {adj.data(), adj.size() * 4, 0},
         {T.box_w.data(), T.box_w.size() * 4, 0},
         {T.box_wf.data(), T.box_wf.size() * 4, 0},
-        {T.lambda_box_ptr.data(), T.lambda_box_ptr.size() * 4, 0},
         {T.h.data(), T.h.size() * 4, 0},
-        {T.tile_order.data(), T.tile_order.size() * 4, 0},
-        {T.tile_item_ptr.data(), T.tile_item_ptr.size() * 4, 0},
-        {T.item_box.data(), T.item_box.size() * 4, 0},
     };
     size_t total = 0;
     for (auto &pt : parts) {
@@ -358,15 +399,12 @@ ctis_status upload_tables(ctis_plan *p) {
     }
     p->dev_mem = mem;
     auto at = [&](int k) { return (const void *)((const char *)mem + parts[(size_t)k].off); };
-    p->dt.box_rc = (const int32_t *)at(0);
-    p->dt.box_lambda = (const int32_t *)at(1);
-    p->dt.box_w = (const float *)at(2);
-    p->dt.box_wf = (const float *)at(3);
-    p->dt.lambda_box_ptr = (const int32_t *)at(4);
+    p->dt.unit_tile = (const int32_t *)at(0);
+    p->dt.fwd_items = (const int4 *)at(1);
+    p->dt.adj_items = (const int4 *)at(2);
+    p->dt.box_w = (const float *)at(3);
+    p->dt.box_wf = (const float *)at(4);
     p->dt.h = (const float *)at(5);
-    p->dt.tile_order = (const int32_t *)at(6);
-    p->dt.tile_item_ptr = (const int32_t *)at(7);
-    p->dt.item_box = (const int32_t *)at(8);
     return CTIS_OK;
 }
 

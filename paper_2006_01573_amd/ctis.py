@@ -26,7 +26,7 @@ STATUS_NAMES = {0: "CTIS_OK", 1: "CTIS_E_ARG", 2: "CTIS_E_INDEX", 3: "CTIS_E_VAL
 # every function include/ctis.h declares
 EXPORTED = ["ctis_plan_create", "ctis_plan_destroy", "ctis_plan_get_info",
             "ctis_plan_lambda_sums", "ctis_plan_export_boxes", "ctis_plan_export_worklist",
-            "ctis_forward", "ctis_adjoint", "ctis_em_iterate", "ctis_em_iterate_timed", "ctis_status_str",
+            "ctis_forward", "ctis_adjoint", "ctis_em_iterate", "ctis_em_forward_ratio", "ctis_em_adjoint_update", "ctis_status_str",
             "ctis_last_error", "ctis_version"]
 
 
@@ -115,9 +115,10 @@ def load_library(path: str | None = None):
         L.ctis_adjoint.restype = st
         L.ctis_em_iterate.argtypes = [vp, vp, vp, i32, vp, sz, vp]
         L.ctis_em_iterate.restype = st
-        L.ctis_em_iterate_timed.argtypes = [vp, vp, vp, i32, vp, sz, vp, ctypes.POINTER(ctypes.c_float),
-                                            ctypes.POINTER(ctypes.c_float)]
-        L.ctis_em_iterate_timed.restype = st
+        L.ctis_em_forward_ratio.argtypes = [vp, vp, vp, vp, vp]
+        L.ctis_em_forward_ratio.restype = st
+        L.ctis_em_adjoint_update.argtypes = [vp, vp, vp, vp, vp]
+        L.ctis_em_adjoint_update.restype = st
         L.ctis_status_str.argtypes = [st]
         L.ctis_status_str.restype = ctypes.c_char_p
         L.ctis_last_error.argtypes = []
@@ -284,20 +285,24 @@ class Plan:
         nbytes = self.info.workspace_bytes
         return torch.empty(max(nbytes // 4, 64), dtype=torch.float32, device=self.device)
 
-    def em_timed(self, g, iters: int, f, workspace):
-        """EM in place on ``f`` with per-kernel HIP-event timing; waits for the
-        work.  Returns (ms of all forward+ratio launches, ms of all
-        adjoint+update launches)."""
+    def em_forward_ratio(self, f, g, u):
+        """u = g / (H f) on the active FPA tiles (one EM half; see ctis.h)."""
         self._need_device()
         torch = _torch()
-        fw = ctypes.c_float()
-        ad = ctypes.c_float()
-        st = self._L.ctis_em_iterate_timed(self._handle, ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(f.data_ptr()),
-                                           int(iters), ctypes.c_void_p(workspace.data_ptr()),
-                                           workspace.numel() * workspace.element_size(), _stream(torch, self.device),
-                                           ctypes.byref(fw), ctypes.byref(ad))
-        _check(self._L, st, "ctis_em_iterate_timed")
-        return fw.value, ad.value
+        st = self._L.ctis_em_forward_ratio(self._handle, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(g.data_ptr()),
+                                           ctypes.c_void_p(u.data_ptr()), _stream(torch, self.device))
+        _check(self._L, st, "ctis_em_forward_ratio")
+        return u
+
+    def em_adjoint_update(self, u, f_in, f_out):
+        """f_out = f_in * (H^T u) / h (the other EM half)."""
+        self._need_device()
+        torch = _torch()
+        st = self._L.ctis_em_adjoint_update(self._handle, ctypes.c_void_p(u.data_ptr()),
+                                            ctypes.c_void_p(f_in.data_ptr()), ctypes.c_void_p(f_out.data_ptr()),
+                                            _stream(torch, self.device))
+        _check(self._L, st, "ctis_em_adjoint_update")
+        return f_out
 
     def em(self, g, iters: int, f0=None, f=None, workspace=None):
         """EM iterations.  Returns f after ``iters`` updates of f0 (default ones).

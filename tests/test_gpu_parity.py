@@ -261,3 +261,22 @@ def test_c3_sampled_projections(torch, ctis, oracle_mod):
     z_gpu = p.adjoint(torch.from_numpy(r).cuda()).cpu().numpy().ravel()
     cols = rng.choice(geo.m, 3000, replace=False)
     assert rel_l2(z_gpu[cols], ok.adjoint_cols(r, cols)) <= PROJ_TOL
+
+
+def test_em_halves_compose_to_em_iterate(torch, c1):
+    """ctis_em_forward_ratio + ctis_em_adjoint_update (out of place and in
+    place) reproduce ctis_em_iterate bit for bit."""
+    case, o, p, g = c1
+    gd = torch.from_numpy(g).cuda()
+    ref = p.em(gd, 3)
+    f = torch.ones(p.shape_f, device="cuda")
+    u = torch.empty(p.shape_g, device="cuda")
+    tmp = torch.empty_like(f)
+    for k in range(3):
+        p.em_forward_ratio(f, gd, u)
+        if k % 2 == 0:
+            p.em_adjoint_update(u, f, tmp)
+            f, tmp = tmp, f
+        else:
+            p.em_adjoint_update(u, f, f)
+    assert torch.equal(f, ref)
