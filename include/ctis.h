@@ -179,7 +179,8 @@ ctis_status ctis_adjoint(const ctis_plan *plan, const float *r, float *z_out, vo
  *   f          DEVICE float[m], in: start (the paper starts from all ones),
  *              out: f after `iters` updates; iters = 0 leaves f unchanged
  *   workspace  DEVICE, >= info.workspace_bytes, 256-byte aligned; its
- *              contents are scratch
+ *              contents are scratch (u, and the partial tiles of FPA tiles
+ *              whose boxes are split over several workgroups)
  * Errors: CTIS_E_NEGATIVE if a calibration value is negative, CTIS_E_WORKSPACE,
  * CTIS_E_ARG, CTIS_E_HIP.
  */
@@ -188,23 +189,24 @@ ctis_status ctis_em_iterate(const ctis_plan *plan, const float *g, float *f, int
 
 /*
  * The two fused kernels of one EM iteration, for callers that schedule the
- * iteration themselves (ctis_em_iterate is these two calls, iters times):
+ * iteration themselves.  ctis_em_iterate is `iters` pairs of these two calls
+ * on one workspace (>= info.workspace_bytes, 256-byte aligned).
  *
- *   ctis_em_forward_ratio:  u_i = g_i / (H f)_i, or 0 where (H f)_i <= 0, for
- *       every pixel of an FPA tile that meets the image of some calibration
- *       nonzero; the other pixels of u are not written (the back projection
- *       never reads them).
- *       f DEVICE float[m] (read), g DEVICE float[n] (read), u DEVICE float[n]
- *       (written as described).
+ *   ctis_em_forward_ratio:  u_i = g_i / (H f)_i, or 0 where (H f)_i <= 0, into
+ *       the first n floats of the workspace, for every pixel of an FPA tile
+ *       that meets the image of some calibration nonzero (the back projection
+ *       reads no other pixel).  f DEVICE float[m], g DEVICE float[n].
  *   ctis_em_adjoint_update: f_out_j = f_in_j * (H^T u)_j / h_j, or 0 where
- *       h_j == 0.  u as left by ctis_em_forward_ratio; f_out may equal f_in
- *       (in place) but must not overlap it otherwise.
- * Errors: CTIS_E_NEGATIVE if a calibration value is negative, CTIS_E_ARG.
+ *       h_j == 0, with u as left in the workspace by ctis_em_forward_ratio.
+ *       f_out may equal f_in (in place) but must not overlap it otherwise.
+ * Errors: CTIS_E_NEGATIVE if a calibration value is negative, CTIS_E_WORKSPACE,
+ * CTIS_E_ARG, CTIS_E_HIP.  Calls sharing one workspace must be ordered on one
+ * stream.
  */
-ctis_status ctis_em_forward_ratio(const ctis_plan *plan, const float *f, const float *g, float *u,
-                                  void *stream);
-ctis_status ctis_em_adjoint_update(const ctis_plan *plan, const float *u, const float *f_in, float *f_out,
-                                   void *stream);
+ctis_status ctis_em_forward_ratio(const ctis_plan *plan, const float *f, const float *g, void *workspace,
+                                  size_t workspace_bytes, void *stream);
+ctis_status ctis_em_adjoint_update(const ctis_plan *plan, const void *workspace, size_t workspace_bytes,
+                                   const float *f_in, float *f_out, void *stream);
 
 /* Static description of a status code. */
 const char *ctis_status_str(ctis_status status);

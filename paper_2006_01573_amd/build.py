@@ -39,7 +39,7 @@ def _compile(src: str) -> str:
     if src.endswith(".hip"):
         cmd = [hipcc(), "-x", "hip", *DEVICE, *COMMON, "-c", path, "-o", obj]
     else:
-        cmd = [hipcc(), "-D__HIP_PLATFORM_AMD__", *COMMON, "-c", path, "-o", obj]
+        cmd = [hipcc(), "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", *COMMON, "-c", path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -170,7 +170,7 @@ ctis_status ctis_plan_get_info(const ctis_plan *p, ctis_plan_info *info) {
     info->workspace_bytes = p->workspace_bytes;
     info->nonnegative = p->ht.nonneg ? 1 : 0;
     info->device = p->device;
-    info->waves_forward = p->waves_fwd;
+    info->waves_forward = p->ht.fwd_em.waves;
     info->waves_adjoint = p->waves_adj;
     return CTIS_OK;
 }
@@ -205,7 +205,7 @@ ctis_status ctis_forward(const ctis_plan *p, const float *f, float *g_out, void 
     if (overlaps(f, (size_t)p->m * 4, g_out, (size_t)p->n * 4)) return fail(CTIS_E_ARG, "f and g_out overlap");
     ctis_status st = check_device(p);
     if (st != CTIS_OK) return st;
-    return launch_status(launch_forward(p, f, nullptr, g_out, false, stream), "forward launch");
+    return launch_status(launch_forward(p, f, nullptr, g_out, false, nullptr, stream), "forward launch");
 }
 
 ctis_status ctis_adjoint(const ctis_plan *p, const float *r, float *z_out, void *stream) {
@@ -219,6 +219,13 @@ ctis_status ctis_adjoint(const ctis_plan *p, const float *r, float *z_out, void 
 }
 
 namespace {
+ctis_status workspace_check(const ctis_plan *p, const void *workspace, size_t workspace_bytes) {
+    if (!workspace || workspace_bytes < p->workspace_bytes)
+        return fail(CTIS_E_WORKSPACE, "workspace needs " + std::to_string(p->workspace_bytes) + " bytes");
+    if (((uintptr_t)workspace & 255u) != 0) return fail(CTIS_E_WORKSPACE, "workspace must be 256-byte aligned");
+    return CTIS_OK;
+}
+
 ctis_status em_check(const ctis_plan *p, const float *g, float *f, int32_t iters, void *workspace,
                      size_t workspace_bytes) {
     if (!p) return fail(CTIS_E_ARG, "plan is NULL");
@@ -226,9 +233,8 @@ ctis_status em_check(const ctis_plan *p, const float *g, float *f, int32_t iters
     if (iters < 0) return fail(CTIS_E_ARG, "iters must be >= 0");
     if (!aligned4(g) || !aligned4(f)) return fail(CTIS_E_ARG, "g and f must be 4-byte aligned");
     if (!p->ht.nonneg) return fail(CTIS_E_NEGATIVE, "the plan has a negative calibration value");
-    if (!workspace || workspace_bytes < p->workspace_bytes)
-        return fail(CTIS_E_WORKSPACE, "workspace needs " + std::to_string(p->workspace_bytes) + " bytes");
-    if (((uintptr_t)workspace & 255u) != 0) return fail(CTIS_E_WORKSPACE, "workspace must be 256-byte aligned");
+    ctis_status st = workspace_check(p, workspace, workspace_bytes);
+    if (st != CTIS_OK) return st;
     if (overlaps(g, (size_t)p->n * 4, f, (size_t)p->m * 4) ||
         overlaps(workspace, p->workspace_bytes, f, (size_t)p->m * 4) ||
         overlaps(workspace, p->workspace_bytes, g, (size_t)p->n * 4))
@@ -240,10 +246,10 @@ ctis_status em_check(const ctis_plan *p, const float *g, float *f, int32_t iters
 ctis_status ctis_em_iterate(const ctis_plan *p, const float *g, float *f, int32_t iters, void *workspace,
                             size_t workspace_bytes, void *stream) {
     ctis_status st = em_check(p, g, f, iters, workspace, workspace_bytes);
-    if (st != CTIS_OK) return st;
+    if (st != CTIS_OK || iters == 0) return st;
     float *u = (float *)workspace;
     for (int32_t k = 0; k < iters; ++k) {
-        st = launch_status(launch_forward(p, f, g, u, true, stream), "forward+ratio launch");
+        st = launch_status(launch_forward(p, f, g, u, true, workspace, stream), "forward+ratio launch");
         if (st != CTIS_OK) return st;
         st = launch_status(launch_adjoint(p, u, f, f, true, stream), "adjoint+update launch");
         if (st != CTIS_OK) return st;
@@ -251,31 +257,39 @@ ctis_status ctis_em_iterate(const ctis_plan *p, const float *g, float *f, int32_
     return CTIS_OK;
 }
 
-ctis_status ctis_em_forward_ratio(const ctis_plan *p, const float *f, const float *g, float *u, void *stream) {
+ctis_status ctis_em_forward_ratio(const ctis_plan *p, const float *f, const float *g, void *workspace,
+                                  size_t workspace_bytes, void *stream) {
     if (!p) return fail(CTIS_E_ARG, "plan is NULL");
-    if (!f || !g || !u) return fail(CTIS_E_ARG, "f, g or u is NULL");
-    if (!aligned4(f) || !aligned4(g) || !aligned4(u)) return fail(CTIS_E_ARG, "f, g and u must be 4-byte aligned");
+    if (!f || !g) return fail(CTIS_E_ARG, "f or g is NULL");
+    if (!aligned4(f) || !aligned4(g)) return fail(CTIS_E_ARG, "f and g must be 4-byte aligned");
     if (!p->ht.nonneg) return fail(CTIS_E_NEGATIVE, "the plan has a negative calibration value");
-    if (overlaps(u, (size_t)p->n * 4, f, (size_t)p->m * 4) || overlaps(u, (size_t)p->n * 4, g, (size_t)p->n * 4))
-        return fail(CTIS_E_ARG, "u must not overlap f or g");
-    ctis_status st = check_device(p);
+    ctis_status st = workspace_check(p, workspace, workspace_bytes);
     if (st != CTIS_OK) return st;
-    return launch_status(launch_forward(p, f, g, u, true, stream), "forward+ratio launch");
+    if (overlaps(workspace, p->workspace_bytes, f, (size_t)p->m * 4) ||
+        overlaps(workspace, p->workspace_bytes, g, (size_t)p->n * 4))
+        return fail(CTIS_E_ARG, "the workspace must not overlap f or g");
+    st = check_device(p);
+    if (st != CTIS_OK) return st;
+    return launch_status(launch_forward(p, f, g, (float *)workspace, true, workspace, stream),
+                         "forward+ratio launch");
 }
 
-ctis_status ctis_em_adjoint_update(const ctis_plan *p, const float *u, const float *f_in, float *f_out,
-                                   void *stream) {
+ctis_status ctis_em_adjoint_update(const ctis_plan *p, const void *workspace, size_t workspace_bytes,
+                                   const float *f_in, float *f_out, void *stream) {
     if (!p) return fail(CTIS_E_ARG, "plan is NULL");
-    if (!u || !f_in || !f_out) return fail(CTIS_E_ARG, "u, f_in or f_out is NULL");
-    if (!aligned4(u) || !aligned4(f_in) || !aligned4(f_out))
-        return fail(CTIS_E_ARG, "u, f_in and f_out must be 4-byte aligned");
+    if (!f_in || !f_out) return fail(CTIS_E_ARG, "f_in or f_out is NULL");
+    if (!aligned4(f_in) || !aligned4(f_out)) return fail(CTIS_E_ARG, "f_in and f_out must be 4-byte aligned");
     if (!p->ht.nonneg) return fail(CTIS_E_NEGATIVE, "the plan has a negative calibration value");
+    ctis_status st = workspace_check(p, workspace, workspace_bytes);
+    if (st != CTIS_OK) return st;
     const size_t mb = (size_t)p->m * 4;
     if (f_in != f_out && overlaps(f_in, mb, f_out, mb)) return fail(CTIS_E_ARG, "f_in and f_out overlap");
-    if (overlaps(u, (size_t)p->n * 4, f_out, mb)) return fail(CTIS_E_ARG, "u and f_out overlap");
-    ctis_status st = check_device(p);
+    if (overlaps(workspace, p->workspace_bytes, f_out, mb))
+        return fail(CTIS_E_ARG, "the workspace and f_out overlap");
+    st = check_device(p);
     if (st != CTIS_OK) return st;
-    return launch_status(launch_adjoint(p, u, f_in, f_out, true, stream), "adjoint+update launch");
+    return launch_status(launch_adjoint(p, (const float *)workspace, f_in, f_out, true, stream),
+                         "adjoint+update launch");
 }
 
 }  // extern "C"

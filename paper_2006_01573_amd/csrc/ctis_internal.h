@@ -24,14 +24,22 @@ constexpr int kMaxBox = 8;
 // 32-bit buffer offsets (in bytes) address the FPA and one wavelength block
 constexpr int64_t kMaxPixels = (int64_t(1) << 29) - 1;
 
+// One forward launch: a list of work units, one workgroup each.  A unit is a
+// chunk of the boxes that meet one FPA tile; a tile with more boxes than the
+// chunk size is split over several units, whose partial tiles a second,
+// small kernel sums.
+struct FwdList {
+    const int4 *unit_meta;   // n_units: (tile, chunk, n_chunks, partial slot of chunk 0)
+    const int4 *items;       // n_units * stride records (X, Y, s, box), X, Y = window
+                             //   origin (r0 - (B-1) - rA, c0 - (B-1) - cA); box = -1 ends
+    int32_t n_units = 0, stride = 1, waves = 4;
+};
+
 // Device-side tables of a plan (one allocation, pointers into it).
-// Work records are int4 (X, Y, s, box); box = -1 ends a list.
 struct DevTables {
-    const int32_t *unit_tile;   // n_tiles: FPA tile of each forward workgroup (active
-                                //   tiles, heaviest first, then the empty ones)
-    const int4 *fwd_items;      // n_tiles * fwd_stride: per workgroup, its (tile, box)
-                                //   items with X, Y = the window origin
-                                //   (r0 - (B-1) - rA, c0 - (B-1) - cA)
+    FwdList fwd_full;           // every FPA tile, one unit each (plain projection)
+    FwdList fwd_em;             // FPA tiles with boxes, heavy tiles split (EM)
+    const int4 *split_meta;     // n_split_tiles: (tile, n_chunks, partial slot of chunk 0, 0)
     const int4 *adj_items;      // w * adj_stride: per wavelength, its boxes with
                                 //   X, Y = the anchor (rA, cA)
     const float *box_w;         // nb*B*B, [dc*B + dr]
@@ -45,8 +53,12 @@ struct KParams {
     int32_t ell, n;
     int32_t ntr;        // FPA tiles along the fast axis
     int32_t nbx, nby;   // field-stop tiles along x and y
-    int32_t fwd_stride; // records per forward workgroup (max boxes on one FPA tile)
     int32_t adj_stride; // records per wavelength (max boxes of one wavelength)
+};
+
+struct HostList {
+    std::vector<int32_t> unit_meta, items;   // int4 records, flattened
+    int32_t n_units = 0, stride = 1, waves = 4;
 };
 
 struct HostTables {
@@ -58,6 +70,11 @@ struct HostTables {
     int32_t nbx = 0, nby = 0;
     int64_t nnz = 0, n_support = 0;
     bool nonneg = true;
+    HostList fwd_full, fwd_em;
+    int32_t chunk = 64;          // max boxes per forward unit in EM
+    int32_t partial_slots = 0;   // 64x16 partial tiles of split FPA tiles
+    int32_t n_split_tiles = 0;
+    std::vector<int32_t> split_meta;
 };
 
 }  // namespace ctis
@@ -70,9 +87,9 @@ struct ctis_plan {
     void *dev_mem = nullptr;    // one allocation holding every table
     ctis::DevTables dt{};
     ctis::KParams kp{};
-    int32_t waves_fwd = 4;
     int32_t waves_adj = 4;
     size_t workspace_bytes = 0;
+    size_t ws_partials = 0;      // byte offset of the partial tiles in the EM workspace
 };
 
 namespace ctis {
@@ -89,7 +106,7 @@ ctis_status upload_tables(ctis_plan *p);
 int max_waves(int box);
 int min_waves();
 int launch_forward(const ctis_plan *p, const float *f, const float *g, float *out, bool em_ratio,
-                   void *stream);
+                   void *workspace, void *stream);
 int launch_adjoint(const ctis_plan *p, const float *u, const float *fin, float *out, bool em_update,
                    void *stream);
 

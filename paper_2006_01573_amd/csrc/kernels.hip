@@ -7,9 +7,8 @@
 // nonzeros.  A wavefront owns a 64 x 16 output tile (fast x slow axis) with a
 // 4 x 4 register micro-tile per lane, stages the (64+B-1) x (16+B-1) input
 // window of one box into its own LDS region, and correlates it with the box's
-// values, which are wave-uniform and arrive through scalar loads.  Each wave
-// keeps the next box's window in flight in registers while it computes the
-// current one.  The waves of a workgroup split the boxes of one tile and meet
+// values.  Each wave keeps the next two boxes' windows in flight in
+// registers while it computes the current one.  The waves of a workgroup split the boxes of one tile and meet
 // in an LDS reduction in a fixed order (deterministic results); the reduced
 // tile leaves row by row, so every epilogue load and store is a contiguous
 // 256-byte wavefront access.
@@ -54,7 +53,7 @@ struct Win {
     static constexpr int E = B - 1;                // window columns beyond the 64 lanes
     static constexpr int NXT = (E * SY + 63) / 64; // extra slots per lane
     static constexpr int WREG = REG + 64;          // region incl. the box values (<= 64)
-    static constexpr int MAXW = B <= 6 ? 16 : 8;   // waves per workgroup (VGPR budget)
+    static constexpr int MAXW = B <= 5 ? 16 : 8;   // waves per workgroup (VGPR budget)
     static_assert(REG >= TX * TY, "the reduction reuses 1024 floats per wave");
     static_assert(REG % 4 == 0 && B * B <= 64, "box values sit 16-byte aligned after the window");
     static_assert(4 * (TX / 4 - 1) + 4 * NV <= SXP, "segment reads stay inside the row");
@@ -100,25 +99,10 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const float *base, int nf
     return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, nfloats * 4, kRsrcWord3);
 }
 
-// raw 32-bit buffer load, reinterpreted as float (the builtin returns the bits)
-__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, unsigned off) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
-}
-
-// 1-D FPA address (Xs + col) + gamma*(Ys + row) mod n, for row = 0:
-// xm = (Xs + col) mod gamma, y = (Ys + (Xs + col) div gamma) mod xi.
-// Xs, Ys are wave-uniform (scalar divisions), col is per lane.
-__device__ __forceinline__ void decode(const KParams &p, int Xs, int Ys, int col, int &xm, int &y) {
-    int q0, r0;
-    floor_divmod(Xs, p.gamma, q0, r0);
-    int yq, y0;
-    floor_divmod(Ys + q0, p.xi, yq, y0);
-    xm = r0 + col;
-    y = y0;
-    while (xm >= p.gamma) {
-        xm -= p.gamma;
-        y = step_mod(y, p.xi);
-    }
+// raw 32-bit buffer load, reinterpreted as float (the builtin returns the
+// bits); byte offset = voff (per lane) + soff (wave-uniform)
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff = 0) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }
 
 template <int B>
@@ -129,15 +113,56 @@ __device__ __forceinline__ void load_values(Pending<B> &pd, const float *__restr
 
 // Forward window of one (tile, box) item, rec = (Xs, Ys, s, box):
 // slot (xx, yy) <- fE((Xs + xx) + gamma*(Ys + yy) mod n).
+// Interior windows (no window row crosses the end of an FPA column, so the
+// slow-axis index of a row is the same for every lane) take the row offset
+// as the buffer's scalar offset; other windows decode every slot.
 template <int B>
 __device__ __forceinline__ void load_forward(Pending<B> &pd, const float *f, const float *__restrict__ wtab,
                                              const KParams &p, int4 rec, int lane) {
     using Wn = Win<B>;
     const __amdgpu_buffer_rsrc_t fr = rsrc(f + (size_t)rec.z * p.ell, p.ell);
     const int Xs = rec.x, Ys = rec.y;
-    {
-        int xm, y;
-        decode(p, Xs, Ys, lane, xm, y);
+    int q0, xr, yq, y0;
+    floor_divmod(Xs, p.gamma, q0, xr);
+    floor_divmod(Ys + q0, p.xi, yq, y0);
+    if (xr + Wn::SX <= p.gamma) {
+        const int xm = xr + lane;
+        const unsigned lane_off = xm < p.a ? (unsigned)xm * 4u : kOutOfRange;
+        const unsigned row_step = (unsigned)p.a * 4u;
+        int y = y0;
+        unsigned row_off = (unsigned)(p.a * y0) * 4u;
+#pragma unroll
+        for (int yy = 0; yy < Wn::SY; ++yy) {
+            // rows outside the field stop: every lane out of range (and a
+            // scalar offset of 0, so no address leaves the block)
+            const bool row_ok = y < p.alpha;
+            pd.v[yy] = bload(fr, row_ok ? lane_off : kOutOfRange, row_ok ? row_off : 0u);
+            ++y;
+            row_off += row_step;
+            if (y == p.xi) {
+                y = 0;
+                row_off = 0;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < Wn::NXT; ++t) {
+            const int k = lane + 64 * t;
+            unsigned off = kOutOfRange;
+            if (k < Wn::E * Wn::SY) {
+                const int e = k % Wn::E, yy = k / Wn::E;
+                const int xe = xr + TX + e;
+                int ye = y0 + yy;
+                while (ye >= p.xi) ye -= p.xi;
+                if (xe < p.a && ye < p.alpha) off = (unsigned)(xe + p.a * ye) * 4u;
+            }
+            pd.x[t] = bload(fr, off);
+        }
+    } else {
+        int xm = xr + lane, y = y0;
+        while (xm >= p.gamma) {
+            xm -= p.gamma;
+            y = step_mod(y, p.xi);
+        }
         const bool vx = xm < p.a;
 #pragma unroll
         for (int yy = 0; yy < Wn::SY; ++yy) {
@@ -145,20 +170,23 @@ __device__ __forceinline__ void load_forward(Pending<B> &pd, const float *f, con
             pd.v[yy] = bload(fr, ok ? (unsigned)(xm + p.a * y) * 4u : kOutOfRange);
             y = step_mod(y, p.xi);
         }
-    }
 #pragma unroll
-    for (int t = 0; t < Wn::NXT; ++t) {
-        const int k = lane + 64 * t;
-        unsigned off = kOutOfRange;
-        if (k < Wn::E * Wn::SY) {
-            const int e = k % Wn::E, yy = k / Wn::E;
-            int xm, y;
-            decode(p, Xs, Ys, TX + e, xm, y);
-            y += yy;
-            while (y >= p.xi) y -= p.xi;
-            if (xm < p.a && y < p.alpha) off = (unsigned)(xm + p.a * y) * 4u;
+        for (int t = 0; t < Wn::NXT; ++t) {
+            const int k = lane + 64 * t;
+            unsigned off = kOutOfRange;
+            if (k < Wn::E * Wn::SY) {
+                const int e = k % Wn::E, yy = k / Wn::E;
+                int xe = xr + TX + e, ye = y0;
+                while (xe >= p.gamma) {
+                    xe -= p.gamma;
+                    ye = step_mod(ye, p.xi);
+                }
+                ye += yy;
+                while (ye >= p.xi) ye -= p.xi;
+                if (xe < p.a && ye < p.alpha) off = (unsigned)(xe + p.a * ye) * 4u;
+            }
+            pd.x[t] = bload(fr, off);
         }
-        pd.x[t] = bload(fr, off);
     }
     load_values<B>(pd, wtab, rec.w, lane);
 }
@@ -168,33 +196,70 @@ __device__ __forceinline__ void load_forward(Pending<B> &pd, const float *f, con
 // (xx >= a + B - 1 - x0 or yy >= alpha + B - 1 - y0) only ever meet output
 // voxels outside the field stop, which are never written, so they need no
 // masking; their addresses are still reduced mod n and stay in bounds.
+// Interior windows take the row offset as the buffer's scalar offset.
 template <int B>
 __device__ __forceinline__ void load_adjoint(Pending<B> &pd, __amdgpu_buffer_rsrc_t ur,
                                              const float *__restrict__ wtab, const KParams &p, int Xs, int Ys,
                                              int box, int lane) {
     using Wn = Win<B>;
-    {
-        int xm, y;
-        decode(p, Xs, Ys, lane, xm, y);
+    int q0, xr, yq, y0;
+    floor_divmod(Xs, p.gamma, q0, xr);
+    floor_divmod(Ys + q0, p.xi, yq, y0);
+    if (xr + Wn::SX <= p.gamma) {
+        const unsigned lane_off = (unsigned)(xr + lane) * 4u;
+        const unsigned row_step = (unsigned)p.gamma * 4u;
+        int y = y0;
+        unsigned row_off = (unsigned)(p.gamma * y0) * 4u;
+#pragma unroll
+        for (int yy = 0; yy < Wn::SY; ++yy) {
+            pd.v[yy] = bload(ur, lane_off, row_off);
+            ++y;
+            row_off += row_step;
+            if (y == p.xi) {
+                y = 0;
+                row_off = 0;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < Wn::NXT; ++t) {
+            const int k = lane + 64 * t;
+            unsigned off = kOutOfRange;
+            if (k < Wn::E * Wn::SY) {
+                const int e = k % Wn::E, yy = k / Wn::E;
+                int ye = y0 + yy;
+                while (ye >= p.xi) ye -= p.xi;
+                off = (unsigned)(xr + TX + e + p.gamma * ye) * 4u;
+            }
+            pd.x[t] = bload(ur, off);
+        }
+    } else {
+        int xm = xr + lane, y = y0;
+        while (xm >= p.gamma) {
+            xm -= p.gamma;
+            y = step_mod(y, p.xi);
+        }
 #pragma unroll
         for (int yy = 0; yy < Wn::SY; ++yy) {
             pd.v[yy] = bload(ur, (unsigned)(xm + p.gamma * y) * 4u);
             y = step_mod(y, p.xi);
         }
-    }
 #pragma unroll
-    for (int t = 0; t < Wn::NXT; ++t) {
-        const int k = lane + 64 * t;
-        unsigned off = kOutOfRange;
-        if (k < Wn::E * Wn::SY) {
-            const int e = k % Wn::E, yy = k / Wn::E;
-            int xm, y;
-            decode(p, Xs, Ys, TX + e, xm, y);
-            y += yy;
-            while (y >= p.xi) y -= p.xi;
-            off = (unsigned)(xm + p.gamma * y) * 4u;
+        for (int t = 0; t < Wn::NXT; ++t) {
+            const int k = lane + 64 * t;
+            unsigned off = kOutOfRange;
+            if (k < Wn::E * Wn::SY) {
+                const int e = k % Wn::E, yy = k / Wn::E;
+                int xe = xr + TX + e, ye = y0;
+                while (xe >= p.gamma) {
+                    xe -= p.gamma;
+                    ye = step_mod(ye, p.xi);
+                }
+                ye += yy;
+                while (ye >= p.xi) ye -= p.xi;
+                off = (unsigned)(xe + p.gamma * ye) * 4u;
+            }
+            pd.x[t] = bload(ur, off);
         }
-        pd.x[t] = bload(ur, off);
     }
     load_values<B>(pd, wtab, box, lane);
 }
@@ -267,33 +332,38 @@ __device__ __forceinline__ float row_sum(const float *lds, int nw, int row, int 
     _Pragma("unroll") for (int j = 0; j < kRowsPerWave; ++j)  \
         if (const int row = wv + j * nw; row < TY)
 
+// Forward projection of one work unit (a chunk of the boxes meeting one FPA
+// tile).  A tile split into several units writes one partial tile per unit
+// to `partials`; k_finish_split then sums them (next launch on the stream).
 template <int B>
-__global__ void __launch_bounds__(64 * Win<B>::MAXW) k_forward(const KParams p, const int32_t *__restrict__ unit_tile,
-                                                  const int4 *__restrict__ items, const float *__restrict__ box_wf,
-                                                  const float *__restrict__ f, const float *__restrict__ g,
-                                                  float *__restrict__ out, int em) {
+__global__ void __launch_bounds__(64 * Win<B>::MAXW) k_forward(const KParams p, const int4 *__restrict__ unit_meta,
+                                                               const int4 *__restrict__ items, const int stride,
+                                                               const float *__restrict__ box_wf,
+                                                               const float *__restrict__ f,
+                                                               const float *__restrict__ g, float *__restrict__ out,
+                                                               int em, float *__restrict__ partials) {
     using Wn = Win<B>;
     extern __shared__ float4 lds4[];
     float *lds = reinterpret_cast<float *>(lds4);
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nw = blockDim.x >> 6;
-    const int stride = p.fwd_stride;
     const int4 *list = items + (size_t)blockIdx.x * stride;
     int k = wv;
     int4 rec0 = record(list, k, stride);
     int4 rec1 = record(list, k + nw, stride);
-    const int tile = unit_tile[blockIdx.x];
-    const int r0 = (tile % p.ntr) * TX, c0 = (tile / p.ntr) * TY;
+    const int4 um = unit_meta[blockIdx.x];   // (tile, chunk, n_chunks, partial slot of chunk 0)
+    const int r0 = (um.x % p.ntr) * TX, c0 = (um.x / p.ntr) * TY;
     float *S = lds + wv * Wn::WREG;
     const int lx = lane & 15, ly = lane >> 4;
     const int r = r0 + lane;
+    const bool whole = um.z == 1;
 
     // operands of the epilogue, fetched up front
     float gpre[kRowsPerWave];
     FOR_OWN_ROWS(j, row) {
         const int c = c0 + row;
-        gpre[j] = (em && r < p.gamma && c < p.xi) ? g[(size_t)r + (size_t)p.gamma * c] : 0.0f;
+        gpre[j] = (em && whole && r < p.gamma && c < p.xi) ? g[(size_t)r + (size_t)p.gamma * c] : 0.0f;
     }
 
     float acc[4][4];
@@ -302,21 +372,42 @@ __global__ void __launch_bounds__(64 * Win<B>::MAXW) k_forward(const KParams p, 
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[a][q] = 0.0f;
 
-    Pending<B> pd;
-    if (rec0.w >= 0) load_forward<B>(pd, f, box_wf, p, rec0, lane);
+    // two windows in flight: pa holds item k, pb item k + nw; while item k is
+    // computed, item k + 2nw is fetched into the buffer item k came from
+    int4 rec2 = record(list, k + 2 * nw, stride);
+    Pending<B> pa, pb;
+    if (rec0.w >= 0) load_forward<B>(pa, f, box_wf, p, rec0, lane);
+    if (rec1.w >= 0) load_forward<B>(pb, f, box_wf, p, rec1, lane);
     while (rec0.w >= 0) {
-        store_window<B>(S, pd, lane);
+        store_window<B>(S, pa, lane);
         wave_lds_sync();
-        k += nw;
-        const int4 rec2 = record(list, k + nw, stride);
-        if (rec1.w >= 0) load_forward<B>(pd, f, box_wf, p, rec1, lane);
+        int4 rec3 = record(list, k + 3 * nw, stride);
+        if (rec2.w >= 0) load_forward<B>(pa, f, box_wf, p, rec2, lane);
         correlate<B>(acc, S, lx, ly);
         wave_lds_sync();
+        k += nw;
         rec0 = rec1;
         rec1 = rec2;
+        rec2 = rec3;
+        if (rec0.w < 0) break;
+        store_window<B>(S, pb, lane);
+        wave_lds_sync();
+        rec3 = record(list, k + 3 * nw, stride);
+        if (rec2.w >= 0) load_forward<B>(pb, f, box_wf, p, rec2, lane);
+        correlate<B>(acc, S, lx, ly);
+        wave_lds_sync();
+        k += nw;
+        rec0 = rec1;
+        rec1 = rec2;
+        rec2 = rec3;
     }
 
     park_tile(acc, lds, wv, lx, ly);
+    if (!whole) {
+        float *mine = partials + ((size_t)um.w + um.y) * (TX * TY);
+        FOR_OWN_ROWS(j, row) mine[row * TX + lane] = row_sum(lds, nw, row, lane);
+        return;
+    }
     FOR_OWN_ROWS(j, row) {
         const int c = c0 + row;
         float v = row_sum(lds, nw, row, lane);
@@ -324,6 +415,30 @@ __global__ void __launch_bounds__(64 * Win<B>::MAXW) k_forward(const KParams p, 
             if (em) v = v > 0.0f ? gpre[j] / v : 0.0f;
             out[(size_t)r + (size_t)p.gamma * c] = v;
         }
+    }
+}
+
+// Sum the partial tiles of every split FPA tile in chunk order and apply the
+// forward epilogue.  One workgroup (4 waves, 4 rows each) per split tile;
+// split_meta[t] = (tile, n_chunks, partial slot of chunk 0, 0).
+__global__ void __launch_bounds__(256) k_finish_split(const KParams p, const int4 *__restrict__ split_meta,
+                                                      const float *__restrict__ partials,
+                                                      const float *__restrict__ g, float *__restrict__ out,
+                                                      int em) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int4 sm = split_meta[blockIdx.x];
+    const int r0 = (sm.x % p.ntr) * TX, c0 = (sm.x / p.ntr) * TY;
+    const int r = r0 + lane;
+#pragma unroll
+    for (int j = 0; j < TY / 4; ++j) {
+        const int row = wv + 4 * j, c = c0 + row;
+        if (r >= p.gamma || c >= p.xi) continue;
+        const size_t i = (size_t)r + (size_t)p.gamma * c;
+        const float gv = em ? g[i] : 0.0f;
+        float v = 0.0f;
+        for (int ch = 0; ch < sm.y; ++ch) v += partials[((size_t)sm.z + ch) * (TX * TY) + row * TX + lane];
+        if (em) v = v > 0.0f ? gv / v : 0.0f;
+        out[i] = v;
     }
 }
 
@@ -364,18 +479,32 @@ __global__ void __launch_bounds__(64 * Win<B>::MAXW) k_adjoint(const KParams p, 
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[a][q] = 0.0f;
 
-    Pending<B> pd;
-    if (rec0.w >= 0) load_adjoint<B>(pd, ur, box_w, p, rec0.x + x0, rec0.y + y0, rec0.w, lane);
+    int4 rec2 = record(list, k + 2 * nw, stride);
+    Pending<B> pa, pb;
+    if (rec0.w >= 0) load_adjoint<B>(pa, ur, box_w, p, rec0.x + x0, rec0.y + y0, rec0.w, lane);
+    if (rec1.w >= 0) load_adjoint<B>(pb, ur, box_w, p, rec1.x + x0, rec1.y + y0, rec1.w, lane);
     while (rec0.w >= 0) {
-        store_window<B>(S, pd, lane);
+        store_window<B>(S, pa, lane);
         wave_lds_sync();
-        k += nw;
-        const int4 rec2 = record(list, k + nw, stride);
-        if (rec1.w >= 0) load_adjoint<B>(pd, ur, box_w, p, rec1.x + x0, rec1.y + y0, rec1.w, lane);
+        int4 rec3 = record(list, k + 3 * nw, stride);
+        if (rec2.w >= 0) load_adjoint<B>(pa, ur, box_w, p, rec2.x + x0, rec2.y + y0, rec2.w, lane);
         correlate<B>(acc, S, lx, ly);
         wave_lds_sync();
+        k += nw;
         rec0 = rec1;
         rec1 = rec2;
+        rec2 = rec3;
+        if (rec0.w < 0) break;
+        store_window<B>(S, pb, lane);
+        wave_lds_sync();
+        rec3 = record(list, k + 3 * nw, stride);
+        if (rec2.w >= 0) load_adjoint<B>(pb, ur, box_w, p, rec2.x + x0, rec2.y + y0, rec2.w, lane);
+        correlate<B>(acc, S, lx, ly);
+        wave_lds_sync();
+        k += nw;
+        rec0 = rec1;
+        rec1 = rec2;
+        rec2 = rec3;
     }
 
     park_tile(acc, lds, wv, lx, ly);
@@ -403,18 +532,25 @@ int enable_large_lds() {
 }
 
 template <int B>
-int forward_B(const ctis_plan *pl, const float *f, const float *g, float *out, bool em, hipStream_t st) {
-    const int nwg = em ? pl->ht.n_active : pl->ht.n_tiles;
-    if (nwg == 0) return 0;
-    const int nw = pl->waves_fwd;
-    const size_t lds = (size_t)nw * Win<B>::WREG * sizeof(float);
+int forward_B(const ctis_plan *pl, const float *f, const float *g, float *out, bool em, void *workspace,
+              hipStream_t st) {
+    const FwdList &L = em ? pl->dt.fwd_em : pl->dt.fwd_full;
+    if (L.n_units == 0) return 0;
+    const size_t lds = (size_t)L.waves * Win<B>::WREG * sizeof(float);
     if (lds > 65536) {
         const int e = enable_large_lds<B>();
         if (e) return e;
     }
-    const DevTables &t = pl->dt;
-    hipLaunchKernelGGL(k_forward<B>, dim3(nwg), dim3(64 * nw), lds, st, pl->kp, t.unit_tile, t.fwd_items, t.box_wf,
-                       f, g, out, em ? 1 : 0);
+    float *partials = nullptr;
+    if (em && pl->ht.partial_slots > 0) partials = (float *)((char *)workspace + pl->ws_partials);
+    hipLaunchKernelGGL(k_forward<B>, dim3(L.n_units), dim3(64 * L.waves), lds, st, pl->kp, L.unit_meta, L.items,
+                       L.stride, pl->dt.box_wf, f, g, out, em ? 1 : 0, partials);
+    if (partials) {
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return (int)e;
+        hipLaunchKernelGGL(k_finish_split, dim3(pl->ht.n_split_tiles), dim3(256), 0, st, pl->kp, pl->dt.split_meta,
+                           (const float *)partials, g, out, 1);
+    }
     return (int)hipGetLastError();
 }
 
@@ -435,20 +571,21 @@ int adjoint_B(const ctis_plan *pl, const float *u, const float *fin, float *out,
 
 }  // namespace
 
-int max_waves(int B) { return B <= 6 ? Win<1>::MAXW : Win<8>::MAXW; }
+int max_waves(int B) { return B <= 5 ? Win<1>::MAXW : Win<8>::MAXW; }
 int min_waves() { return kMinWaves; }
 
-int launch_forward(const ctis_plan *p, const float *f, const float *g, float *out, bool em, void *stream) {
+int launch_forward(const ctis_plan *p, const float *f, const float *g, float *out, bool em, void *workspace,
+                   void *stream) {
     hipStream_t st = (hipStream_t)stream;
     switch (p->ht.B) {
-        case 1: return forward_B<1>(p, f, g, out, em, st);
-        case 2: return forward_B<2>(p, f, g, out, em, st);
-        case 3: return forward_B<3>(p, f, g, out, em, st);
-        case 4: return forward_B<4>(p, f, g, out, em, st);
-        case 5: return forward_B<5>(p, f, g, out, em, st);
-        case 6: return forward_B<6>(p, f, g, out, em, st);
-        case 7: return forward_B<7>(p, f, g, out, em, st);
-        case 8: return forward_B<8>(p, f, g, out, em, st);
+        case 1: return forward_B<1>(p, f, g, out, em, workspace, st);
+        case 2: return forward_B<2>(p, f, g, out, em, workspace, st);
+        case 3: return forward_B<3>(p, f, g, out, em, workspace, st);
+        case 4: return forward_B<4>(p, f, g, out, em, workspace, st);
+        case 5: return forward_B<5>(p, f, g, out, em, workspace, st);
+        case 6: return forward_B<6>(p, f, g, out, em, workspace, st);
+        case 7: return forward_B<7>(p, f, g, out, em, workspace, st);
+        case 8: return forward_B<8>(p, f, g, out, em, workspace, st);
     }
     return (int)hipErrorInvalidValue;
 }

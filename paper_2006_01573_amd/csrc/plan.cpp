@@ -311,20 +311,72 @@ ctis_status build_host_tables(ctis_plan *p, const int64_t *lambda_ptr, const int
     k.ntr = T.ntr;
     k.nbx = T.nbx;
     k.nby = T.nby;
-    p->workspace_bytes = ((size_t)n * sizeof(float) + 255) & ~(size_t)255;
     int32_t max_boxes = 0, max_items = 0;
+    int64_t active_items = 0;
     for (int32_t s = 0; s < w; ++s)
         max_boxes = std::max(max_boxes, T.lambda_box_ptr[(size_t)s + 1] - T.lambda_box_ptr[(size_t)s]);
-    for (int32_t t = 0; t < T.n_tiles; ++t) max_items = std::max(max_items, count(t));
-    // one wavefront per two boxes of the heaviest tile: each wave then has a
+    for (int32_t t = 0; t < T.n_tiles; ++t) {
+        max_items = std::max(max_items, count(t));
+        active_items += count(t);
+    }
+    // one wavefront per two boxes of the heaviest unit: each wave then has a
     // second window in flight while it computes the first
     auto waves_for = [&](int32_t work) { return std::max(min_waves(), std::min(max_waves(B), (work + 1) / 2)); };
-    p->waves_fwd = waves_for(max_items);
+    // EM chunk: a tile is split over several workgroups only when it holds
+    // more than 64 boxes (4 per wave) and more than twice the boxes an
+    // average compute unit gets (256 CUs); otherwise splitting only adds the
+    // partial-tile pass
+    T.chunk = (int32_t)std::max<int64_t>(64, 2 * ((active_items + 255) / 256));
+    auto build_list = [&](HostList &L, int32_t n_tiles_in_list, int32_t chunk, int32_t &slots) -> ctis_status {
+        L.stride = std::max(1, chunk);
+        L.unit_meta.clear();
+        L.items.clear();
+        for (int32_t u = 0; u < n_tiles_in_list; ++u) {
+            const int32_t tile = T.tile_order[(size_t)u];
+            const int32_t cnt = count(tile), b0 = T.tile_item_ptr[(size_t)tile];
+            const int32_t nch = std::max(1, (cnt + L.stride - 1) / L.stride);
+            const int32_t pbase = nch > 1 ? slots : -1;
+            if (nch > 1) {
+                if (&slots == &T.partial_slots) T.split_meta.insert(T.split_meta.end(), {tile, nch, pbase, 0});
+                slots += nch;
+            }
+            const int32_t r0 = (tile % T.ntr) * kTileFast, c0 = (tile / T.ntr) * kTileSlow;
+            for (int32_t c = 0; c < nch; ++c) {
+                L.unit_meta.insert(L.unit_meta.end(), {tile, c, nch, pbase});
+                for (int32_t k = 0; k < L.stride; ++k) {
+                    const int32_t idx = c * L.stride + k;
+                    if (idx < cnt) {
+                        const int32_t b = T.item_box[(size_t)(b0 + idx)];
+                        L.items.insert(L.items.end(), {r0 - (B - 1) - T.box_rc[2 * (size_t)b],
+                                                       c0 - (B - 1) - T.box_rc[2 * (size_t)b + 1],
+                                                       T.box_lambda[(size_t)b], b});
+                    } else {
+                        L.items.insert(L.items.end(), {0, 0, 0, -1});
+                    }
+                }
+            }
+            if (L.items.size() > (size_t)INT32_MAX) return fail(CTIS_E_TOO_LARGE, "forward work list too large");
+        }
+        L.n_units = (int32_t)(L.unit_meta.size() / 4);
+        return CTIS_OK;
+    };
+    int32_t unused = 0;
+    T.partial_slots = 0;
+    T.split_meta.clear();
+    ctis_status st = build_list(T.fwd_full, T.n_tiles, std::max(1, max_items), unused);
+    if (st != CTIS_OK) return st;
+    st = build_list(T.fwd_em, T.n_active, T.chunk, T.partial_slots);
+    if (st != CTIS_OK) return st;
+    T.n_split_tiles = (int32_t)(T.split_meta.size() / 4);
+    T.fwd_full.waves = waves_for(max_items);
+    T.fwd_em.waves = waves_for(std::min(max_items, T.chunk));
     p->waves_adj = waves_for(max_boxes);
-    if ((int64_t)max_items * T.n_tiles > INT32_MAX / 4 || (int64_t)max_boxes * w > INT32_MAX / 4)
-        return fail(CTIS_E_TOO_LARGE, "work tables too large");
-    k.fwd_stride = std::max(1, max_items);
+    if ((int64_t)max_boxes * w > INT32_MAX / 4) return fail(CTIS_E_TOO_LARGE, "work tables too large");
     k.adj_stride = std::max(1, max_boxes);
+    // EM workspace: u (n floats), then the partial tiles of split FPA tiles
+    auto up256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    p->ws_partials = up256((size_t)n * sizeof(float));
+    p->workspace_bytes = p->ws_partials + (size_t)T.partial_slots * kTileFast * kTileSlow * sizeof(float);
     return CTIS_OK;
 }
 
@@ -335,27 +387,7 @@ ctis_status upload_tables(ctis_plan *p) {
         size_t bytes;
         size_t off;
     };
-    const int B = T.B;
-    const int32_t fs = p->kp.fwd_stride, as = p->kp.adj_stride;
-    // forward: one list per workgroup, in launch order
-    std::vector<int32_t> fwd((size_t)4 * T.n_tiles * fs, 0);
-    for (int32_t u = 0; u < T.n_tiles; ++u) {
-        const int32_t tile = T.tile_order[(size_t)u];
-        const int32_t r0 = (tile % T.ntr) * kTileFast, c0 = (tile / T.ntr) * kTileSlow;
-        const int32_t b0 = T.tile_item_ptr[(size_t)tile], b1 = T.tile_item_ptr[(size_t)tile + 1];
-        for (int32_t k = 0; k < fs; ++k) {
-            int32_t *rec = &fwd[(size_t)4 * ((size_t)u * fs + k)];
-            if (b0 + k < b1) {
-                const int32_t b = T.item_box[(size_t)(b0 + k)];
-                rec[0] = r0 - (B - 1) - T.box_rc[2 * (size_t)b];
-                rec[1] = c0 - (B - 1) - T.box_rc[2 * (size_t)b + 1];
-                rec[2] = T.box_lambda[(size_t)b];
-                rec[3] = b;
-            } else {
-                rec[3] = -1;
-            }
-        }
-    }
+    const int32_t as = p->kp.adj_stride;
     // adjoint: one list per wavelength
     std::vector<int32_t> adj((size_t)4 * p->w * as, 0);
     for (int32_t s = 0; s < p->w; ++s) {
@@ -374,9 +406,12 @@ ctis_status upload_tables(ctis_plan *p) {
         }
     }
     std::vector<Part> parts = {
-        {T.tile_order.data(), T.tile_order.size() * 4, 0},
-        {fwd.data(), fwd.size() * 4, 0},
+        {T.fwd_full.unit_meta.data(), T.fwd_full.unit_meta.size() * 4, 0},
+        {T.fwd_full.items.data(), T.fwd_full.items.size() * 4, 0},
+        {T.fwd_em.unit_meta.data(), T.fwd_em.unit_meta.size() * 4, 0},
+        {T.fwd_em.items.data(), T.fwd_em.items.size() * 4, 0},
         {adj.data(), adj.size() * 4, 0},
+        {T.split_meta.data(), T.split_meta.size() * 4, 0},
         {T.box_w.data(), T.box_w.size() * 4, 0},
         {T.box_wf.data(), T.box_wf.size() * 4, 0},
         {T.h.data(), T.h.size() * 4, 0},
@@ -399,12 +434,20 @@ ctis_status upload_tables(ctis_plan *p) {
     }
     p->dev_mem = mem;
     auto at = [&](int k) { return (const void *)((const char *)mem + parts[(size_t)k].off); };
-    p->dt.unit_tile = (const int32_t *)at(0);
-    p->dt.fwd_items = (const int4 *)at(1);
-    p->dt.adj_items = (const int4 *)at(2);
-    p->dt.box_w = (const float *)at(3);
-    p->dt.box_wf = (const float *)at(4);
-    p->dt.h = (const float *)at(5);
+    auto list = [&](FwdList &L, const HostList &H, int k0) {
+        L.unit_meta = (const int4 *)at(k0);
+        L.items = (const int4 *)at(k0 + 1);
+        L.n_units = H.n_units;
+        L.stride = H.stride;
+        L.waves = H.waves;
+    };
+    list(p->dt.fwd_full, T.fwd_full, 0);
+    list(p->dt.fwd_em, T.fwd_em, 2);
+    p->dt.adj_items = (const int4 *)at(4);
+    p->dt.split_meta = (const int4 *)at(5);
+    p->dt.box_w = (const float *)at(6);
+    p->dt.box_wf = (const float *)at(7);
+    p->dt.h = (const float *)at(8);
     return CTIS_OK;
 }
 

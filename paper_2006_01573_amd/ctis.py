@@ -115,9 +115,9 @@ def load_library(path: str | None = None):
         L.ctis_adjoint.restype = st
         L.ctis_em_iterate.argtypes = [vp, vp, vp, i32, vp, sz, vp]
         L.ctis_em_iterate.restype = st
-        L.ctis_em_forward_ratio.argtypes = [vp, vp, vp, vp, vp]
+        L.ctis_em_forward_ratio.argtypes = [vp, vp, vp, vp, sz, vp]
         L.ctis_em_forward_ratio.restype = st
-        L.ctis_em_adjoint_update.argtypes = [vp, vp, vp, vp, vp]
+        L.ctis_em_adjoint_update.argtypes = [vp, vp, sz, vp, vp, vp]
         L.ctis_em_adjoint_update.restype = st
         L.ctis_status_str.argtypes = [st]
         L.ctis_status_str.restype = ctypes.c_char_p
@@ -285,22 +285,27 @@ class Plan:
         nbytes = self.info.workspace_bytes
         return torch.empty(max(nbytes // 4, 64), dtype=torch.float32, device=self.device)
 
-    def em_forward_ratio(self, f, g, u):
-        """u = g / (H f) on the active FPA tiles (one EM half; see ctis.h)."""
-        self._need_device()
-        torch = _torch()
-        st = self._L.ctis_em_forward_ratio(self._handle, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(g.data_ptr()),
-                                           ctypes.c_void_p(u.data_ptr()), _stream(torch, self.device))
-        _check(self._L, st, "ctis_em_forward_ratio")
-        return u
+    @staticmethod
+    def _ws(workspace):
+        return ctypes.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size()
 
-    def em_adjoint_update(self, u, f_in, f_out):
-        """f_out = f_in * (H^T u) / h (the other EM half)."""
+    def em_forward_ratio(self, f, g, workspace):
+        """u = g / (H f) into the first n floats of the workspace (one EM half)."""
         self._need_device()
         torch = _torch()
-        st = self._L.ctis_em_adjoint_update(self._handle, ctypes.c_void_p(u.data_ptr()),
-                                            ctypes.c_void_p(f_in.data_ptr()), ctypes.c_void_p(f_out.data_ptr()),
-                                            _stream(torch, self.device))
+        wp, wb = self._ws(workspace)
+        st = self._L.ctis_em_forward_ratio(self._handle, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(g.data_ptr()),
+                                           wp, wb, _stream(torch, self.device))
+        _check(self._L, st, "ctis_em_forward_ratio")
+        return workspace[: self.info.n].view(self.shape_g)
+
+    def em_adjoint_update(self, workspace, f_in, f_out):
+        """f_out = f_in * (H^T u) / h with u from the workspace (the other EM half)."""
+        self._need_device()
+        torch = _torch()
+        wp, wb = self._ws(workspace)
+        st = self._L.ctis_em_adjoint_update(self._handle, wp, wb, ctypes.c_void_p(f_in.data_ptr()),
+                                            ctypes.c_void_p(f_out.data_ptr()), _stream(torch, self.device))
         _check(self._L, st, "ctis_em_adjoint_update")
         return f_out
 

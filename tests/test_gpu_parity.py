@@ -270,13 +270,79 @@ def test_em_halves_compose_to_em_iterate(torch, c1):
     gd = torch.from_numpy(g).cuda()
     ref = p.em(gd, 3)
     f = torch.ones(p.shape_f, device="cuda")
-    u = torch.empty(p.shape_g, device="cuda")
+    ws = p.workspace()
     tmp = torch.empty_like(f)
     for k in range(3):
-        p.em_forward_ratio(f, gd, u)
+        p.em_forward_ratio(f, gd, ws)
         if k % 2 == 0:
-            p.em_adjoint_update(u, f, tmp)
+            p.em_adjoint_update(ws, f, tmp)
             f, tmp = tmp, f
         else:
-            p.em_adjoint_update(u, f, f)
+            p.em_adjoint_update(ws, f, f)
     assert torch.equal(f, ref)
+
+
+def test_c3_em_split_tiles_parity(torch, ctis, oracle_mod):
+    """c3 geometry: FPA tiles with more boxes than one workgroup takes are
+    split over several workgroups and summed by the last one.  One EM
+    iteration at full size against the oracle's single rows / columns (the
+    ratio u is checked on sampled pixels, the update on sampled voxels)."""
+    case = W.make_case(3)
+    geo = case.geometry
+    p = ctis.Plan.from_case(case)
+    assert p.info.n_active_tiles < p._info().n_tiles
+    log(f"c3 split: workspace {p.info.workspace_bytes} bytes")
+    ok = oracle_mod.Oracle.from_case(case, assemble=False)
+    rng = np.random.default_rng(5)
+    f0 = (case.f_true + 0.05).astype(np.float32)
+    g = (rng.random(geo.n) * 3).astype(np.float32)
+    ws = p.workspace()
+    fd = torch.from_numpy(f0).cuda()
+    gd = torch.from_numpy(g).cuda()
+    u = p.em_forward_ratio(fd, gd, ws).cpu().numpy().ravel()
+    ghat = p.forward(fd).cpu().numpy().ravel()
+    rows = np.flatnonzero(ghat > 0)[::61]
+    gh_ref = ok.forward_rows(f0, rows)
+    u_ref = g[rows].astype(np.float64) / gh_ref
+    assert rel_l2(u[rows], u_ref) <= PROJ_TOL
+    # a second pass on the same workspace
+    u2 = p.em_forward_ratio(fd, gd, ws).cpu().numpy().ravel()
+    assert np.array_equal(u, u2)
+    f1 = p.em_adjoint_update(ws, fd, torch.empty_like(fd)).cpu().numpy().ravel()
+    # the update needs u on the whole support: take it from the GPU's u only
+    # through the oracle's own ratio on every support pixel
+    cols = rng.choice(geo.m, 1500, replace=False)
+    full_u = np.zeros(geo.n)
+    sup = np.flatnonzero(ghat > 0)
+    full_u[sup] = g[sup].astype(np.float64) / ok.forward_rows(f0, sup)
+    zeta = ok.adjoint_cols(full_u, cols)
+    h = np.repeat(p.lambda_sums().astype(np.float64), geo.ell)
+    f1_ref = f0.ravel()[cols].astype(np.float64) * zeta / h[cols]
+    assert rel_l2(f1[cols], f1_ref) <= PROJ_TOL
+
+
+def test_split_tiles_em_parity(torch, ctis, oracle_mod):
+    """70 wavelengths whose nonzeros all land near one spot: the FPA tiles
+    there carry more boxes than one workgroup takes and are split; EM over
+    several iterations (and repeated calls on one workspace) match the
+    oracle."""
+    geo = W.Geometry(8, 8, 70, 64, 40)
+    rng = np.random.default_rng(11)
+    ptr, idx, val = [0], [], []
+    for s in range(geo.w):
+        r, c = 20 + rng.integers(0, 4), 10 + rng.integers(0, 4)
+        for dr in range(2):
+            idx.append(r + dr + geo.gamma * c)
+            val.append(rng.uniform(0.2, 1.0))
+        ptr.append(len(idx))
+    ptr, idx, val = np.array(ptr, np.int64), np.array(idx, np.int32), np.array(val, np.float32)
+    p = gpu_plan(ctis, geo, ptr, idx, val)
+    o = oracle_for(oracle_mod, geo, ptr, idx, val)
+    assert p.info.workspace_bytes > 4 * geo.n + 256, "expected split tiles"
+    g = (o.forward(np.ones(geo.m)) * rng.uniform(0.5, 1.5, geo.n)).astype(np.float32)
+    gd = torch.from_numpy(g).cuda()
+    ws = p.workspace()
+    for k in (1, 4, 9):
+        f = torch.ones(p.shape_f, device="cuda")
+        p.em(gd, k, f=f, workspace=ws)
+        assert rel_l2(f.cpu().numpy(), o.em(g, k)) <= EM_TOL
