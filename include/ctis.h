@@ -69,6 +69,7 @@ typedef enum {
 } ctis_status;
 
 typedef struct ctis_plan ctis_plan;
+typedef struct ctis_batch ctis_batch;
 
 /* ctis_plan_create flags */
 #define CTIS_PLAN_HOST_ONLY 0x1u        /* build the tables on the host only (no
@@ -207,6 +208,57 @@ ctis_status ctis_em_forward_ratio(const ctis_plan *plan, const float *f, const f
                                   size_t workspace_bytes, void *stream);
 ctis_status ctis_em_adjoint_update(const ctis_plan *plan, const void *workspace, size_t workspace_bytes,
                                    const float *f_in, float *f_out, void *stream);
+
+
+/*
+ * Batches: many frames, each with its own plan (geometry and calibration,
+ * uneven sizes allowed), reconstructed together -- each EM iteration is one
+ * forward+ratio launch and one adjoint+update launch for all frames, whose
+ * workgroups walk one work list that holds the units of every frame.  No
+ * host synchronisation, memset or allocation happens inside the calls, so a
+ * caller may capture them in a HIP graph.
+ *
+ * Layout: frame k's datacube occupies f_all[f_offset_k, f_offset_k + m_k) and
+ * its FPA image g_all[g_offset_k, g_offset_k + n_k), frames back to back in
+ * order: f_offset_k = sum_{j<k} m_j, g_offset_k = sum_{j<k} n_j (each block in
+ * the layout of the single-frame calls).  plans[k] may repeat (frames sharing
+ * one calibration).  All plans need the same box side B (ctis_plan_info.box;
+ * CTIS_PLAN_BOX forces it) and the batch's device.  The batch keeps pointers
+ * to the plans, which must outlive it.
+ */
+#define CTIS_BATCH_WAVES_FORWARD(n) (((uint32_t)(n) & 0x1Fu) << 0)   /* 0 = chosen */
+#define CTIS_BATCH_WAVES_ADJOINT(n) (((uint32_t)(n) & 0x1Fu) << 5)   /* 0 = chosen */
+#define CTIS_BATCH_PERSISTENT 0x400u   /* launch only as many workgroups as fit on the chip
+                                          at once, each walking the work list; default:
+                                          one workgroup per work unit                    */
+
+typedef struct {
+    int32_t n_frames;
+    int32_t box;
+    int64_t m_total, n_total;      /* sizes of f_all and g_all (floats)          */
+    int64_t forward_units, adjoint_units;
+    int32_t waves_forward, waves_adjoint;
+    size_t workspace_bytes;        /* EM workspace of ctis_batch_em_iterate      */
+} ctis_batch_info;
+
+/* Create a batch over n_frames >= 1 frames.  flags: CTIS_BATCH_WAVES_* (wave
+ * counts per workgroup of the two kernels, 4..16, or 0 for the built-in
+ * choice), CTIS_BATCH_PERSISTENT.  Errors: CTIS_E_ARG (different B, host-only or other-device plan,
+ * bad flags), CTIS_E_TOO_LARGE (buffers beyond 2^31 floats), CTIS_E_NOMEM,
+ * CTIS_E_HIP. */
+ctis_status ctis_batch_create(ctis_batch **out, const ctis_plan *const *plans, int32_t n_frames, uint32_t flags);
+void ctis_batch_destroy(ctis_batch *batch);
+ctis_status ctis_batch_get_info(const ctis_batch *batch, ctis_batch_info *info);
+
+/* g_all = H f_all frame by frame (DEVICE, layouts above). */
+ctis_status ctis_batch_forward(const ctis_batch *batch, const float *f_all, float *g_all, void *stream);
+/* z_all = H^T r_all frame by frame. */
+ctis_status ctis_batch_adjoint(const ctis_batch *batch, const float *r_all, float *z_all, void *stream);
+/* iters EM iterations of every frame, in place on f_all, with one workspace
+ * (>= info.workspace_bytes, 256-byte aligned).  Same semantics per frame as
+ * ctis_em_iterate; CTIS_E_NEGATIVE if any plan has a negative value. */
+ctis_status ctis_batch_em_iterate(const ctis_batch *batch, const float *g_all, float *f_all, int32_t iters,
+                                  void *workspace, size_t workspace_bytes, void *stream);
 
 /* Static description of a status code. */
 const char *ctis_status_str(ctis_status status);

@@ -131,11 +131,34 @@ ctis_status ctis_plan_create(ctis_plan **out, int32_t a, int32_t alpha, int32_t 
             return fail(CTIS_E_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
         }
         p->device = dev;
-        st = upload_tables(p);
+        HostWork hw;
+        try {
+            st = build_work({FrameRef{p, 0, 0, 0}}, true, hw);
+        } catch (const std::bad_alloc &) {
+            st = fail(CTIS_E_NOMEM, "host allocation while building the work tables");
+        }
+        if (st == CTIS_OK) st = upload_work(hw, p->work);
         if (st != CTIS_OK) {
             delete p;
             return st;
         }
+        p->workspace_bytes = p->work.workspace_bytes;
+    } else {
+        // host-only plans still report the workspace an EM call would need
+        HostWork hw;
+        try {
+            st = build_work({FrameRef{p, 0, 0, 0}}, false, hw);
+        } catch (const std::bad_alloc &) {
+            st = fail(CTIS_E_NOMEM, "host allocation while building the work tables");
+        }
+        if (st != CTIS_OK) {
+            delete p;
+            return st;
+        }
+        p->workspace_bytes = (((size_t)hw.u_floats * 4 + 255) & ~(size_t)255) +
+                             (size_t)hw.partial_slots * kTileFast * kTileSlow * sizeof(float);
+        p->work.fwd_em.waves = hw.fwd_em.waves;
+        p->work.adj.waves = hw.adj.waves;
     }
     *out = p;
     return CTIS_OK;
@@ -143,7 +166,7 @@ ctis_status ctis_plan_create(ctis_plan **out, int32_t a, int32_t alpha, int32_t 
 
 void ctis_plan_destroy(ctis_plan *p) {
     if (!p) return;
-    if (p->dev_mem) (void)hipFree(p->dev_mem);
+    free_work(p->work);
     delete p;
 }
 
@@ -170,8 +193,8 @@ ctis_status ctis_plan_get_info(const ctis_plan *p, ctis_plan_info *info) {
     info->workspace_bytes = p->workspace_bytes;
     info->nonnegative = p->ht.nonneg ? 1 : 0;
     info->device = p->device;
-    info->waves_forward = p->ht.fwd_em.waves;
-    info->waves_adjoint = p->waves_adj;
+    info->waves_forward = p->work.fwd_em.waves;
+    info->waves_adjoint = p->work.adj.waves;
     return CTIS_OK;
 }
 
@@ -205,7 +228,7 @@ ctis_status ctis_forward(const ctis_plan *p, const float *f, float *g_out, void 
     if (overlaps(f, (size_t)p->m * 4, g_out, (size_t)p->n * 4)) return fail(CTIS_E_ARG, "f and g_out overlap");
     ctis_status st = check_device(p);
     if (st != CTIS_OK) return st;
-    return launch_status(launch_forward(p, f, nullptr, g_out, false, nullptr, stream), "forward launch");
+    return launch_status(launch_forward(p->work, f, nullptr, g_out, false, nullptr, stream), "forward launch");
 }
 
 ctis_status ctis_adjoint(const ctis_plan *p, const float *r, float *z_out, void *stream) {
@@ -215,7 +238,7 @@ ctis_status ctis_adjoint(const ctis_plan *p, const float *r, float *z_out, void 
     if (overlaps(r, (size_t)p->n * 4, z_out, (size_t)p->m * 4)) return fail(CTIS_E_ARG, "r and z_out overlap");
     ctis_status st = check_device(p);
     if (st != CTIS_OK) return st;
-    return launch_status(launch_adjoint(p, r, nullptr, z_out, false, stream), "adjoint launch");
+    return launch_status(launch_adjoint(p->work, r, nullptr, z_out, false, stream), "adjoint launch");
 }
 
 namespace {
@@ -249,9 +272,9 @@ ctis_status ctis_em_iterate(const ctis_plan *p, const float *g, float *f, int32_
     if (st != CTIS_OK || iters == 0) return st;
     float *u = (float *)workspace;
     for (int32_t k = 0; k < iters; ++k) {
-        st = launch_status(launch_forward(p, f, g, u, true, workspace, stream), "forward+ratio launch");
+        st = launch_status(launch_forward(p->work, f, g, u, true, workspace, stream), "forward+ratio launch");
         if (st != CTIS_OK) return st;
-        st = launch_status(launch_adjoint(p, u, f, f, true, stream), "adjoint+update launch");
+        st = launch_status(launch_adjoint(p->work, u, f, f, true, stream), "adjoint+update launch");
         if (st != CTIS_OK) return st;
     }
     return CTIS_OK;
@@ -270,7 +293,7 @@ ctis_status ctis_em_forward_ratio(const ctis_plan *p, const float *f, const floa
         return fail(CTIS_E_ARG, "the workspace must not overlap f or g");
     st = check_device(p);
     if (st != CTIS_OK) return st;
-    return launch_status(launch_forward(p, f, g, (float *)workspace, true, workspace, stream),
+    return launch_status(launch_forward(p->work, f, g, (float *)workspace, true, workspace, stream),
                          "forward+ratio launch");
 }
 
@@ -288,7 +311,7 @@ ctis_status ctis_em_adjoint_update(const ctis_plan *p, const void *workspace, si
         return fail(CTIS_E_ARG, "the workspace and f_out overlap");
     st = check_device(p);
     if (st != CTIS_OK) return st;
-    return launch_status(launch_adjoint(p, (const float *)workspace, f_in, f_out, true, stream),
+    return launch_status(launch_adjoint(p->work, (const float *)workspace, f_in, f_out, true, stream),
                          "adjoint+update launch");
 }
 

@@ -1,0 +1,166 @@
+// Batches of frames (C ABI): several plans merged into one work description,
+// so that each EM iteration of all frames is one forward+ratio launch and one
+// adjoint+update launch.
+#include <new>
+#include <string>
+
+#include "ctis_internal.h"
+
+using namespace ctis;
+
+namespace {
+
+ctis_status batch_device(const ctis_batch *b) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(CTIS_E_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev != b->device) return fail(CTIS_E_ARG, "current HIP device differs from the batch's device");
+    return CTIS_OK;
+}
+
+bool aligned4(const void *ptr) { return ((uintptr_t)ptr & 3u) == 0; }
+
+bool overlaps(const void *x, size_t xb, const void *y, size_t yb) {
+    const char *a = (const char *)x, *b = (const char *)y;
+    return a < b + yb && b < a + xb;
+}
+
+ctis_status launched(int err, const char *what) {
+    if (err != 0) return fail(CTIS_E_HIP, std::string(what) + ": " + hipGetErrorString((hipError_t)err));
+    return CTIS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ctis_status ctis_batch_create(ctis_batch **out, const ctis_plan *const *plans, int32_t n_frames, uint32_t flags) {
+    if (!out) return fail(CTIS_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!plans || n_frames < 1) return fail(CTIS_E_ARG, "need at least one plan");
+    if (flags & ~(0x3FFu | CTIS_BATCH_PERSISTENT)) return fail(CTIS_E_ARG, "unknown flag bits");
+    const int wf = (int)(flags & 0x1Fu), wa = (int)((flags >> 5) & 0x1Fu);
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(CTIS_E_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    std::vector<FrameRef> frames;
+    int64_t fo = 0, go = 0;
+    bool nonneg = true;
+    for (int32_t k = 0; k < n_frames; ++k) {
+        const ctis_plan *p = plans[k];
+        if (!p) return fail(CTIS_E_ARG, "plan " + std::to_string(k) + " is NULL");
+        if (p->device < 0) return fail(CTIS_E_ARG, "plan " + std::to_string(k) + " is host-only");
+        if (p->device != dev) return fail(CTIS_E_ARG, "plan " + std::to_string(k) + " lives on another device");
+        if (p->ht.B != plans[0]->ht.B) return fail(CTIS_E_ARG, "all plans of a batch need the same box side B");
+        frames.push_back(FrameRef{p, fo, go, go});
+        fo += p->m;
+        go += p->n;
+        nonneg = nonneg && p->ht.nonneg;
+        if (fo > INT32_MAX || go > INT32_MAX) return fail(CTIS_E_TOO_LARGE, "batch buffers beyond 2^31 floats");
+    }
+    const int B = plans[0]->ht.B;
+    for (int nw : {wf, wa})
+        if (nw != 0 && (nw < min_waves() || nw > max_waves(B)))
+            return fail(CTIS_E_ARG, "waves per workgroup must be 0 or in " + std::to_string(min_waves()) + ".." +
+                                        std::to_string(max_waves(B)));
+    ctis_batch *b = new (std::nothrow) ctis_batch();
+    if (!b) return fail(CTIS_E_NOMEM, "batch allocation");
+    ctis_status st;
+    HostWork hw;
+    try {
+        st = build_work(frames, true, hw);
+    } catch (const std::bad_alloc &) {
+        st = fail(CTIS_E_NOMEM, "host allocation while building the work tables");
+    }
+    if (st == CTIS_OK) {
+        if (wf) hw.fwd_em.waves = hw.fwd_full.waves = wf;
+        if (wa) hw.adj.waves = wa;
+        st = upload_work(hw, b->work);
+        b->work.persistent = (flags & CTIS_BATCH_PERSISTENT) != 0;
+    }
+    if (st != CTIS_OK) {
+        delete b;
+        return st;
+    }
+    for (const FrameRef &fr : frames) {
+        b->plans.push_back(fr.plan);
+        b->f_base.push_back(fr.f_base);
+        b->g_base.push_back(fr.g_base);
+        b->u_base.push_back(fr.u_base);
+    }
+    b->f_floats = fo;
+    b->g_floats = go;
+    b->device = dev;
+    b->nonneg = nonneg;
+    *out = b;
+    return CTIS_OK;
+}
+
+void ctis_batch_destroy(ctis_batch *b) {
+    if (!b) return;
+    free_work(b->work);
+    delete b;
+}
+
+ctis_status ctis_batch_get_info(const ctis_batch *b, ctis_batch_info *info) {
+    if (!b || !info) return fail(CTIS_E_ARG, "batch or info is NULL");
+    info->n_frames = (int32_t)b->plans.size();
+    info->box = b->work.B;
+    info->m_total = b->f_floats;
+    info->n_total = b->g_floats;
+    info->forward_units = b->work.fwd_em.n_units;
+    info->adjoint_units = b->work.adj.n_units;
+    info->waves_forward = b->work.fwd_em.waves;
+    info->waves_adjoint = b->work.adj.waves;
+    info->workspace_bytes = b->work.workspace_bytes;
+    return CTIS_OK;
+}
+
+ctis_status ctis_batch_forward(const ctis_batch *b, const float *f_all, float *g_all, void *stream) {
+    if (!b) return fail(CTIS_E_ARG, "batch is NULL");
+    if (!f_all || !g_all || !aligned4(f_all) || !aligned4(g_all))
+        return fail(CTIS_E_ARG, "f_all and g_all must be non-NULL and 4-byte aligned");
+    if (overlaps(f_all, (size_t)b->f_floats * 4, g_all, (size_t)b->g_floats * 4))
+        return fail(CTIS_E_ARG, "f_all and g_all overlap");
+    ctis_status st = batch_device(b);
+    if (st != CTIS_OK) return st;
+    return launched(launch_forward(b->work, f_all, nullptr, g_all, false, nullptr, stream), "batch forward launch");
+}
+
+ctis_status ctis_batch_adjoint(const ctis_batch *b, const float *r_all, float *z_all, void *stream) {
+    if (!b) return fail(CTIS_E_ARG, "batch is NULL");
+    if (!r_all || !z_all || !aligned4(r_all) || !aligned4(z_all))
+        return fail(CTIS_E_ARG, "r_all and z_all must be non-NULL and 4-byte aligned");
+    if (overlaps(r_all, (size_t)b->g_floats * 4, z_all, (size_t)b->f_floats * 4))
+        return fail(CTIS_E_ARG, "r_all and z_all overlap");
+    ctis_status st = batch_device(b);
+    if (st != CTIS_OK) return st;
+    return launched(launch_adjoint(b->work, r_all, nullptr, z_all, false, stream), "batch adjoint launch");
+}
+
+ctis_status ctis_batch_em_iterate(const ctis_batch *b, const float *g_all, float *f_all, int32_t iters,
+                                  void *workspace, size_t workspace_bytes, void *stream) {
+    if (!b) return fail(CTIS_E_ARG, "batch is NULL");
+    if (!g_all || !f_all || !aligned4(g_all) || !aligned4(f_all))
+        return fail(CTIS_E_ARG, "g_all and f_all must be non-NULL and 4-byte aligned");
+    if (iters < 0) return fail(CTIS_E_ARG, "iters must be >= 0");
+    if (!b->nonneg) return fail(CTIS_E_NEGATIVE, "a plan of the batch has a negative calibration value");
+    if (!workspace || workspace_bytes < b->work.workspace_bytes)
+        return fail(CTIS_E_WORKSPACE, "workspace needs " + std::to_string(b->work.workspace_bytes) + " bytes");
+    if (((uintptr_t)workspace & 255u) != 0) return fail(CTIS_E_WORKSPACE, "workspace must be 256-byte aligned");
+    const size_t fb = (size_t)b->f_floats * 4, gb = (size_t)b->g_floats * 4, wb = b->work.workspace_bytes;
+    if (overlaps(g_all, gb, f_all, fb) || overlaps(workspace, wb, f_all, fb) || overlaps(workspace, wb, g_all, gb))
+        return fail(CTIS_E_ARG, "g_all, f_all and the workspace must not overlap");
+    ctis_status st = batch_device(b);
+    if (st != CTIS_OK) return st;
+    float *u = (float *)workspace;
+    for (int32_t k = 0; k < iters; ++k) {
+        st = launched(launch_forward(b->work, f_all, g_all, u, true, workspace, stream), "batch forward+ratio launch");
+        if (st != CTIS_OK) return st;
+        st = launched(launch_adjoint(b->work, u, f_all, f_all, true, stream), "batch adjoint+update launch");
+        if (st != CTIS_OK) return st;
+    }
+    return CTIS_OK;
+}
+
+}  // extern "C"

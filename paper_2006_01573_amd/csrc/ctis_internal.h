@@ -24,43 +24,63 @@ constexpr int kMaxBox = 8;
 // 32-bit buffer offsets (in bytes) address the FPA and one wavelength block
 constexpr int64_t kMaxPixels = (int64_t(1) << 29) - 1;
 
-// One forward launch: a list of work units, one workgroup each.  A unit is a
-// chunk of the boxes that meet one FPA tile; a tile with more boxes than the
-// chunk size is split over several units, whose partial tiles a second,
-// small kernel sums.
-struct FwdList {
-    const int4 *unit_meta;   // n_units: (tile, chunk, n_chunks, partial slot of chunk 0)
-    const int4 *items;       // n_units * stride records (X, Y, s, box), X, Y = window
-                             //   origin (r0 - (B-1) - rA, c0 - (B-1) - cA); box = -1 ends
+// ---------------------------------------------------------------------------
+// Work description of one launch set.  A plan is a batch of one frame; a
+// batch (ctis_batch) merges several plans (frames) that share the box side B.
+// Every work unit carries its frame's geometry and buffer offsets, so the
+// kernels never look up a frame table.
+//
+// forward unit meta, 3 x int4:
+//   (r0, c0, n_chunks, partial slot)   FPA tile origin; a tile whose boxes are
+//                                      split over n_chunks > 1 units writes its
+//                                      partial tile to that slot
+//   (a, alpha, gamma, xi)              frame geometry
+//   (g_off, out_off, 0, 0)             frame offsets (floats) into g and out
+// forward record, int4: (Xs, Ys, f_off, box): window origin
+//   (r0 - (B-1) - rA, c0 - (B-1) - cA), offset of f_s in the f buffer, global
+//   box id; box = -1 ends a unit's list
+// split meta, 2 x int4: (r0, c0, n_chunks, first slot), (gamma, xi, g_off, out_off)
+// adjoint unit meta, 3 x int4:
+//   (x0, y0, global wavelength, f_off)  field-stop tile, offset of f_s
+//   (a, alpha, gamma, xi)
+//   (u_off, 0, 0, 0)                    frame offset into u
+// adjoint record, int4: (rA, cA, 0, box), adj_stride records per global
+//   wavelength
+struct DevList {
+    const int4 *meta = nullptr;
+    const int4 *items = nullptr;
     int32_t n_units = 0, stride = 1, waves = 4;
 };
 
-// Device-side tables of a plan (one allocation, pointers into it).
-struct DevTables {
-    FwdList fwd_full;           // every FPA tile, one unit each (plain projection)
-    FwdList fwd_em;             // FPA tiles with boxes, heavy tiles split (EM)
-    const int4 *split_meta;     // n_split_tiles: (tile, n_chunks, partial slot of chunk 0, 0)
-    const int4 *adj_items;      // w * adj_stride: per wavelength, its boxes with
-                                //   X, Y = the anchor (rA, cA)
-    const float *box_w;         // nb*B*B, [dc*B + dr]
-    const float *box_wf;        // nb*B*B, flipped: [(B-1-dc)*B + (B-1-dr)]
-    const float *h;             // w: column sums per wavelength
-};
-
-// Scalar kernel parameters (passed by value).
-struct KParams {
-    int32_t a, alpha, w, gamma, xi;
-    int32_t ell, n;
-    int32_t ntr;        // FPA tiles along the fast axis
-    int32_t nbx, nby;   // field-stop tiles along x and y
-    int32_t adj_stride; // records per wavelength (max boxes of one wavelength)
+struct DevWork {
+    int32_t B = 1;
+    DevList fwd_full;            // plain projection: every FPA tile once
+    DevList fwd_em;              // EM: tiles with boxes, heavy tiles split
+    const int4 *split_meta = nullptr;
+    int32_t n_split = 0;
+    DevList adj;                 // adjoint units; items indexed by global wavelength
+    const float *box_w = nullptr, *box_wf = nullptr, *h = nullptr;
+    size_t partials_off = 0;     // byte offset of the partial tiles in the EM workspace
+    size_t workspace_bytes = 0;  // u region + partial tiles
+    bool persistent = false;     // grid-stride workgroups instead of one per unit
+    void *mem = nullptr;         // device allocation holding the tables
 };
 
 struct HostList {
-    std::vector<int32_t> unit_meta, items;   // int4 records, flattened
+    std::vector<int32_t> meta, items;   // int4 records, flattened
     int32_t n_units = 0, stride = 1, waves = 4;
 };
 
+struct HostWork {
+    int32_t B = 1;
+    HostList fwd_full, fwd_em, adj;
+    std::vector<int32_t> split_meta;
+    int32_t n_split = 0, partial_slots = 0;
+    std::vector<float> box_w, box_wf, h;
+    int64_t u_floats = 0;        // u region of the EM workspace
+};
+
+// Per-plan analysis of the calibration (host).
 struct HostTables {
     int32_t B = 1;
     std::vector<int32_t> box_rc, box_lambda, lambda_box_ptr;
@@ -69,12 +89,9 @@ struct HostTables {
     int32_t ntr = 0, ntc = 0, n_tiles = 0, n_active = 0;
     int32_t nbx = 0, nby = 0;
     int64_t nnz = 0, n_support = 0;
-    bool nonneg = true;
-    HostList fwd_full, fwd_em;
+    int32_t max_items = 0, max_boxes = 0;
     int32_t chunk = 64;          // max boxes per forward unit in EM
-    int32_t partial_slots = 0;   // 64x16 partial tiles of split FPA tiles
-    int32_t n_split_tiles = 0;
-    std::vector<int32_t> split_meta;
+    bool nonneg = true;
 };
 
 }  // namespace ctis
@@ -84,12 +101,17 @@ struct ctis_plan {
     int64_t n, ell, m;
     ctis::HostTables ht;
     int32_t device = -1;
-    void *dev_mem = nullptr;    // one allocation holding every table
-    ctis::DevTables dt{};
-    ctis::KParams kp{};
-    int32_t waves_adj = 4;
+    ctis::DevWork work;          // the plan as a batch of one frame
     size_t workspace_bytes = 0;
-    size_t ws_partials = 0;      // byte offset of the partial tiles in the EM workspace
+};
+
+struct ctis_batch {
+    std::vector<const ctis_plan *> plans;
+    std::vector<int64_t> f_base, g_base, u_base;   // per frame, in floats
+    int64_t f_floats = 0, g_floats = 0;
+    int32_t device = -1;
+    bool nonneg = true;
+    ctis::DevWork work;
 };
 
 namespace ctis {
@@ -100,14 +122,21 @@ ctis_status fail(ctis_status st, const std::string &msg);
 // host plan builder (plan.cpp)
 ctis_status build_host_tables(ctis_plan *p, const int64_t *lambda_ptr, const int32_t *fpa_index,
                               const float *value, int forced_box);
-ctis_status upload_tables(ctis_plan *p);
+
+// One frame of a work description: its plan and buffer offsets (floats).
+struct FrameRef {
+    const ctis_plan *plan;
+    int64_t f_base, g_base, u_base;
+};
+ctis_status build_work(const std::vector<FrameRef> &frames, bool with_full, HostWork &hw);
+ctis_status upload_work(const HostWork &hw, DevWork &dw);
+void free_work(DevWork &dw);
 
 // kernel launchers (kernels.hip); return hipError_t as int
 int max_waves(int box);
 int min_waves();
-int launch_forward(const ctis_plan *p, const float *f, const float *g, float *out, bool em_ratio,
-                   void *workspace, void *stream);
-int launch_adjoint(const ctis_plan *p, const float *u, const float *fin, float *out, bool em_update,
+int launch_forward(const DevWork &w, const float *f, const float *g, float *out, bool em, void *workspace,
                    void *stream);
+int launch_adjoint(const DevWork &w, const float *u, const float *fin, float *out, bool em, void *stream);
 
 }  // namespace ctis

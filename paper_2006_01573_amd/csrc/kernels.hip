@@ -28,6 +28,7 @@
 // unit returns as 0.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <mutex>
 
 #include "ctis_internal.h"
@@ -105,22 +106,27 @@ __device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, unsigned voff, 
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }
 
+// Frame geometry of a work unit.
+struct Geo {
+    int a, alpha, gamma, xi;
+};
+
 template <int B>
 __device__ __forceinline__ void load_values(Pending<B> &pd, const float *__restrict__ wtab, int box, int lane) {
     pd.wt = 0.0f;
     if (lane < B * B) pd.wt = wtab[(size_t)box * (B * B) + lane];
 }
 
-// Forward window of one (tile, box) item, rec = (Xs, Ys, s, box):
+// Forward window of one (tile, box) item, rec = (Xs, Ys, f_off, box):
 // slot (xx, yy) <- fE((Xs + xx) + gamma*(Ys + yy) mod n).
 // Interior windows (no window row crosses the end of an FPA column, so the
 // slow-axis index of a row is the same for every lane) take the row offset
 // as the buffer's scalar offset; other windows decode every slot.
 template <int B>
 __device__ __forceinline__ void load_forward(Pending<B> &pd, const float *f, const float *__restrict__ wtab,
-                                             const KParams &p, int4 rec, int lane) {
+                                             const Geo &p, int4 rec, int lane) {
     using Wn = Win<B>;
-    const __amdgpu_buffer_rsrc_t fr = rsrc(f + (size_t)rec.z * p.ell, p.ell);
+    const __amdgpu_buffer_rsrc_t fr = rsrc(f + (size_t)(unsigned)rec.z, p.a * p.alpha);
     const int Xs = rec.x, Ys = rec.y;
     int q0, xr, yq, y0;
     floor_divmod(Xs, p.gamma, q0, xr);
@@ -199,7 +205,7 @@ __device__ __forceinline__ void load_forward(Pending<B> &pd, const float *f, con
 // Interior windows take the row offset as the buffer's scalar offset.
 template <int B>
 __device__ __forceinline__ void load_adjoint(Pending<B> &pd, __amdgpu_buffer_rsrc_t ur,
-                                             const float *__restrict__ wtab, const KParams &p, int Xs, int Ys,
+                                             const float *__restrict__ wtab, const Geo &p, int Xs, int Ys,
                                              int box, int lane) {
     using Wn = Win<B>;
     int q0, xr, yq, y0;
@@ -332,189 +338,201 @@ __device__ __forceinline__ float row_sum(const float *lds, int nw, int row, int 
     _Pragma("unroll") for (int j = 0; j < kRowsPerWave; ++j)  \
         if (const int row = wv + j * nw; row < TY)
 
-// Forward projection of one work unit (a chunk of the boxes meeting one FPA
-// tile).  A tile split into several units writes one partial tile per unit
-// to `partials`; k_finish_split then sums them (next launch on the stream).
+// Forward projection.  Workgroups walk the unit list (grid stride); a unit is
+// a chunk of the boxes meeting one FPA tile of one frame.  A tile split into
+// several units writes one partial tile per unit to `partials`;
+// k_finish_split sums them (next launch on the stream).
 template <int B>
-__global__ void __launch_bounds__(64 * Win<B>::MAXW) k_forward(const KParams p, const int4 *__restrict__ unit_meta,
+__global__ void __launch_bounds__(64 * Win<B>::MAXW) k_forward(const int4 *__restrict__ meta,
                                                                const int4 *__restrict__ items, const int stride,
-                                                               const float *__restrict__ box_wf,
+                                                               const int n_units, const float *__restrict__ box_wf,
                                                                const float *__restrict__ f,
                                                                const float *__restrict__ g, float *__restrict__ out,
-                                                               int em, float *__restrict__ partials) {
+                                                               float *__restrict__ partials, const int em) {
     using Wn = Win<B>;
     extern __shared__ float4 lds4[];
     float *lds = reinterpret_cast<float *>(lds4);
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nw = blockDim.x >> 6;
-    const int4 *list = items + (size_t)blockIdx.x * stride;
-    int k = wv;
-    int4 rec0 = record(list, k, stride);
-    int4 rec1 = record(list, k + nw, stride);
-    const int4 um = unit_meta[blockIdx.x];   // (tile, chunk, n_chunks, partial slot of chunk 0)
-    const int r0 = (um.x % p.ntr) * TX, c0 = (um.x / p.ntr) * TY;
     float *S = lds + wv * Wn::WREG;
     const int lx = lane & 15, ly = lane >> 4;
-    const int r = r0 + lane;
-    const bool whole = um.z == 1;
 
-    // operands of the epilogue, fetched up front
-    float gpre[kRowsPerWave];
-    FOR_OWN_ROWS(j, row) {
-        const int c = c0 + row;
-        gpre[j] = (em && whole && r < p.gamma && c < p.xi) ? g[(size_t)r + (size_t)p.gamma * c] : 0.0f;
-    }
+    for (int unit = blockIdx.x; unit < n_units; unit += gridDim.x) {
+        const int4 *list = items + (size_t)unit * stride;
+        int k = wv;
+        int4 rec0 = record(list, k, stride);
+        int4 rec1 = record(list, k + nw, stride);
+        int4 rec2 = record(list, k + 2 * nw, stride);
+        const int4 m0 = meta[3 * unit], m1 = meta[3 * unit + 1], m2 = meta[3 * unit + 2];
+        const Geo geo{m1.x, m1.y, m1.z, m1.w};
+        const int r0 = m0.x, c0 = m0.y;
+        const int r = r0 + lane;
+        const bool whole = m0.z == 1;
 
-    float acc[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[a][q] = 0.0f;
-
-    // two windows in flight: pa holds item k, pb item k + nw; while item k is
-    // computed, item k + 2nw is fetched into the buffer item k came from
-    int4 rec2 = record(list, k + 2 * nw, stride);
-    Pending<B> pa, pb;
-    if (rec0.w >= 0) load_forward<B>(pa, f, box_wf, p, rec0, lane);
-    if (rec1.w >= 0) load_forward<B>(pb, f, box_wf, p, rec1, lane);
-    while (rec0.w >= 0) {
-        store_window<B>(S, pa, lane);
-        wave_lds_sync();
-        int4 rec3 = record(list, k + 3 * nw, stride);
-        if (rec2.w >= 0) load_forward<B>(pa, f, box_wf, p, rec2, lane);
-        correlate<B>(acc, S, lx, ly);
-        wave_lds_sync();
-        k += nw;
-        rec0 = rec1;
-        rec1 = rec2;
-        rec2 = rec3;
-        if (rec0.w < 0) break;
-        store_window<B>(S, pb, lane);
-        wave_lds_sync();
-        rec3 = record(list, k + 3 * nw, stride);
-        if (rec2.w >= 0) load_forward<B>(pb, f, box_wf, p, rec2, lane);
-        correlate<B>(acc, S, lx, ly);
-        wave_lds_sync();
-        k += nw;
-        rec0 = rec1;
-        rec1 = rec2;
-        rec2 = rec3;
-    }
-
-    park_tile(acc, lds, wv, lx, ly);
-    if (!whole) {
-        float *mine = partials + ((size_t)um.w + um.y) * (TX * TY);
-        FOR_OWN_ROWS(j, row) mine[row * TX + lane] = row_sum(lds, nw, row, lane);
-        return;
-    }
-    FOR_OWN_ROWS(j, row) {
-        const int c = c0 + row;
-        float v = row_sum(lds, nw, row, lane);
-        if (r < p.gamma && c < p.xi) {
-            if (em) v = v > 0.0f ? gpre[j] / v : 0.0f;
-            out[(size_t)r + (size_t)p.gamma * c] = v;
+        // operands of the epilogue, fetched up front
+        float gpre[kRowsPerWave];
+        FOR_OWN_ROWS(j, row) {
+            const int c = c0 + row;
+            gpre[j] = (em && whole && r < geo.gamma && c < geo.xi)
+                          ? g[(size_t)m2.x + (size_t)r + (size_t)geo.gamma * c] : 0.0f;
         }
+
+        float acc[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[a][q] = 0.0f;
+
+        // two windows in flight: pa holds item k, pb item k + nw; while item k
+        // is computed, item k + 2nw is fetched into the buffer item k came from
+        Pending<B> pa, pb;
+        if (rec0.w >= 0) load_forward<B>(pa, f, box_wf, geo, rec0, lane);
+        if (rec1.w >= 0) load_forward<B>(pb, f, box_wf, geo, rec1, lane);
+        while (rec0.w >= 0) {
+            store_window<B>(S, pa, lane);
+            wave_lds_sync();
+            int4 rec3 = record(list, k + 3 * nw, stride);
+            if (rec2.w >= 0) load_forward<B>(pa, f, box_wf, geo, rec2, lane);
+            correlate<B>(acc, S, lx, ly);
+            wave_lds_sync();
+            k += nw;
+            rec0 = rec1;
+            rec1 = rec2;
+            rec2 = rec3;
+            if (rec0.w < 0) break;
+            store_window<B>(S, pb, lane);
+            wave_lds_sync();
+            rec3 = record(list, k + 3 * nw, stride);
+            if (rec2.w >= 0) load_forward<B>(pb, f, box_wf, geo, rec2, lane);
+            correlate<B>(acc, S, lx, ly);
+            wave_lds_sync();
+            k += nw;
+            rec0 = rec1;
+            rec1 = rec2;
+            rec2 = rec3;
+        }
+
+        park_tile(acc, lds, wv, lx, ly);
+        if (!whole) {
+            float *mine = partials + (size_t)m0.w * (TX * TY);
+            FOR_OWN_ROWS(j, row) mine[row * TX + lane] = row_sum(lds, nw, row, lane);
+        } else {
+            FOR_OWN_ROWS(j, row) {
+                const int c = c0 + row;
+                float v = row_sum(lds, nw, row, lane);
+                if (r < geo.gamma && c < geo.xi) {
+                    if (em) v = v > 0.0f ? gpre[j] / v : 0.0f;
+                    out[(size_t)m2.y + (size_t)r + (size_t)geo.gamma * c] = v;
+                }
+            }
+        }
+        __syncthreads();   // the next unit reuses the LDS regions
     }
 }
 
 // Sum the partial tiles of every split FPA tile in chunk order and apply the
-// forward epilogue.  One workgroup (4 waves, 4 rows each) per split tile;
-// split_meta[t] = (tile, n_chunks, partial slot of chunk 0, 0).
-__global__ void __launch_bounds__(256) k_finish_split(const KParams p, const int4 *__restrict__ split_meta,
+// forward epilogue.  One workgroup (4 waves, 4 rows each) per split tile.
+__global__ void __launch_bounds__(256) k_finish_split(const int4 *__restrict__ split_meta,
                                                       const float *__restrict__ partials,
                                                       const float *__restrict__ g, float *__restrict__ out,
                                                       int em) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int4 sm = split_meta[blockIdx.x];
-    const int r0 = (sm.x % p.ntr) * TX, c0 = (sm.x / p.ntr) * TY;
-    const int r = r0 + lane;
+    const int4 s0 = split_meta[2 * blockIdx.x], s1 = split_meta[2 * blockIdx.x + 1];
+    const int r = s0.x + lane;
 #pragma unroll
     for (int j = 0; j < TY / 4; ++j) {
-        const int row = wv + 4 * j, c = c0 + row;
-        if (r >= p.gamma || c >= p.xi) continue;
-        const size_t i = (size_t)r + (size_t)p.gamma * c;
-        const float gv = em ? g[i] : 0.0f;
+        const int row = wv + 4 * j, c = s0.y + row;
+        if (r >= s1.x || c >= s1.y) continue;
+        const size_t i = (size_t)r + (size_t)s1.x * c;
+        const float gv = em ? g[(size_t)s1.z + i] : 0.0f;
         float v = 0.0f;
-        for (int ch = 0; ch < sm.y; ++ch) v += partials[((size_t)sm.z + ch) * (TX * TY) + row * TX + lane];
+        for (int ch = 0; ch < s0.z; ++ch) v += partials[((size_t)s0.w + ch) * (TX * TY) + row * TX + lane];
         if (em) v = v > 0.0f ? gv / v : 0.0f;
-        out[i] = v;
+        out[(size_t)s1.w + i] = v;
     }
 }
 
+// Back projection (+ EM update).  Units: (frame, wavelength, field-stop tile).
 template <int B>
-__global__ void __launch_bounds__(64 * Win<B>::MAXW) k_adjoint(const KParams p, const int4 *__restrict__ items,
-                                                  const float *__restrict__ box_w, const float *__restrict__ hsum,
-                                                  const float *__restrict__ u, const float *fin, float *out, int em) {
+__global__ void __launch_bounds__(64 * Win<B>::MAXW) k_adjoint(const int4 *__restrict__ meta,
+                                                               const int4 *__restrict__ items, const int stride,
+                                                               const int n_units, const float *__restrict__ box_w,
+                                                               const float *__restrict__ hsum,
+                                                               const float *__restrict__ u, const float *fin,
+                                                               float *out, const int em) {
     using Wn = Win<B>;
     extern __shared__ float4 lds4[];
     float *lds = reinterpret_cast<float *>(lds4);
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nw = blockDim.x >> 6;
-    const int per = p.nbx * p.nby;
-    const int s = blockIdx.x / per, vt = blockIdx.x - s * per;
-    const int stride = p.adj_stride;
-    const int4 *list = items + (size_t)s * stride;
-    int k = wv;
-    int4 rec0 = record(list, k, stride);
-    int4 rec1 = record(list, k + nw, stride);
-    const int x0 = (vt % p.nbx) * TX, y0 = (vt / p.nbx) * TY;
     float *S = lds + wv * Wn::WREG;
     const int lx = lane & 15, ly = lane >> 4;
-    const __amdgpu_buffer_rsrc_t ur = rsrc(u, p.n);
-    const int x = x0 + lane;
-    const size_t sb = (size_t)s * p.ell;
 
-    float fpre[kRowsPerWave];
-    FOR_OWN_ROWS(j, row) {
-        const int y = y0 + row;
-        fpre[j] = (em && x < p.a && y < p.alpha) ? fin[sb + (size_t)x + (size_t)p.a * y] : 0.0f;
-    }
-    const float hs = hsum[s];
+    for (int unit = blockIdx.x; unit < n_units; unit += gridDim.x) {
+        const int4 m0 = meta[3 * unit], m1 = meta[3 * unit + 1], m2 = meta[3 * unit + 2];
+        const int4 *list = items + (size_t)m0.z * stride;
+        int k = wv;
+        int4 rec0 = record(list, k, stride);
+        int4 rec1 = record(list, k + nw, stride);
+        int4 rec2 = record(list, k + 2 * nw, stride);
+        const Geo geo{m1.x, m1.y, m1.z, m1.w};
+        const int x0 = m0.x, y0 = m0.y;
+        const __amdgpu_buffer_rsrc_t ur = rsrc(u + (size_t)(unsigned)m2.x, geo.gamma * geo.xi);
+        const int x = x0 + lane;
+        const size_t sb = (size_t)(unsigned)m0.w;
 
-    float acc[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[a][q] = 0.0f;
-
-    int4 rec2 = record(list, k + 2 * nw, stride);
-    Pending<B> pa, pb;
-    if (rec0.w >= 0) load_adjoint<B>(pa, ur, box_w, p, rec0.x + x0, rec0.y + y0, rec0.w, lane);
-    if (rec1.w >= 0) load_adjoint<B>(pb, ur, box_w, p, rec1.x + x0, rec1.y + y0, rec1.w, lane);
-    while (rec0.w >= 0) {
-        store_window<B>(S, pa, lane);
-        wave_lds_sync();
-        int4 rec3 = record(list, k + 3 * nw, stride);
-        if (rec2.w >= 0) load_adjoint<B>(pa, ur, box_w, p, rec2.x + x0, rec2.y + y0, rec2.w, lane);
-        correlate<B>(acc, S, lx, ly);
-        wave_lds_sync();
-        k += nw;
-        rec0 = rec1;
-        rec1 = rec2;
-        rec2 = rec3;
-        if (rec0.w < 0) break;
-        store_window<B>(S, pb, lane);
-        wave_lds_sync();
-        rec3 = record(list, k + 3 * nw, stride);
-        if (rec2.w >= 0) load_adjoint<B>(pb, ur, box_w, p, rec2.x + x0, rec2.y + y0, rec2.w, lane);
-        correlate<B>(acc, S, lx, ly);
-        wave_lds_sync();
-        k += nw;
-        rec0 = rec1;
-        rec1 = rec2;
-        rec2 = rec3;
-    }
-
-    park_tile(acc, lds, wv, lx, ly);
-    FOR_OWN_ROWS(j, row) {
-        const int y = y0 + row;
-        float v = row_sum(lds, nw, row, lane);
-        if (x < p.a && y < p.alpha) {
-            if (em) v = hs != 0.0f ? (fpre[j] * v) / hs : 0.0f;
-            out[sb + (size_t)x + (size_t)p.a * y] = v;
+        float fpre[kRowsPerWave];
+        FOR_OWN_ROWS(j, row) {
+            const int y = y0 + row;
+            fpre[j] = (em && x < geo.a && y < geo.alpha) ? fin[sb + (size_t)x + (size_t)geo.a * y] : 0.0f;
         }
+        const float hs = hsum[m0.z];
+
+        float acc[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[a][q] = 0.0f;
+
+        Pending<B> pa, pb;
+        if (rec0.w >= 0) load_adjoint<B>(pa, ur, box_w, geo, rec0.x + x0, rec0.y + y0, rec0.w, lane);
+        if (rec1.w >= 0) load_adjoint<B>(pb, ur, box_w, geo, rec1.x + x0, rec1.y + y0, rec1.w, lane);
+        while (rec0.w >= 0) {
+            store_window<B>(S, pa, lane);
+            wave_lds_sync();
+            int4 rec3 = record(list, k + 3 * nw, stride);
+            if (rec2.w >= 0) load_adjoint<B>(pa, ur, box_w, geo, rec2.x + x0, rec2.y + y0, rec2.w, lane);
+            correlate<B>(acc, S, lx, ly);
+            wave_lds_sync();
+            k += nw;
+            rec0 = rec1;
+            rec1 = rec2;
+            rec2 = rec3;
+            if (rec0.w < 0) break;
+            store_window<B>(S, pb, lane);
+            wave_lds_sync();
+            rec3 = record(list, k + 3 * nw, stride);
+            if (rec2.w >= 0) load_adjoint<B>(pb, ur, box_w, geo, rec2.x + x0, rec2.y + y0, rec2.w, lane);
+            correlate<B>(acc, S, lx, ly);
+            wave_lds_sync();
+            k += nw;
+            rec0 = rec1;
+            rec1 = rec2;
+            rec2 = rec3;
+        }
+
+        park_tile(acc, lds, wv, lx, ly);
+        FOR_OWN_ROWS(j, row) {
+            const int y = y0 + row;
+            float v = row_sum(lds, nw, row, lane);
+            if (x < geo.a && y < geo.alpha) {
+                if (em) v = hs != 0.0f ? (fpre[j] * v) / hs : 0.0f;
+                out[sb + (size_t)x + (size_t)geo.a * y] = v;
+            }
+        }
+        __syncthreads();   // the next unit reuses the LDS regions
     }
 }
 
@@ -531,41 +549,65 @@ int enable_large_lds() {
     return (int)err;
 }
 
+int device_cus() {
+    static std::once_flag once;
+    static int cus = 256;
+    std::call_once(once, []() {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess &&
+            prop.multiProcessorCount > 0)
+            cus = prop.multiProcessorCount;
+    });
+    return cus;
+}
+
+// Grid of a launch over n_units work units.  By default one workgroup per
+// unit: the hardware dispatcher then hands the next unit to whichever compute
+// unit frees first.  With `persistent`, only as many workgroups as fit on
+// the chip at once (by LDS and waves per CU) are launched and each walks the
+// unit list with a grid stride.
+int grid_for(int n_units, size_t lds_bytes, int waves, bool persistent) {
+    if (!persistent) return std::max(1, n_units);
+    const int by_lds = lds_bytes ? (int)std::min<size_t>(8, (160 * 1024) / lds_bytes) : 8;
+    const int by_waves = std::max(1, 32 / waves);
+    const int resident = std::max(1, std::min(by_lds, by_waves));
+    return std::max(1, std::min(n_units, device_cus() * resident));
+}
+
 template <int B>
-int forward_B(const ctis_plan *pl, const float *f, const float *g, float *out, bool em, void *workspace,
+int forward_B(const DevWork &w, const float *f, const float *g, float *out, bool em, void *workspace,
               hipStream_t st) {
-    const FwdList &L = em ? pl->dt.fwd_em : pl->dt.fwd_full;
+    const DevList &L = em ? w.fwd_em : w.fwd_full;
     if (L.n_units == 0) return 0;
     const size_t lds = (size_t)L.waves * Win<B>::WREG * sizeof(float);
     if (lds > 65536) {
         const int e = enable_large_lds<B>();
         if (e) return e;
     }
-    float *partials = nullptr;
-    if (em && pl->ht.partial_slots > 0) partials = (float *)((char *)workspace + pl->ws_partials);
-    hipLaunchKernelGGL(k_forward<B>, dim3(L.n_units), dim3(64 * L.waves), lds, st, pl->kp, L.unit_meta, L.items,
-                       L.stride, pl->dt.box_wf, f, g, out, em ? 1 : 0, partials);
+    float *partials = (em && w.n_split > 0) ? (float *)((char *)workspace + w.partials_off) : nullptr;
+    hipLaunchKernelGGL(k_forward<B>, dim3(grid_for(L.n_units, lds, L.waves, w.persistent)), dim3(64 * L.waves), lds, st,
+                       L.meta, L.items, L.stride, L.n_units, w.box_wf, f, g, out, partials, em ? 1 : 0);
     if (partials) {
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return (int)e;
-        hipLaunchKernelGGL(k_finish_split, dim3(pl->ht.n_split_tiles), dim3(256), 0, st, pl->kp, pl->dt.split_meta,
-                           (const float *)partials, g, out, 1);
+        hipLaunchKernelGGL(k_finish_split, dim3(w.n_split), dim3(256), 0, st, w.split_meta, (const float *)partials,
+                           g, out, 1);
     }
     return (int)hipGetLastError();
 }
 
 template <int B>
-int adjoint_B(const ctis_plan *pl, const float *u, const float *fin, float *out, bool em, hipStream_t st) {
-    const int nwg = pl->kp.nbx * pl->kp.nby * pl->w;
-    const int nw = pl->waves_adj;
-    const size_t lds = (size_t)nw * Win<B>::WREG * sizeof(float);
+int adjoint_B(const DevWork &w, const float *u, const float *fin, float *out, bool em, hipStream_t st) {
+    const DevList &L = w.adj;
+    if (L.n_units == 0) return 0;
+    const size_t lds = (size_t)L.waves * Win<B>::WREG * sizeof(float);
     if (lds > 65536) {
         const int e = enable_large_lds<B>();
         if (e) return e;
     }
-    const DevTables &t = pl->dt;
-    hipLaunchKernelGGL(k_adjoint<B>, dim3(nwg), dim3(64 * nw), lds, st, pl->kp, t.adj_items, t.box_w, t.h, u, fin,
-                       out, em ? 1 : 0);
+    hipLaunchKernelGGL(k_adjoint<B>, dim3(grid_for(L.n_units, lds, L.waves, w.persistent)), dim3(64 * L.waves), lds, st,
+                       L.meta, L.items, L.stride, L.n_units, w.box_w, w.h, u, fin, out, em ? 1 : 0);
     return (int)hipGetLastError();
 }
 
@@ -574,33 +616,33 @@ int adjoint_B(const ctis_plan *pl, const float *u, const float *fin, float *out,
 int max_waves(int B) { return B <= 5 ? Win<1>::MAXW : Win<8>::MAXW; }
 int min_waves() { return kMinWaves; }
 
-int launch_forward(const ctis_plan *p, const float *f, const float *g, float *out, bool em, void *workspace,
+int launch_forward(const DevWork &w, const float *f, const float *g, float *out, bool em, void *workspace,
                    void *stream) {
     hipStream_t st = (hipStream_t)stream;
-    switch (p->ht.B) {
-        case 1: return forward_B<1>(p, f, g, out, em, workspace, st);
-        case 2: return forward_B<2>(p, f, g, out, em, workspace, st);
-        case 3: return forward_B<3>(p, f, g, out, em, workspace, st);
-        case 4: return forward_B<4>(p, f, g, out, em, workspace, st);
-        case 5: return forward_B<5>(p, f, g, out, em, workspace, st);
-        case 6: return forward_B<6>(p, f, g, out, em, workspace, st);
-        case 7: return forward_B<7>(p, f, g, out, em, workspace, st);
-        case 8: return forward_B<8>(p, f, g, out, em, workspace, st);
+    switch (w.B) {
+        case 1: return forward_B<1>(w, f, g, out, em, workspace, st);
+        case 2: return forward_B<2>(w, f, g, out, em, workspace, st);
+        case 3: return forward_B<3>(w, f, g, out, em, workspace, st);
+        case 4: return forward_B<4>(w, f, g, out, em, workspace, st);
+        case 5: return forward_B<5>(w, f, g, out, em, workspace, st);
+        case 6: return forward_B<6>(w, f, g, out, em, workspace, st);
+        case 7: return forward_B<7>(w, f, g, out, em, workspace, st);
+        case 8: return forward_B<8>(w, f, g, out, em, workspace, st);
     }
     return (int)hipErrorInvalidValue;
 }
 
-int launch_adjoint(const ctis_plan *p, const float *u, const float *fin, float *out, bool em, void *stream) {
+int launch_adjoint(const DevWork &w, const float *u, const float *fin, float *out, bool em, void *stream) {
     hipStream_t st = (hipStream_t)stream;
-    switch (p->ht.B) {
-        case 1: return adjoint_B<1>(p, u, fin, out, em, st);
-        case 2: return adjoint_B<2>(p, u, fin, out, em, st);
-        case 3: return adjoint_B<3>(p, u, fin, out, em, st);
-        case 4: return adjoint_B<4>(p, u, fin, out, em, st);
-        case 5: return adjoint_B<5>(p, u, fin, out, em, st);
-        case 6: return adjoint_B<6>(p, u, fin, out, em, st);
-        case 7: return adjoint_B<7>(p, u, fin, out, em, st);
-        case 8: return adjoint_B<8>(p, u, fin, out, em, st);
+    switch (w.B) {
+        case 1: return adjoint_B<1>(w, u, fin, out, em, st);
+        case 2: return adjoint_B<2>(w, u, fin, out, em, st);
+        case 3: return adjoint_B<3>(w, u, fin, out, em, st);
+        case 4: return adjoint_B<4>(w, u, fin, out, em, st);
+        case 5: return adjoint_B<5>(w, u, fin, out, em, st);
+        case 6: return adjoint_B<6>(w, u, fin, out, em, st);
+        case 7: return adjoint_B<7>(w, u, fin, out, em, st);
+        case 8: return adjoint_B<8>(w, u, fin, out, em, st);
     }
     return (int)hipErrorInvalidValue;
 }

@@ -299,18 +299,6 @@ ctis_status build_host_tables(ctis_plan *p, const int64_t *lambda_ptr, const int
     T.nby = (int32_t)ceil_div(alpha, kTileSlow);
     if ((int64_t)T.nbx * T.nby * w > INT32_MAX) return fail(CTIS_E_TOO_LARGE, "too many field-stop tiles");
 
-    // -- kernel parameters ---------------------------------------------------------
-    KParams &k = p->kp;
-    k.a = a;
-    k.alpha = alpha;
-    k.w = w;
-    k.gamma = gamma;
-    k.xi = xi;
-    k.ell = (int32_t)p->ell;
-    k.n = (int32_t)n;
-    k.ntr = T.ntr;
-    k.nbx = T.nbx;
-    k.nby = T.nby;
     int32_t max_boxes = 0, max_items = 0;
     int64_t active_items = 0;
     for (int32_t s = 0; s < w; ++s)
@@ -319,102 +307,179 @@ ctis_status build_host_tables(ctis_plan *p, const int64_t *lambda_ptr, const int
         max_items = std::max(max_items, count(t));
         active_items += count(t);
     }
-    // one wavefront per two boxes of the heaviest unit: each wave then has a
-    // second window in flight while it computes the first
-    auto waves_for = [&](int32_t work) { return std::max(min_waves(), std::min(max_waves(B), (work + 1) / 2)); };
+    T.max_items = max_items;
+    T.max_boxes = max_boxes;
     // EM chunk: a tile is split over several workgroups only when it holds
     // more than 64 boxes (4 per wave) and more than twice the boxes an
     // average compute unit gets (256 CUs); otherwise splitting only adds the
     // partial-tile pass
     T.chunk = (int32_t)std::max<int64_t>(64, 2 * ((active_items + 255) / 256));
-    auto build_list = [&](HostList &L, int32_t n_tiles_in_list, int32_t chunk, int32_t &slots) -> ctis_status {
-        L.stride = std::max(1, chunk);
-        L.unit_meta.clear();
-        L.items.clear();
-        for (int32_t u = 0; u < n_tiles_in_list; ++u) {
-            const int32_t tile = T.tile_order[(size_t)u];
-            const int32_t cnt = count(tile), b0 = T.tile_item_ptr[(size_t)tile];
-            const int32_t nch = std::max(1, (cnt + L.stride - 1) / L.stride);
-            const int32_t pbase = nch > 1 ? slots : -1;
-            if (nch > 1) {
-                if (&slots == &T.partial_slots) T.split_meta.insert(T.split_meta.end(), {tile, nch, pbase, 0});
-                slots += nch;
+    return CTIS_OK;
+}
+
+namespace {
+
+int32_t waves_for(int32_t work, int B) {
+    // one wavefront per two boxes of the heaviest unit, so that each wave
+    // has a window in flight while it computes another
+    return std::max(min_waves(), std::min(max_waves(B), (work + 1) / 2));
+}
+
+void push4(std::vector<int32_t> &v, int32_t a, int32_t b, int32_t c, int32_t d) {
+    v.push_back(a);
+    v.push_back(b);
+    v.push_back(c);
+    v.push_back(d);
+}
+
+struct UnitRef {
+    int32_t frame, tile, chunk, n_chunks, slot, work;
+};
+
+}  // namespace
+
+ctis_status build_work(const std::vector<FrameRef> &frames, bool with_full, HostWork &hw) {
+    hw = HostWork{};
+    if (frames.empty()) return fail(CTIS_E_ARG, "no frames");
+    hw.B = frames[0].plan->ht.B;
+    const int B = hw.B;
+    int32_t box_base = 0, lambda_base = 0, max_chunk_items = 0, max_full_items = 0, max_boxes = 0;
+    std::vector<int32_t> fbox(frames.size()), flam(frames.size());
+    for (size_t k = 0; k < frames.size(); ++k) {
+        const HostTables &T = frames[k].plan->ht;
+        if (T.B != B) return fail(CTIS_E_ARG, "all frames of a batch need the same box side B");
+        fbox[k] = box_base;
+        flam[k] = lambda_base;
+        box_base += (int32_t)T.box_lambda.size();
+        lambda_base += frames[k].plan->w;
+        hw.box_w.insert(hw.box_w.end(), T.box_w.begin(), T.box_w.end());
+        hw.box_wf.insert(hw.box_wf.end(), T.box_wf.begin(), T.box_wf.end());
+        hw.h.insert(hw.h.end(), T.h.begin(), T.h.end());
+        max_chunk_items = std::max(max_chunk_items, std::min(T.max_items, T.chunk));
+        max_full_items = std::max(max_full_items, T.max_items);
+        max_boxes = std::max(max_boxes, T.max_boxes);
+        hw.u_floats = std::max<int64_t>(hw.u_floats, frames[k].u_base + frames[k].plan->n);
+    }
+    if ((size_t)box_base * B * B > (size_t)INT32_MAX) return fail(CTIS_E_TOO_LARGE, "too many boxes");
+
+    // forward lists: units of every frame, heaviest first (a stable order)
+    auto build_fwd = [&](HostList &L, bool em, int32_t stride) -> ctis_status {
+        std::vector<UnitRef> units;
+        for (size_t k = 0; k < frames.size(); ++k) {
+            const HostTables &T = frames[k].plan->ht;
+            const int32_t ntl = em ? T.n_active : T.n_tiles;
+            for (int32_t u = 0; u < ntl; ++u) {
+                const int32_t tile = T.tile_order[(size_t)u];
+                const int32_t cnt = T.tile_item_ptr[(size_t)tile + 1] - T.tile_item_ptr[(size_t)tile];
+                const int32_t nch = em ? std::max(1, (cnt + stride - 1) / stride) : 1;
+                const int32_t slot0 = nch > 1 ? hw.partial_slots : -1;
+                if (nch > 1) {
+                    push4(hw.split_meta, (tile % T.ntr) * kTileFast, (tile / T.ntr) * kTileSlow, nch, slot0);
+                    push4(hw.split_meta, frames[k].plan->gamma, frames[k].plan->xi, (int32_t)frames[k].g_base,
+                          (int32_t)frames[k].u_base);
+                    hw.partial_slots += nch;
+                    hw.n_split++;
+                }
+                for (int32_t c = 0; c < nch; ++c)
+                    units.push_back(UnitRef{(int32_t)k, tile, c, nch, nch > 1 ? slot0 + c : -1,
+                                            std::min(stride, cnt - c * stride)});
             }
-            const int32_t r0 = (tile % T.ntr) * kTileFast, c0 = (tile / T.ntr) * kTileSlow;
-            for (int32_t c = 0; c < nch; ++c) {
-                L.unit_meta.insert(L.unit_meta.end(), {tile, c, nch, pbase});
-                for (int32_t k = 0; k < L.stride; ++k) {
-                    const int32_t idx = c * L.stride + k;
-                    if (idx < cnt) {
-                        const int32_t b = T.item_box[(size_t)(b0 + idx)];
-                        L.items.insert(L.items.end(), {r0 - (B - 1) - T.box_rc[2 * (size_t)b],
-                                                       c0 - (B - 1) - T.box_rc[2 * (size_t)b + 1],
-                                                       T.box_lambda[(size_t)b], b});
-                    } else {
-                        L.items.insert(L.items.end(), {0, 0, 0, -1});
-                    }
+        }
+        std::stable_sort(units.begin(), units.end(), [](const UnitRef &x, const UnitRef &y) { return x.work > y.work; });
+        L.stride = std::max(1, stride);
+        L.meta.clear();
+        L.items.clear();
+        for (const UnitRef &ur : units) {
+            const FrameRef &fr = frames[(size_t)ur.frame];
+            const ctis_plan *pl = fr.plan;
+            const HostTables &T = pl->ht;
+            const int32_t r0 = (ur.tile % T.ntr) * kTileFast, c0 = (ur.tile / T.ntr) * kTileSlow;
+            push4(L.meta, r0, c0, ur.n_chunks, ur.slot);
+            push4(L.meta, pl->a, pl->alpha, pl->gamma, pl->xi);
+            push4(L.meta, (int32_t)fr.g_base, em ? (int32_t)fr.u_base : (int32_t)fr.g_base, 0, 0);
+            const int32_t b0 = T.tile_item_ptr[(size_t)ur.tile];
+            const int32_t cnt = T.tile_item_ptr[(size_t)ur.tile + 1] - b0;
+            for (int32_t k = 0; k < L.stride; ++k) {
+                const int32_t idx = ur.chunk * L.stride + k;
+                if (k < ur.work && idx < cnt) {
+                    const int32_t b = T.item_box[(size_t)(b0 + idx)];
+                    const int32_t s = T.box_lambda[(size_t)b];
+                    push4(L.items, r0 - (B - 1) - T.box_rc[2 * (size_t)b], c0 - (B - 1) - T.box_rc[2 * (size_t)b + 1],
+                          (int32_t)(fr.f_base + (int64_t)s * pl->ell), fbox[(size_t)ur.frame] + b);
+                } else {
+                    push4(L.items, 0, 0, 0, -1);
                 }
             }
             if (L.items.size() > (size_t)INT32_MAX) return fail(CTIS_E_TOO_LARGE, "forward work list too large");
         }
-        L.n_units = (int32_t)(L.unit_meta.size() / 4);
+        L.n_units = (int32_t)(L.meta.size() / 12);
         return CTIS_OK;
     };
-    int32_t unused = 0;
-    T.partial_slots = 0;
-    T.split_meta.clear();
-    ctis_status st = build_list(T.fwd_full, T.n_tiles, std::max(1, max_items), unused);
+    int32_t chunk = 1 << 30;
+    for (const FrameRef &fr : frames) chunk = std::min(chunk, fr.plan->ht.chunk);
+    ctis_status st = CTIS_OK;
+    if (with_full) {
+        const int32_t saved_slots = hw.partial_slots, saved_split = hw.n_split;
+        st = build_fwd(hw.fwd_full, false, std::max(1, max_full_items));
+        if (st != CTIS_OK) return st;
+        hw.partial_slots = saved_slots;
+        hw.n_split = saved_split;
+        hw.fwd_full.waves = waves_for(max_full_items, B);
+    }
+    st = build_fwd(hw.fwd_em, true, chunk);
     if (st != CTIS_OK) return st;
-    st = build_list(T.fwd_em, T.n_active, T.chunk, T.partial_slots);
-    if (st != CTIS_OK) return st;
-    T.n_split_tiles = (int32_t)(T.split_meta.size() / 4);
-    T.fwd_full.waves = waves_for(max_items);
-    T.fwd_em.waves = waves_for(std::min(max_items, T.chunk));
-    p->waves_adj = waves_for(max_boxes);
-    if ((int64_t)max_boxes * w > INT32_MAX / 4) return fail(CTIS_E_TOO_LARGE, "work tables too large");
-    k.adj_stride = std::max(1, max_boxes);
-    // EM workspace: u (n floats), then the partial tiles of split FPA tiles
-    auto up256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    p->ws_partials = up256((size_t)n * sizeof(float));
-    p->workspace_bytes = p->ws_partials + (size_t)T.partial_slots * kTileFast * kTileSlow * sizeof(float);
+    hw.fwd_em.waves = waves_for(max_chunk_items, B);
+
+    // adjoint: units (frame, wavelength, field-stop tile); records per global wavelength
+    HostList &A = hw.adj;
+    A.stride = std::max(1, max_boxes);
+    A.items.assign((size_t)4 * lambda_base * A.stride, 0);
+    for (size_t k = 0; k < frames.size(); ++k) {
+        const ctis_plan *pl = frames[k].plan;
+        const HostTables &T = pl->ht;
+        for (int32_t s = 0; s < pl->w; ++s) {
+            const int32_t gs = flam[k] + s;
+            const int32_t b0 = T.lambda_box_ptr[(size_t)s], b1 = T.lambda_box_ptr[(size_t)s + 1];
+            for (int32_t j = 0; j < A.stride; ++j) {
+                int32_t *rec = &A.items[(size_t)4 * ((size_t)gs * A.stride + j)];
+                if (b0 + j < b1) {
+                    rec[0] = T.box_rc[2 * (size_t)(b0 + j)];
+                    rec[1] = T.box_rc[2 * (size_t)(b0 + j) + 1];
+                    rec[3] = fbox[k] + b0 + j;
+                } else {
+                    rec[3] = -1;
+                }
+            }
+            for (int32_t vt = 0; vt < T.nbx * T.nby; ++vt) {
+                push4(A.meta, (vt % T.nbx) * kTileFast, (vt / T.nbx) * kTileSlow, gs,
+                      (int32_t)(frames[k].f_base + (int64_t)s * pl->ell));
+                push4(A.meta, pl->a, pl->alpha, pl->gamma, pl->xi);
+                push4(A.meta, (int32_t)frames[k].u_base, 0, 0, 0);
+            }
+        }
+    }
+    A.n_units = (int32_t)(A.meta.size() / 12);
+    A.waves = waves_for(max_boxes, B);
     return CTIS_OK;
 }
 
-ctis_status upload_tables(ctis_plan *p) {
-    const HostTables &T = p->ht;
+ctis_status upload_work(const HostWork &hw, DevWork &dw) {
     struct Part {
         const void *src;
         size_t bytes;
         size_t off;
     };
-    const int32_t as = p->kp.adj_stride;
-    // adjoint: one list per wavelength
-    std::vector<int32_t> adj((size_t)4 * p->w * as, 0);
-    for (int32_t s = 0; s < p->w; ++s) {
-        const int32_t b0 = T.lambda_box_ptr[(size_t)s], b1 = T.lambda_box_ptr[(size_t)s + 1];
-        for (int32_t k = 0; k < as; ++k) {
-            int32_t *rec = &adj[(size_t)4 * ((size_t)s * as + k)];
-            if (b0 + k < b1) {
-                const int32_t b = b0 + k;
-                rec[0] = T.box_rc[2 * (size_t)b];
-                rec[1] = T.box_rc[2 * (size_t)b + 1];
-                rec[2] = s;
-                rec[3] = b;
-            } else {
-                rec[3] = -1;
-            }
-        }
-    }
     std::vector<Part> parts = {
-        {T.fwd_full.unit_meta.data(), T.fwd_full.unit_meta.size() * 4, 0},
-        {T.fwd_full.items.data(), T.fwd_full.items.size() * 4, 0},
-        {T.fwd_em.unit_meta.data(), T.fwd_em.unit_meta.size() * 4, 0},
-        {T.fwd_em.items.data(), T.fwd_em.items.size() * 4, 0},
-        {adj.data(), adj.size() * 4, 0},
-        {T.split_meta.data(), T.split_meta.size() * 4, 0},
-        {T.box_w.data(), T.box_w.size() * 4, 0},
-        {T.box_wf.data(), T.box_wf.size() * 4, 0},
-        {T.h.data(), T.h.size() * 4, 0},
+        {hw.fwd_full.meta.data(), hw.fwd_full.meta.size() * 4, 0},
+        {hw.fwd_full.items.data(), hw.fwd_full.items.size() * 4, 0},
+        {hw.fwd_em.meta.data(), hw.fwd_em.meta.size() * 4, 0},
+        {hw.fwd_em.items.data(), hw.fwd_em.items.size() * 4, 0},
+        {hw.split_meta.data(), hw.split_meta.size() * 4, 0},
+        {hw.adj.meta.data(), hw.adj.meta.size() * 4, 0},
+        {hw.adj.items.data(), hw.adj.items.size() * 4, 0},
+        {hw.box_w.data(), hw.box_w.size() * 4, 0},
+        {hw.box_wf.data(), hw.box_wf.size() * 4, 0},
+        {hw.h.data(), hw.h.size() * 4, 0},
     };
     size_t total = 0;
     for (auto &pt : parts) {
@@ -423,32 +488,47 @@ ctis_status upload_tables(ctis_plan *p) {
     }
     void *mem = nullptr;
     hipError_t e = hipMalloc(&mem, total);
-    if (e != hipSuccess) return fail(CTIS_E_NOMEM, std::string("hipMalloc of plan tables: ") + hipGetErrorString(e));
+    if (e != hipSuccess) return fail(CTIS_E_NOMEM, std::string("hipMalloc of work tables: ") + hipGetErrorString(e));
     for (const auto &pt : parts) {
         if (!pt.bytes) continue;
         e = hipMemcpy((char *)mem + pt.off, pt.src, pt.bytes, hipMemcpyHostToDevice);
         if (e != hipSuccess) {
             (void)hipFree(mem);
-            return fail(CTIS_E_HIP, std::string("hipMemcpy of plan tables: ") + hipGetErrorString(e));
+            return fail(CTIS_E_HIP, std::string("hipMemcpy of work tables: ") + hipGetErrorString(e));
         }
     }
-    p->dev_mem = mem;
     auto at = [&](int k) { return (const void *)((const char *)mem + parts[(size_t)k].off); };
-    auto list = [&](FwdList &L, const HostList &H, int k0) {
-        L.unit_meta = (const int4 *)at(k0);
+    auto list = [&](DevList &L, const HostList &H, int k0) {
+        L.meta = (const int4 *)at(k0);
         L.items = (const int4 *)at(k0 + 1);
         L.n_units = H.n_units;
         L.stride = H.stride;
         L.waves = H.waves;
     };
-    list(p->dt.fwd_full, T.fwd_full, 0);
-    list(p->dt.fwd_em, T.fwd_em, 2);
-    p->dt.adj_items = (const int4 *)at(4);
-    p->dt.split_meta = (const int4 *)at(5);
-    p->dt.box_w = (const float *)at(6);
-    p->dt.box_wf = (const float *)at(7);
-    p->dt.h = (const float *)at(8);
+    dw = DevWork{};
+    dw.B = hw.B;
+    list(dw.fwd_full, hw.fwd_full, 0);
+    list(dw.fwd_em, hw.fwd_em, 2);
+    dw.split_meta = (const int4 *)at(4);
+    dw.n_split = hw.n_split;
+    dw.adj.meta = (const int4 *)at(5);
+    dw.adj.items = (const int4 *)at(6);
+    dw.adj.n_units = hw.adj.n_units;
+    dw.adj.stride = hw.adj.stride;
+    dw.adj.waves = hw.adj.waves;
+    dw.box_w = (const float *)at(7);
+    dw.box_wf = (const float *)at(8);
+    dw.h = (const float *)at(9);
+    auto up256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    dw.partials_off = up256((size_t)hw.u_floats * sizeof(float));
+    dw.workspace_bytes = dw.partials_off + (size_t)hw.partial_slots * kTileFast * kTileSlow * sizeof(float);
+    dw.mem = mem;
     return CTIS_OK;
+}
+
+void free_work(DevWork &dw) {
+    if (dw.mem) (void)hipFree(dw.mem);
+    dw = DevWork{};
 }
 
 }  // namespace ctis

@@ -27,7 +27,8 @@ STATUS_NAMES = {0: "CTIS_OK", 1: "CTIS_E_ARG", 2: "CTIS_E_INDEX", 3: "CTIS_E_VAL
 EXPORTED = ["ctis_plan_create", "ctis_plan_destroy", "ctis_plan_get_info",
             "ctis_plan_lambda_sums", "ctis_plan_export_boxes", "ctis_plan_export_worklist",
             "ctis_forward", "ctis_adjoint", "ctis_em_iterate", "ctis_em_forward_ratio", "ctis_em_adjoint_update", "ctis_status_str",
-            "ctis_last_error", "ctis_version"]
+            "ctis_last_error", "ctis_version", "ctis_batch_create", "ctis_batch_destroy",
+            "ctis_batch_get_info", "ctis_batch_forward", "ctis_batch_adjoint", "ctis_batch_em_iterate"]
 
 
 def CTIS_PLAN_BOX(b: int) -> int:
@@ -52,6 +53,14 @@ class _Info(ctypes.Structure):
                 ("n_items", ctypes.c_int64), ("workspace_bytes", ctypes.c_size_t),
                 ("nonnegative", ctypes.c_int32), ("device", ctypes.c_int32),
                 ("waves_forward", ctypes.c_int32), ("waves_adjoint", ctypes.c_int32)]
+
+
+class _BatchInfo(ctypes.Structure):
+    _fields_ = [("n_frames", ctypes.c_int32), ("box", ctypes.c_int32),
+                ("m_total", ctypes.c_int64), ("n_total", ctypes.c_int64),
+                ("forward_units", ctypes.c_int64), ("adjoint_units", ctypes.c_int64),
+                ("waves_forward", ctypes.c_int32), ("waves_adjoint", ctypes.c_int32),
+                ("workspace_bytes", ctypes.c_size_t)]
 
 
 @dataclasses.dataclass(frozen=True)
@@ -119,6 +128,18 @@ def load_library(path: str | None = None):
         L.ctis_em_forward_ratio.restype = st
         L.ctis_em_adjoint_update.argtypes = [vp, vp, sz, vp, vp, vp]
         L.ctis_em_adjoint_update.restype = st
+        L.ctis_batch_create.argtypes = [ctypes.POINTER(vp), vp, i32, u32]
+        L.ctis_batch_create.restype = st
+        L.ctis_batch_destroy.argtypes = [vp]
+        L.ctis_batch_destroy.restype = None
+        L.ctis_batch_get_info.argtypes = [vp, ctypes.POINTER(_BatchInfo)]
+        L.ctis_batch_get_info.restype = st
+        L.ctis_batch_forward.argtypes = [vp, vp, vp, vp]
+        L.ctis_batch_forward.restype = st
+        L.ctis_batch_adjoint.argtypes = [vp, vp, vp, vp]
+        L.ctis_batch_adjoint.restype = st
+        L.ctis_batch_em_iterate.argtypes = [vp, vp, vp, i32, vp, sz, vp]
+        L.ctis_batch_em_iterate.restype = st
         L.ctis_status_str.argtypes = [st]
         L.ctis_status_str.restype = ctypes.c_char_p
         L.ctis_last_error.argtypes = []
@@ -329,3 +350,91 @@ class Plan:
                                      workspace.numel() * workspace.element_size(), _stream(torch, self.device))
         _check(self._L, st, "ctis_em_iterate")
         return f
+
+
+class Batch:
+    """Frames with their own plans (uneven sizes), reconstructed together: one
+    forward+ratio and one adjoint+update launch per EM iteration for all
+    frames.  Frame k's datacube is f_all[f_offsets[k] : f_offsets[k] + m_k]
+    and its image g_all[g_offsets[k] : ...] (see include/ctis.h)."""
+
+    def __init__(self, plans, waves_forward: int = 0, waves_adjoint: int = 0, persistent: bool = False):
+        self._L = load_library()
+        self._handle = None
+        self.plans = list(plans)
+        if not self.plans:
+            raise ValueError("a batch needs at least one plan")
+        for p in self.plans:
+            p._need_device()
+        self.device = self.plans[0].device
+        arr = (ctypes.c_void_p * len(self.plans))(*[p._handle.value for p in self.plans])
+        flags = (int(waves_forward) & 0x1F) | ((int(waves_adjoint) & 0x1F) << 5) | (0x400 if persistent else 0)
+        h = ctypes.c_void_p()
+        _check(self._L, self._L.ctis_batch_create(ctypes.byref(h), ctypes.cast(arr, ctypes.c_void_p),
+                                                  len(self.plans), flags), "ctis_batch_create")
+        self._handle = h
+        inf = _BatchInfo()
+        _check(self._L, self._L.ctis_batch_get_info(self._handle, ctypes.byref(inf)), "ctis_batch_get_info")
+        self.info = {k: getattr(inf, k) for k, _ in _BatchInfo._fields_}
+        m = np.array([p.info.m for p in self.plans], np.int64)
+        n = np.array([p.info.n for p in self.plans], np.int64)
+        self.f_offsets = np.concatenate([[0], np.cumsum(m)])
+        self.g_offsets = np.concatenate([[0], np.cumsum(n)])
+
+    def close(self):
+        if self._handle:
+            _torch().cuda.synchronize(self.device)
+            self._L.ctis_batch_destroy(self._handle)
+            self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def frame_f(self, f_all, k):
+        return f_all[self.f_offsets[k]:self.f_offsets[k + 1]].view(self.plans[k].shape_f)
+
+    def frame_g(self, g_all, k):
+        return g_all[self.g_offsets[k]:self.g_offsets[k + 1]].view(self.plans[k].shape_g)
+
+    def pack_g(self, images):
+        torch = _torch()
+        return torch.cat([torch.as_tensor(x, dtype=torch.float32, device=self.device).reshape(-1) for x in images])
+
+    def workspace(self):
+        torch = _torch()
+        return torch.empty(max(self.info["workspace_bytes"] // 4, 64), dtype=torch.float32, device=self.device)
+
+    def forward(self, f_all, out=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty(int(self.g_offsets[-1]), dtype=torch.float32, device=self.device)
+        st = self._L.ctis_batch_forward(self._handle, ctypes.c_void_p(f_all.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                        _stream(torch, self.device))
+        _check(self._L, st, "ctis_batch_forward")
+        return out
+
+    def adjoint(self, r_all, out=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty(int(self.f_offsets[-1]), dtype=torch.float32, device=self.device)
+        st = self._L.ctis_batch_adjoint(self._handle, ctypes.c_void_p(r_all.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                        _stream(torch, self.device))
+        _check(self._L, st, "ctis_batch_adjoint")
+        return out
+
+    def em(self, g_all, iters: int, f_all=None, workspace=None):
+        """EM of every frame in place on f_all (default: a new all-ones f_all)."""
+        torch = _torch()
+        if f_all is None:
+            f_all = torch.ones(int(self.f_offsets[-1]), dtype=torch.float32, device=self.device)
+        if workspace is None:
+            workspace = self.workspace()
+        st = self._L.ctis_batch_em_iterate(self._handle, ctypes.c_void_p(g_all.data_ptr()),
+                                           ctypes.c_void_p(f_all.data_ptr()), int(iters),
+                                           ctypes.c_void_p(workspace.data_ptr()),
+                                           workspace.numel() * workspace.element_size(), _stream(torch, self.device))
+        _check(self._L, st, "ctis_batch_em_iterate")
+        return f_all
