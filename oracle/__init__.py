@@ -21,6 +21,13 @@ Each function cites the passage of the paper it follows:
   * ``forward_rows`` / ``adjoint_cols`` -- single rows / columns of H straight
                         from the circulant definition, for sampled checks at
                         sizes where assembling H is too large.
+  * ``em_vjp``       -- reverse-mode derivative of one EM step (Sec. 2 eq. (em))
+                        with respect to its input f and to the calibration
+                        values (the entries of H come from them through
+                        Sec. 3's H_s = C_s E), by the chain rule stage by stage.
+  * ``unrolled_grad`` -- the same through K unrolled EM steps: the steps run
+                        forward keeping every iterate, then their derivatives
+                        are applied last to first.
 """
 from __future__ import annotations
 
@@ -106,6 +113,8 @@ def _load():
         L.oracle_cal_nnz.restype = ctypes.c_int64
         L.oracle_export_cal.argtypes = [P, i64p, i64p, f64p]
         L.oracle_export_cal.restype = None
+        L.oracle_em_vjp.argtypes = [P, f64p, f64p, f64p, f64p, ctypes.c_int64, P, P, P]
+        L.oracle_em_vjp.restype = ci
         _lib = L
         return L
 
@@ -144,6 +153,7 @@ class Oracle:
         _check(st)
         self._h = h
         self.assembled = assemble
+        self.entries = (ptr.copy(), idx[: ptr[-1]].copy(), val[: ptr[-1]].copy())
         if threads:
             self._L.oracle_set_threads(self._h, int(threads))
 
@@ -272,3 +282,50 @@ class Oracle:
         out = np.empty(cols.size, np.float64)
         self._L.oracle_adjoint_cols(self._h, r, cols, cols.size, out)
         return out
+
+    # -- derivatives ---------------------------------------------------------
+    def em_vjp(self, g, f, y, positions=None):
+        """One EM step's reverse-mode derivative at input ``f`` for the upstream
+        gradient ``y`` = dL/df'.  Returns (dL/df, dL/dv) where dL/dv holds, for
+        every calibration entry given at construction (in that order; entries
+        that share a position get the same value), the derivative with respect
+        to that entry's value.  ``positions`` = (lambda, index) arrays picks
+        other calibration positions instead."""
+        self._need_h()
+        g = np.ascontiguousarray(np.asarray(g, dtype=np.float64).reshape(-1))
+        f = np.ascontiguousarray(np.asarray(f, dtype=np.float64).reshape(-1))
+        y = np.ascontiguousarray(np.asarray(y, dtype=np.float64).reshape(-1))
+        if g.size != self.n or f.size != self.m or y.size != self.m:
+            raise OracleError("g must have n entries, f and y m entries")
+        if positions is None:
+            ptr, idx, _ = self.entries
+            lam = np.repeat(np.arange(self.w, dtype=np.int32), np.diff(ptr))
+            pos = idx.astype(np.int64)
+        else:
+            lam = np.ascontiguousarray(positions[0], dtype=np.int32)
+            pos = np.ascontiguousarray(positions[1], dtype=np.int64)
+        df = np.empty(self.m, np.float64)
+        dv = np.empty(max(lam.size, 1), np.float64)
+        st = self._L.oracle_em_vjp(self._h, g, f, y, df, lam.size,
+                                   lam.ctypes.data_as(ctypes.c_void_p),
+                                   pos.ctypes.data_as(ctypes.c_void_p),
+                                   dv.ctypes.data_as(ctypes.c_void_p))
+        _check(st)
+        return df, dv[: lam.size]
+
+    def unrolled_grad(self, g, f0, iters: int, dL_df):
+        """Derivatives of a loss of f^(K+1) (K = ``iters`` EM steps from f0)
+        with respect to f0 and to the calibration entries' values, given
+        ``dL_df`` -- a function of f^(K+1) returning dL/df^(K+1).  Returns
+        (f^(K+1), dL/df0, dL/dv)."""
+        f = np.array(np.asarray(f0, dtype=np.float64).reshape(-1), copy=True)
+        iterates = [f.copy()]
+        for _ in range(iters):
+            f = self.em(g, 1, f0=f)
+            iterates.append(f.copy())
+        y = np.asarray(dL_df(f), dtype=np.float64).reshape(-1)
+        dv = np.zeros(int(self.entries[0][-1]), np.float64)
+        for k in range(iters - 1, -1, -1):
+            y, dvk = self.em_vjp(g, iterates[k], y)
+            dv += dvk
+        return f, y, dv

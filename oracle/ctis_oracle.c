@@ -372,3 +372,85 @@ void oracle_export_cal(const oracle_t *o, int64_t *cptr, int64_t *cidx, double *
     memcpy(cidx, o->cidx, sizeof(int64_t) * (size_t)o->cptr[o->w]);
     memcpy(cval, o->cval, sizeof(double) * (size_t)o->cptr[o->w]);
 }
+
+/*
+ * Reverse-mode derivative of one EM step (Sec. 2 eq. (em), stage order of the
+ * Sec. 3 algorithm), for a scalar loss L of the step's output f':
+ *
+ *   forward stages:  ghat = H f,  u_i = g_i / ghat_i (0 where ghat_i <= 0),
+ *                    zeta = H^T u,  f'_j = f_j zeta_j / h_j (0 where h_j = 0),
+ *                    with H_ij = c_s[(i - q_j) mod n] for voxel j of wavelength
+ *                    s (Sec. 3, H_s = C_s E) and h_j = sum_i H_ij.
+ *   given y = dL/df', the stages are differentiated last to first:
+ *     f' stage:  b_j = dL/dzeta_j = y_j f_j / h_j,  dL/df_j = y_j zeta_j / h_j,
+ *                hbar_j = dL/dh_j = -y_j f'_j / h_j   (all 0 where h_j = 0);
+ *     zeta stage: dL/du = H b,  dL/dH_ij += u_i b_j;
+ *     u stage:   e_i = dL/dghat_i = -(H b)_i g_i / ghat_i^2   (0 where ghat_i <= 0);
+ *     ghat stage: dL/df += H^T e,  dL/dH_ij += e_i f_j;
+ *     H from the calibration vectors: dL/dc_s[p] = sum over the voxels j of
+ *                wavelength s of (dL/dH_{(p + q_j) mod n, j} + hbar_j),
+ *                because H_ij is c_s[p] exactly at i = (p + q_j) mod n and
+ *                every column sum h_j of wavelength s holds c_s[p] once.
+ *
+ * Inputs g[n], f[m] (the step's input), y[m].  Outputs df[m] = dL/df and, for
+ * npos requested calibration positions (pos_lambda[k], pos_index[k]),
+ * dv[k] = dL/dc_s[p].  dv may be NULL when npos = 0.
+ */
+int oracle_em_vjp(const oracle_t *o, const double *g, const double *f, const double *y,
+                  double *df, int64_t npos, const int32_t *pos_lambda, const int64_t *pos_index,
+                  double *dv) {
+    if (!o->rowptr || npos < 0) return OR_E_ARG;
+    for (int64_t k = 0; k < npos; ++k)
+        if (pos_lambda[k] < 0 || pos_lambda[k] >= o->w || pos_index[k] < 0 || pos_index[k] >= o->n)
+            return OR_E_INDEX;
+    const int64_t n = o->n, m = o->m;
+    double *ghat = (double *)malloc(sizeof(double) * (size_t)n);
+    double *u = (double *)malloc(sizeof(double) * (size_t)n);
+    double *Hb = (double *)malloc(sizeof(double) * (size_t)n);
+    double *e = (double *)malloc(sizeof(double) * (size_t)n);
+    double *zeta = (double *)malloc(sizeof(double) * (size_t)m);
+    double *b = (double *)malloc(sizeof(double) * (size_t)m);
+    double *hbar = (double *)malloc(sizeof(double) * (size_t)m);
+    double *Hte = (double *)malloc(sizeof(double) * (size_t)m);
+    if (!ghat || !u || !Hb || !e || !zeta || !b || !hbar || !Hte) {
+        free(ghat); free(u); free(Hb); free(e); free(zeta); free(b); free(hbar); free(Hte);
+        return OR_E_NOMEM;
+    }
+    /* forward stages, recomputed from the step's input */
+    oracle_forward(o, f, ghat);
+    for (int64_t i = 0; i < n; ++i) u[i] = ghat[i] > 0.0 ? g[i] / ghat[i] : 0.0;
+    oracle_adjoint(o, u, zeta);
+    /* f' stage */
+    for (int64_t j = 0; j < m; ++j) {
+        if (o->h[j] != 0.0) {
+            const double fnew = f[j] * zeta[j] / o->h[j];
+            b[j] = y[j] * f[j] / o->h[j];
+            df[j] = y[j] * zeta[j] / o->h[j];
+            hbar[j] = -y[j] * fnew / o->h[j];
+        } else {
+            b[j] = 0.0;
+            df[j] = 0.0;
+            hbar[j] = 0.0;
+        }
+    }
+    /* zeta stage and u stage */
+    oracle_forward(o, b, Hb);
+    for (int64_t i = 0; i < n; ++i) e[i] = ghat[i] > 0.0 ? -Hb[i] * g[i] / (ghat[i] * ghat[i]) : 0.0;
+    /* ghat stage */
+    oracle_adjoint(o, e, Hte);
+    for (int64_t j = 0; j < m; ++j) df[j] += Hte[j];
+    /* calibration values, from the entries of H they appear in */
+    int nt = set_threads(o);
+#pragma omp parallel for schedule(dynamic, 4) num_threads(nt)
+    for (int64_t k = 0; k < npos; ++k) {
+        const int64_t s = pos_lambda[k], p = pos_index[k];
+        double acc = 0.0;
+        for (int64_t j = s * o->ell; j < (s + 1) * o->ell; ++j) {
+            const int64_t i = (p + oracle_index_map(o, j)) % n;
+            acc += u[i] * b[j] + e[i] * f[j] + hbar[j];
+        }
+        dv[k] = acc;
+    }
+    free(ghat); free(u); free(Hb); free(e); free(zeta); free(b); free(hbar); free(Hte);
+    return OR_OK;
+}
