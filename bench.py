@@ -87,8 +87,9 @@ def main(argv=None) -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4],
-                    help="1-3: one frame; 4: 64 uneven frames, batched vs sequential")
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5],
+                    help="1-3: one frame; 4: 64 uneven frames, batched vs sequential; "
+                         "5: gradients of 10 unrolled EM iterations, 8 frames sharing one plan")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -123,6 +124,8 @@ def main(argv=None) -> int:
         return 0
     if args.config == 4:
         return bench_batched(args, torch, ctis, W, dev)
+    if args.config == 5:
+        return bench_differentiable(args, torch, ctis, W, dev)
     case = W.make_case(args.config)
     cfg = case.cfg
     geo = case.geometry
@@ -348,6 +351,112 @@ def bench_batched(args, torch, ctis, W, dev) -> int:
                      "kernel": "forward_ratio + adjoint_update (one EM iteration of all frames)",
                      "algorithmic_bytes_per_iteration": bytes_it,
                      "algorithmic_flop_per_iteration": 2 * flops},
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def bench_differentiable(args, torch, ctis, W, dev) -> int:
+    """8 frames of the c2 shape sharing one calibration plan; one step = the
+    loss sum ||f^(K+1) - f_true||^2 of K = 10 unrolled EM iterations and its
+    gradients with respect to f0 and every calibration value (set the
+    values, K checkpointed EM iterations, K derivative calls)."""
+    from paper_2006_01573_amd.autodiff import unrolled_em
+    K = 10
+    cases = W.differentiable_cases(8, iters=K)
+    c0 = cases[0]
+    nf = len(cases)
+    progress(f"c5: plan and {nf} frames")
+    plan = ctis.Plan.from_case(c0, keep_zeros=True)
+    b = ctis.Batch([plan] * nf)
+    images = []
+    for c in cases:
+        clean = plan.forward(torch.from_numpy(c.f_true.astype(np.float32)).to(dev)).double().cpu().numpy()
+        images.append(c.noisy(clean))
+    g_all = b.pack_g(images)
+    target = torch.from_numpy(np.concatenate([c.f_true.ravel() for c in cases]).astype(np.float32)).to(dev)
+    f0 = torch.ones(int(b.f_offsets[-1]), dtype=torch.float32, device=dev, requires_grad=True)
+    v = torch.from_numpy(c0.value.astype(np.float32)).to(dev).requires_grad_(True)
+
+    def step():
+        f0.grad = None
+        v.grad = None
+        fK = unrolled_em(b, g_all, f0, K, values=v)
+        loss = ((fK - target) ** 2).sum()
+        loss.backward()
+        return loss
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    progress(f"c5: timing {args.steps} gradient steps")
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        loss = step()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    if not (torch.isfinite(f0.grad).all() and torch.isfinite(v.grad).all()):
+        print("bench.py: non-finite gradient", file=sys.stderr)
+        return 1
+    # the pieces: one batched EM iteration and one batched derivative call
+    ws = b.vjp_workspace()
+    f_all = torch.ones_like(target)
+    y = torch.randn_like(target)
+    dv = torch.zeros(b.info["n_entries"], dtype=torch.float32, device=dev)
+    reps = 20
+    b.em(g_all, 1, f_all=f_all, workspace=ws)
+    e0.record()
+    for _ in range(reps):
+        b.em(g_all, 1, f_all=f_all, workspace=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    em_us = e0.elapsed_time(e1) / reps * 1e3
+    f_in = f_all.clone()
+    b.em_vjp(g_all, f_in, y, df_all=y, dvalues=dv, accumulate=True, workspace=ws)
+    e0.record()
+    for _ in range(reps):
+        b.em_vjp(g_all, f_in, y, df_all=y, dvalues=dv, accumulate=True, workspace=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    vjp_us = e0.elapsed_time(e1) / reps * 1e3
+    inf = plan.info
+    m_all, nsup = nf * inf.m, nf * inf.n_support
+    # algorithmic bytes of one derivative call: forward+ratio (f, g, u), back
+    # projection (u; y, f in; zeta, b out), forward of b (b, g, u; e out), back
+    # projection (e; y, zeta in; df out), value partials (u, e, b, f)
+    bytes_vjp = 4 * (11 * m_all + 9 * nsup)
+    achieved = bytes_vjp / (vjp_us * 1e-6) / 1e9
+    line = {
+        "metric": METRIC,
+        "value": nf * args.steps / (ms / 1e3),
+        "unit": "differentiated frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "c5 8 frames a=alpha=64 w=32 FPA512 sharing one calibration plan, loss "
+                               "||f^(11) - f_true||^2 after 10 unrolled EM iterations, gradients w.r.t. f0 "
+                               "and all calibration values; one step = forward + backward",
+                   "frames": nf, "em_iters": K, "m_total": m_all, "n_entries": int(b.info["n_entries"])},
+        "loss": float(loss.item()),
+        "wall_s": wall,
+        "em_iteration_all_frames_us": em_us,
+        "vjp_call_all_frames_us": vjp_us,
+        "vjp_vs_em_iteration": vjp_us / em_us,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "one derivative call of all frames (4 projections + value partials + sums)",
+                     "algorithmic_bytes_per_call": bytes_vjp},
     }
     print(json.dumps(line), flush=True)
     return 0

@@ -78,6 +78,14 @@ typedef struct ctis_batch ctis_batch;
 #define CTIS_PLAN_BOX(b) (((uint32_t)(b) & 0xFu) << 8)
                                         /* force the calibration box side B in
                                            1..8 (0 = chosen by the plan)         */
+#define CTIS_PLAN_KEEP_ZEROS 0x2u       /* the structure is the set of given
+                                           positions, whatever their values:
+                                           entries that merge to an exact zero
+                                           are kept (as zero-valued box slots)
+                                           instead of dropped.  Needed for the
+                                           value derivatives of ctis_em_vjp and
+                                           for ctis_plan_set_values when some
+                                           value may be zero                    */
 
 typedef struct {
     int32_t a, alpha, w, gamma, xi;
@@ -97,6 +105,11 @@ typedef struct {
     int32_t device;          /* HIP device of the plan, -1 if host-only         */
     int32_t waves_forward;   /* wavefronts per forward workgroup                */
     int32_t waves_adjoint;   /* wavefronts per adjoint workgroup                */
+    int64_t n_entries;       /* calibration entries as given (lambda_ptr[w])    */
+    size_t vjp_workspace_bytes;  /* device workspace ctis_em_vjp needs (also
+                                    enough for ctis_em_iterate)                 */
+    int32_t dropped;         /* 1 if some entry merged to an exact zero and was
+                                dropped (never with CTIS_PLAN_KEEP_ZEROS)       */
 } ctis_plan_info;
 
 /*
@@ -239,6 +252,9 @@ typedef struct {
     int64_t forward_units, adjoint_units;
     int32_t waves_forward, waves_adjoint;
     size_t workspace_bytes;        /* EM workspace of ctis_batch_em_iterate      */
+    int32_t n_plans;               /* distinct plans (frames may share one)      */
+    int64_t n_entries;             /* calibration entries of the distinct plans  */
+    size_t vjp_workspace_bytes;    /* workspace of ctis_batch_em_vjp             */
 } ctis_batch_info;
 
 /* Create a batch over n_frames >= 1 frames.  flags: CTIS_BATCH_WAVES_* (wave
@@ -259,6 +275,72 @@ ctis_status ctis_batch_adjoint(const ctis_batch *batch, const float *r_all, floa
  * ctis_em_iterate; CTIS_E_NEGATIVE if any plan has a negative value. */
 ctis_status ctis_batch_em_iterate(const ctis_batch *batch, const float *g_all, float *f_all, int32_t iters,
                                   void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Derivatives of EM (reverse mode), for losses of f after K unrolled
+ * iterations: each call differentiates ONE iteration (Sec. 2 eq. (em)), so a
+ * caller keeps the iterates f^(1..K) (one checkpoint per iteration) and calls
+ * ctis_em_vjp for k = K..1, feeding each call's df_out back as the next y.
+ *
+ * With f' = (f . zeta) / h, zeta = H^T u, u = g / H f (the step of
+ * ctis_em_iterate, with its two zero rules) and the upstream gradient
+ * y = dL/df', one call computes (in four projections and two reductions):
+ *   b = y f / h,  e = -(H b) u / (H f)   (0 where u = 0 or h = 0),
+ *   df_out = dL/df = y zeta / h + H^T e,
+ *   dL/dv_t = sum over the voxels j of entry t's wavelength s of
+ *             [u_i b_j + e_i f_j]  at  i = (p_t + q_j) mod n
+ *             - sum_{j in s} y_j f'_j / h_s,
+ * where p_t is entry t's FPA position and q_j the Sec. 3 shift of voxel j
+ * (H_ij = c_s[(i - q_j) mod n], h_s = sum of c_s).  Entries that share a
+ * position get the same derivative.
+ *
+ *   g          DEVICE float[n], the measured frame (as for EM)
+ *   f          DEVICE float[m], the iteration's input f^(k)
+ *   y          DEVICE float[m], dL/df^(k+1)
+ *   df_out     DEVICE float[m], dL/df^(k); may equal y (in place), must not
+ *              overlap f, g or the workspace otherwise
+ *   dvalues    DEVICE float[n_entries] or NULL: dL/dv per calibration entry in
+ *              the plan's input order; added to the array's contents if
+ *              `accumulate` is nonzero, else overwritten
+ *   workspace  DEVICE, >= info.vjp_workspace_bytes, 256-byte aligned; scratch
+ * Errors: CTIS_E_ARG (also for dvalues on a plan that dropped an entry: create
+ * it with CTIS_PLAN_KEEP_ZEROS), CTIS_E_NEGATIVE, CTIS_E_WORKSPACE, CTIS_E_HIP.
+ * The launches are stream-ordered; nothing is allocated or synchronised.
+ */
+ctis_status ctis_em_vjp(const ctis_plan *plan, const float *g, const float *f, const float *y, float *df_out,
+                        float *dvalues, int32_t accumulate, void *workspace, size_t workspace_bytes,
+                        void *stream);
+
+/*
+ * New calibration values on the plan's structure (Sec. 2 calibration images;
+ * same positions, same box grouping): values DEVICE float[n_entries] in the
+ * plan's input order, duplicates of a position summed (in double) as at
+ * creation.  Rewrites the plan's box values and column sums h on `stream`;
+ * later calls on the stream see them.  The sign check of EM keeps the sign of
+ * the values given at creation: values made negative here are the caller's
+ * contract violation.  Errors: CTIS_E_ARG (also if the plan dropped an entry:
+ * use CTIS_PLAN_KEEP_ZEROS), CTIS_E_HIP.  Batches hold their own copy of their
+ * plans' values, taken at ctis_batch_create (see ctis_batch_set_values).
+ */
+ctis_status ctis_plan_set_values(ctis_plan *plan, const float *values, void *stream);
+
+/*
+ * Batch forms.  Frames that share a plan share its values: dvalues and the
+ * values of ctis_batch_set_values hold the entries of the batch's distinct
+ * plans back to back, in order of first appearance in the plans array (see
+ * ctis_batch_plan_entries), and the derivative of a shared value sums over
+ * the frames that use it.  Layouts of g_all, f_all, y_all and df_all as for
+ * ctis_batch_em_iterate.
+ */
+ctis_status ctis_batch_em_vjp(const ctis_batch *batch, const float *g_all, const float *f_all,
+                              const float *y_all, float *df_all, float *dvalues, int32_t accumulate,
+                              void *workspace, size_t workspace_bytes, void *stream);
+/* New values for the plan of frame `frame` (and every frame sharing it), in
+ * the batch's copy: values DEVICE float[that plan's n_entries]. */
+ctis_status ctis_batch_set_values(ctis_batch *batch, int32_t frame, const float *values, void *stream);
+/* Where the entries of frame `frame`'s plan sit in the batch's value arrays:
+ * [*offset, *offset + *count). */
+ctis_status ctis_batch_plan_entries(const ctis_batch *batch, int32_t frame, int64_t *offset, int64_t *count);
 
 /* Static description of a status code. */
 const char *ctis_status_str(ctis_status status);

@@ -79,7 +79,7 @@ ctis_status ctis_plan_create(ctis_plan **out, int32_t a, int32_t alpha, int32_t 
     g_last_error.clear();
     if (!out) return fail(CTIS_E_ARG, "out is NULL");
     *out = nullptr;
-    const uint32_t known = CTIS_PLAN_HOST_ONLY | CTIS_PLAN_BOX(0xF);
+    const uint32_t known = CTIS_PLAN_HOST_ONLY | CTIS_PLAN_KEEP_ZEROS | CTIS_PLAN_BOX(0xF);
     if (flags & ~known) return fail(CTIS_E_ARG, "unknown flag bits");
     const int forced_box = (int)((flags >> 8) & 0xFu);
     if (forced_box > kMaxBox) return fail(CTIS_E_ARG, "forced box side must be in 1..8");
@@ -115,7 +115,7 @@ ctis_status ctis_plan_create(ctis_plan **out, int32_t a, int32_t alpha, int32_t 
     p->m = m;
     ctis_status st;
     try {
-        st = build_host_tables(p, lambda_ptr, fpa_index, value, forced_box);
+        st = build_host_tables(p, lambda_ptr, fpa_index, value, forced_box, (flags & CTIS_PLAN_KEEP_ZEROS) != 0);
     } catch (const std::bad_alloc &) {
         st = fail(CTIS_E_NOMEM, "host allocation while building the plan");
     }
@@ -143,6 +143,7 @@ ctis_status ctis_plan_create(ctis_plan **out, int32_t a, int32_t alpha, int32_t 
             return st;
         }
         p->workspace_bytes = p->work.workspace_bytes;
+        p->vjp_workspace_bytes = p->work.vjp_workspace_bytes;
     } else {
         // host-only plans still report the workspace an EM call would need
         HostWork hw;
@@ -155,8 +156,9 @@ ctis_status ctis_plan_create(ctis_plan **out, int32_t a, int32_t alpha, int32_t 
             delete p;
             return st;
         }
-        p->workspace_bytes = (((size_t)hw.u_floats * 4 + 255) & ~(size_t)255) +
-                             (size_t)hw.partial_slots * kTileFast * kTileSlow * sizeof(float);
+        const Layout L = layout_for(hw);
+        p->workspace_bytes = L.em_bytes;
+        p->vjp_workspace_bytes = L.vjp_bytes;
         p->work.fwd_em.waves = hw.fwd_em.waves;
         p->work.adj.waves = hw.adj.waves;
     }
@@ -195,6 +197,9 @@ ctis_status ctis_plan_get_info(const ctis_plan *p, ctis_plan_info *info) {
     info->device = p->device;
     info->waves_forward = p->work.fwd_em.waves;
     info->waves_adjoint = p->work.adj.waves;
+    info->n_entries = p->ht.n_in;
+    info->vjp_workspace_bytes = p->vjp_workspace_bytes;
+    info->dropped = p->ht.dropped ? 1 : 0;
     return CTIS_OK;
 }
 
@@ -228,7 +233,7 @@ ctis_status ctis_forward(const ctis_plan *p, const float *f, float *g_out, void 
     if (overlaps(f, (size_t)p->m * 4, g_out, (size_t)p->n * 4)) return fail(CTIS_E_ARG, "f and g_out overlap");
     ctis_status st = check_device(p);
     if (st != CTIS_OK) return st;
-    return launch_status(launch_forward(p->work, f, nullptr, g_out, false, nullptr, stream), "forward launch");
+    return launch_status(launch_forward(p->work, f, nullptr, nullptr, g_out, kFwdPlain, nullptr, stream), "forward launch");
 }
 
 ctis_status ctis_adjoint(const ctis_plan *p, const float *r, float *z_out, void *stream) {
@@ -238,7 +243,7 @@ ctis_status ctis_adjoint(const ctis_plan *p, const float *r, float *z_out, void 
     if (overlaps(r, (size_t)p->n * 4, z_out, (size_t)p->m * 4)) return fail(CTIS_E_ARG, "r and z_out overlap");
     ctis_status st = check_device(p);
     if (st != CTIS_OK) return st;
-    return launch_status(launch_adjoint(p->work, r, nullptr, z_out, false, stream), "adjoint launch");
+    return launch_status(launch_adjoint(p->work, r, nullptr, nullptr, z_out, nullptr, nullptr, kAdjPlain, stream), "adjoint launch");
 }
 
 namespace {
@@ -272,9 +277,9 @@ ctis_status ctis_em_iterate(const ctis_plan *p, const float *g, float *f, int32_
     if (st != CTIS_OK || iters == 0) return st;
     float *u = (float *)workspace;
     for (int32_t k = 0; k < iters; ++k) {
-        st = launch_status(launch_forward(p->work, f, g, u, true, workspace, stream), "forward+ratio launch");
+        st = launch_status(launch_forward(p->work, f, g, nullptr, u, kFwdRatio, workspace, stream), "forward+ratio launch");
         if (st != CTIS_OK) return st;
-        st = launch_status(launch_adjoint(p->work, u, f, f, true, stream), "adjoint+update launch");
+        st = launch_status(launch_adjoint(p->work, u, f, nullptr, f, nullptr, nullptr, kAdjUpdate, stream), "adjoint+update launch");
         if (st != CTIS_OK) return st;
     }
     return CTIS_OK;
@@ -293,7 +298,7 @@ ctis_status ctis_em_forward_ratio(const ctis_plan *p, const float *f, const floa
         return fail(CTIS_E_ARG, "the workspace must not overlap f or g");
     st = check_device(p);
     if (st != CTIS_OK) return st;
-    return launch_status(launch_forward(p->work, f, g, (float *)workspace, true, workspace, stream),
+    return launch_status(launch_forward(p->work, f, g, nullptr, (float *)workspace, kFwdRatio, workspace, stream),
                          "forward+ratio launch");
 }
 
@@ -311,7 +316,7 @@ ctis_status ctis_em_adjoint_update(const ctis_plan *p, const void *workspace, si
         return fail(CTIS_E_ARG, "the workspace and f_out overlap");
     st = check_device(p);
     if (st != CTIS_OK) return st;
-    return launch_status(launch_adjoint(p->work, (const float *)workspace, f_in, f_out, true, stream),
+    return launch_status(launch_adjoint(p->work, (const float *)workspace, f_in, nullptr, f_out, nullptr, nullptr, kAdjUpdate, stream),
                          "adjoint+update launch");
 }
 

@@ -1,6 +1,7 @@
 // Batches of frames (C ABI): several plans merged into one work description,
 // so that each EM iteration of all frames is one forward+ratio launch and one
 // adjoint+update launch.
+#include <cstring>
 #include <new>
 #include <string>
 
@@ -90,6 +91,11 @@ ctis_status ctis_batch_create(ctis_batch **out, const ctis_plan *const *plans, i
     }
     b->f_floats = fo;
     b->g_floats = go;
+    b->dropped = hw.dropped;
+    b->frame_plan = hw.frame_plan;
+    b->plan_box0 = hw.plan_box0;
+    b->plan_lam0 = hw.plan_lam0;
+    b->plan_entry0 = hw.plan_entry0;
     b->device = dev;
     b->nonneg = nonneg;
     *out = b;
@@ -104,6 +110,7 @@ void ctis_batch_destroy(ctis_batch *b) {
 
 ctis_status ctis_batch_get_info(const ctis_batch *b, ctis_batch_info *info) {
     if (!b || !info) return fail(CTIS_E_ARG, "batch or info is NULL");
+    std::memset(info, 0, sizeof(*info));
     info->n_frames = (int32_t)b->plans.size();
     info->box = b->work.B;
     info->m_total = b->f_floats;
@@ -113,6 +120,9 @@ ctis_status ctis_batch_get_info(const ctis_batch *b, ctis_batch_info *info) {
     info->waves_forward = b->work.fwd_em.waves;
     info->waves_adjoint = b->work.adj.waves;
     info->workspace_bytes = b->work.workspace_bytes;
+    info->n_plans = (int32_t)b->plan_entry0.size();
+    info->n_entries = b->work.n_entries;
+    info->vjp_workspace_bytes = b->work.vjp_workspace_bytes;
     return CTIS_OK;
 }
 
@@ -124,7 +134,7 @@ ctis_status ctis_batch_forward(const ctis_batch *b, const float *f_all, float *g
         return fail(CTIS_E_ARG, "f_all and g_all overlap");
     ctis_status st = batch_device(b);
     if (st != CTIS_OK) return st;
-    return launched(launch_forward(b->work, f_all, nullptr, g_all, false, nullptr, stream), "batch forward launch");
+    return launched(launch_forward(b->work, f_all, nullptr, nullptr, g_all, kFwdPlain, nullptr, stream), "batch forward launch");
 }
 
 ctis_status ctis_batch_adjoint(const ctis_batch *b, const float *r_all, float *z_all, void *stream) {
@@ -135,7 +145,7 @@ ctis_status ctis_batch_adjoint(const ctis_batch *b, const float *r_all, float *z
         return fail(CTIS_E_ARG, "r_all and z_all overlap");
     ctis_status st = batch_device(b);
     if (st != CTIS_OK) return st;
-    return launched(launch_adjoint(b->work, r_all, nullptr, z_all, false, stream), "batch adjoint launch");
+    return launched(launch_adjoint(b->work, r_all, nullptr, nullptr, z_all, nullptr, nullptr, kAdjPlain, stream), "batch adjoint launch");
 }
 
 ctis_status ctis_batch_em_iterate(const ctis_batch *b, const float *g_all, float *f_all, int32_t iters,
@@ -155,9 +165,9 @@ ctis_status ctis_batch_em_iterate(const ctis_batch *b, const float *g_all, float
     if (st != CTIS_OK) return st;
     float *u = (float *)workspace;
     for (int32_t k = 0; k < iters; ++k) {
-        st = launched(launch_forward(b->work, f_all, g_all, u, true, workspace, stream), "batch forward+ratio launch");
+        st = launched(launch_forward(b->work, f_all, g_all, nullptr, u, kFwdRatio, workspace, stream), "batch forward+ratio launch");
         if (st != CTIS_OK) return st;
-        st = launched(launch_adjoint(b->work, u, f_all, f_all, true, stream), "batch adjoint+update launch");
+        st = launched(launch_adjoint(b->work, u, f_all, nullptr, f_all, nullptr, nullptr, kAdjUpdate, stream), "batch adjoint+update launch");
         if (st != CTIS_OK) return st;
     }
     return CTIS_OK;

@@ -46,6 +46,22 @@ constexpr int64_t kMaxPixels = (int64_t(1) << 29) - 1;
 //   (u_off, 0, 0, 0)                    frame offset into u
 // adjoint record, int4: (rA, cA, 0, box), adj_stride records per global
 //   wavelength
+//
+// Frames that share a plan share its boxes, wavelengths and values: the
+// "global" box and wavelength ids run over the distinct plans of the work, in
+// order of first appearance.
+//
+// Value-gradient tables (the calibration values as variables):
+//   entry_slot[t]      global slot (box * B*B + position in the box) of
+//                      calibration entry t, entries of the distinct plans back
+//                      to back in each plan's input order; -1 if the entry was
+//                      dropped (merged to an exact zero)
+//   box_lam[b]         global wavelength of global box b
+//   lam_box0[l]        first global box of global wavelength l (n_lambda + 1)
+//   lam_units[..]      adjoint units of global wavelength l (every frame that
+//                      uses it): lam_units[lam_units_ptr[l] .. lam_units_ptr[l+1])
+//   slot_entries[..]   entries feeding global slot k (duplicates of one
+//                      position): slot_entries[slot_entries_ptr[k] .. [k+1])
 struct DevList {
     const int4 *meta = nullptr;
     const int4 *items = nullptr;
@@ -59,10 +75,19 @@ struct DevWork {
     const int4 *split_meta = nullptr;
     int32_t n_split = 0;
     DevList adj;                 // adjoint units; items indexed by global wavelength
-    const float *box_w = nullptr, *box_wf = nullptr, *h = nullptr;
+    float *box_w = nullptr, *box_wf = nullptr, *h = nullptr;
     size_t partials_off = 0;     // byte offset of the partial tiles in the EM workspace
     size_t workspace_bytes = 0;  // u region + partial tiles
     bool persistent = false;     // grid-stride workgroups instead of one per unit
+    // value gradients and value updates
+    const int32_t *entry_slot = nullptr, *box_lam = nullptr, *lam_box0 = nullptr;
+    const int32_t *lam_units_ptr = nullptr, *lam_units = nullptr;
+    const int32_t *slot_entries_ptr = nullptr, *slot_entries = nullptr;
+    int64_t n_entries = 0;
+    int32_t n_lambda = 0, n_boxes = 0;
+    // VJP workspace: the EM workspace (u, partial tiles) followed by
+    // e, zeta, b, per-unit flux partials and per-(unit, box) value partials
+    size_t e_off = 0, zeta_off = 0, b_off = 0, hpart_off = 0, vg_off = 0, vjp_workspace_bytes = 0;
     void *mem = nullptr;         // device allocation holding the tables
 };
 
@@ -78,7 +103,21 @@ struct HostWork {
     int32_t n_split = 0, partial_slots = 0;
     std::vector<float> box_w, box_wf, h;
     int64_t u_floats = 0;        // u region of the EM workspace
+    int64_t f_floats = 0;        // extent of the f buffer
+    // value tables (layout as in DevWork)
+    std::vector<int32_t> entry_slot, box_lam, lam_box0, lam_units_ptr, lam_units, slot_entries_ptr, slot_entries;
+    // distinct plans: per frame its distinct plan, per distinct plan the first
+    // global box, wavelength and entry
+    std::vector<int32_t> frame_plan, plan_box0, plan_lam0;
+    std::vector<int64_t> plan_entry0;
+    bool dropped = false;        // some entry of some plan was dropped
 };
+
+// Workspace layout of a work description (byte offsets, 256-byte aligned).
+struct Layout {
+    size_t partials_off, em_bytes, e_off, zeta_off, b_off, hpart_off, vg_off, vjp_bytes;
+};
+Layout layout_for(const HostWork &hw);
 
 // Per-plan analysis of the calibration (host).
 struct HostTables {
@@ -92,6 +131,11 @@ struct HostTables {
     int32_t max_items = 0, max_boxes = 0;
     int32_t chunk = 64;          // max boxes per forward unit in EM
     bool nonneg = true;
+    // calibration entries as given: count, slot of each (global box of the
+    // plan * B*B + position in the box; -1 if dropped), any dropped
+    int64_t n_in = 0;
+    std::vector<int32_t> entry_slot;
+    bool dropped = false;
 };
 
 }  // namespace ctis
@@ -102,7 +146,7 @@ struct ctis_plan {
     ctis::HostTables ht;
     int32_t device = -1;
     ctis::DevWork work;          // the plan as a batch of one frame
-    size_t workspace_bytes = 0;
+    size_t workspace_bytes = 0, vjp_workspace_bytes = 0;
 };
 
 struct ctis_batch {
@@ -111,6 +155,9 @@ struct ctis_batch {
     int64_t f_floats = 0, g_floats = 0;
     int32_t device = -1;
     bool nonneg = true;
+    bool dropped = false;
+    std::vector<int32_t> frame_plan, plan_box0, plan_lam0;   // distinct plans
+    std::vector<int64_t> plan_entry0;
     ctis::DevWork work;
 };
 
@@ -121,7 +168,7 @@ ctis_status fail(ctis_status st, const std::string &msg);
 
 // host plan builder (plan.cpp)
 ctis_status build_host_tables(ctis_plan *p, const int64_t *lambda_ptr, const int32_t *fpa_index,
-                              const float *value, int forced_box);
+                              const float *value, int forced_box, bool keep_zeros);
 
 // One frame of a work description: its plan and buffer offsets (floats).
 struct FrameRef {
@@ -135,8 +182,34 @@ void free_work(DevWork &dw);
 // kernel launchers (kernels.hip); return hipError_t as int
 int max_waves(int box);
 int min_waves();
-int launch_forward(const DevWork &w, const float *f, const float *g, float *out, bool em, void *workspace,
-                   void *stream);
-int launch_adjoint(const DevWork &w, const float *u, const float *fin, float *out, bool em, void *stream);
+
+// Epilogues of the forward projection v = (H x)_i:
+enum FwdMode : int {
+    kFwdPlain = 0,   // out = v                                  (every FPA tile)
+    kFwdRatio = 1,   // out = g / v, 0 where v <= 0              (EM: u)
+    kFwdVjp = 2,     // out = -v u^2 / g, 0 where u == 0          (EM derivative: e)
+};
+// Epilogues of the back projection v = (H^T r)_j:
+enum AdjMode : int {
+    kAdjPlain = 0,   // out = v
+    kAdjUpdate = 1,  // out = in1 v / h, 0 where h == 0          (EM update)
+    kAdjVjpPre = 2,  // out = v (zeta), out2 = in1 in2 / h (b = y f / h),
+                     // flux[unit] = sum over the unit's voxels of b v
+    kAdjVjpGrad = 3, // out = in1 in2 / h + v (y zeta / h + H^T e)
+};
+int launch_forward(const DevWork &w, const float *x, const float *g, const float *u, float *out, int mode,
+                   void *workspace, void *stream);
+int launch_adjoint(const DevWork &w, const float *r, const float *in1, const float *in2, float *out, float *out2,
+                   float *flux, int mode, void *stream);
+// per-(adjoint unit, box) partial derivatives of the calibration values, then
+// their sums per entry into dv (accumulated if `accumulate`)
+int launch_value_grad(const DevWork &w, const float *u, const float *e, const float *b, const float *f,
+                      float *partial, void *stream);
+int launch_value_finish(const DevWork &w, const float *partial, const float *flux, float *dv, int64_t entry0,
+                        int64_t n_entries, bool accumulate, void *stream);
+// box values and column sums of the global wavelengths [lam0, lam1) from
+// the entry values `values` (entry `entry0` first)
+int launch_set_values(const DevWork &w, const float *values, int64_t entry0, int32_t lam0, int32_t lam1,
+                      void *stream);
 
 }  // namespace ctis

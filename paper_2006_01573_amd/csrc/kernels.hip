@@ -1,7 +1,11 @@
 // HIP kernels for gfx950: the forward projection H f (fused with the EM ratio
 // u = g / H f) and the back projection H^T u (fused with the EM update
 // f = f . H^T u / h).  White, Bell & Haygood, Sec. 2 eq. (em); Sec. 3 eqs.
-// (vs_linear) and (Htu).
+// (vs_linear) and (Htu).  The same two kernels, with other epilogues, and a
+// correlation-reduction kernel over the calibration boxes give the
+// reverse-mode derivative of an EM step (forward of b = y f / h with
+// e = -(H b) u / (H f); back projections with y zeta / h + H^T e; the value
+// derivatives sum u b + e f over the voxels of each box slot).
 //
 // Both are atomic-free gathers over dense B x B boxes of calibration
 // nonzeros.  A wavefront owns a 64 x 16 output tile (fast x slow axis) with a
@@ -52,6 +56,7 @@ struct Win {
     static constexpr int NR = 4 + B - 1;           // row segment a lane reads
     static constexpr int NV = (NR + 3) / 4;        // float4 reads per segment
     static constexpr int E = B - 1;                // window columns beyond the 64 lanes
+    static constexpr int ED = E > 0 ? E : 1;       // divisor for the extra slots (none when B = 1)
     static constexpr int NXT = (E * SY + 63) / 64; // extra slots per lane
     static constexpr int WREG = REG + 64;          // region incl. the box values (<= 64)
     static constexpr int MAXW = B <= 5 ? 16 : 8;   // waves per workgroup (VGPR budget)
@@ -94,6 +99,14 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Sum over the 64 lanes of a wavefront (every lane gets the total; a fixed
+// butterfly order, so the result does not depend on timing).
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
 }
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const float *base, int nfloats) {
@@ -155,7 +168,7 @@ __device__ __forceinline__ void load_forward(Pending<B> &pd, const float *f, con
             const int k = lane + 64 * t;
             unsigned off = kOutOfRange;
             if (k < Wn::E * Wn::SY) {
-                const int e = k % Wn::E, yy = k / Wn::E;
+                const int e = k % Wn::ED, yy = k / Wn::ED;
                 const int xe = xr + TX + e;
                 int ye = y0 + yy;
                 while (ye >= p.xi) ye -= p.xi;
@@ -181,7 +194,7 @@ __device__ __forceinline__ void load_forward(Pending<B> &pd, const float *f, con
             const int k = lane + 64 * t;
             unsigned off = kOutOfRange;
             if (k < Wn::E * Wn::SY) {
-                const int e = k % Wn::E, yy = k / Wn::E;
+                const int e = k % Wn::ED, yy = k / Wn::ED;
                 int xe = xr + TX + e, ye = y0;
                 while (xe >= p.gamma) {
                     xe -= p.gamma;
@@ -231,7 +244,7 @@ __device__ __forceinline__ void load_adjoint(Pending<B> &pd, __amdgpu_buffer_rsr
             const int k = lane + 64 * t;
             unsigned off = kOutOfRange;
             if (k < Wn::E * Wn::SY) {
-                const int e = k % Wn::E, yy = k / Wn::E;
+                const int e = k % Wn::ED, yy = k / Wn::ED;
                 int ye = y0 + yy;
                 while (ye >= p.xi) ye -= p.xi;
                 off = (unsigned)(xr + TX + e + p.gamma * ye) * 4u;
@@ -254,7 +267,7 @@ __device__ __forceinline__ void load_adjoint(Pending<B> &pd, __amdgpu_buffer_rsr
             const int k = lane + 64 * t;
             unsigned off = kOutOfRange;
             if (k < Wn::E * Wn::SY) {
-                const int e = k % Wn::E, yy = k / Wn::E;
+                const int e = k % Wn::ED, yy = k / Wn::ED;
                 int xe = xr + TX + e, ye = y0;
                 while (xe >= p.gamma) {
                     xe -= p.gamma;
@@ -270,8 +283,8 @@ __device__ __forceinline__ void load_adjoint(Pending<B> &pd, __amdgpu_buffer_rsr
     load_values<B>(pd, wtab, box, lane);
 }
 
-// Window into S[0, REG), box values into S[REG, REG + B*B).
-template <int B>
+// Window into S[0, REG), box values into S[REG, REG + B*B) (kValues).
+template <int B, bool kValues = true>
 __device__ __forceinline__ void store_window(float *S, const Pending<B> &pd, int lane) {
     using Wn = Win<B>;
 #pragma unroll
@@ -279,9 +292,9 @@ __device__ __forceinline__ void store_window(float *S, const Pending<B> &pd, int
 #pragma unroll
     for (int t = 0; t < Wn::NXT; ++t) {
         const int k = lane + 64 * t;
-        if (k < Wn::E * Wn::SY) S[(k / Wn::E) * Wn::SXP + TX + k % Wn::E] = pd.x[t];
+        if (k < Wn::E * Wn::SY) S[(k / Wn::ED) * Wn::SXP + TX + k % Wn::ED] = pd.x[t];
     }
-    if (lane < B * B) S[Wn::REG + lane] = pd.wt;
+    if (kValues && lane < B * B) S[Wn::REG + lane] = pd.wt;
 }
 
 // acc[k][q] += sum_{i,j < B} W[j*B + i] * S[(4ly + k + j) * SXP + 4lx + q + i]
@@ -338,6 +351,15 @@ __device__ __forceinline__ float row_sum(const float *lds, int nw, int row, int 
     _Pragma("unroll") for (int j = 0; j < kRowsPerWave; ++j)  \
         if (const int row = wv + j * nw; row < TY)
 
+// Forward epilogue: v = (H x)_i, gv = g_i, uv = u_i.
+//   ratio: u = g / v (0 where v <= 0);
+//   vjp:   e = -v u / ghat = -v u (u / g), 0 where u == 0 (u != 0 implies g != 0)
+__device__ __forceinline__ float fwd_epilogue(int mode, float v, float gv, float uv) {
+    if (mode == kFwdRatio) return v > 0.0f ? gv / v : 0.0f;
+    if (mode == kFwdVjp) return uv != 0.0f ? -(v * uv) * (uv / gv) : 0.0f;
+    return v;
+}
+
 // Forward projection.  Workgroups walk the unit list (grid stride); a unit is
 // a chunk of the boxes meeting one FPA tile of one frame.  A tile split into
 // several units writes one partial tile per unit to `partials`;
@@ -347,8 +369,9 @@ __global__ void __launch_bounds__(64 * Win<B>::MAXW) k_forward(const int4 *__res
                                                                const int4 *__restrict__ items, const int stride,
                                                                const int n_units, const float *__restrict__ box_wf,
                                                                const float *__restrict__ f,
-                                                               const float *__restrict__ g, float *__restrict__ out,
-                                                               float *__restrict__ partials, const int em) {
+                                                               const float *__restrict__ g,
+                                                               const float *__restrict__ uaux, float *__restrict__ out,
+                                                               float *__restrict__ partials, const int mode) {
     using Wn = Win<B>;
     extern __shared__ float4 lds4[];
     float *lds = reinterpret_cast<float *>(lds4);
@@ -371,11 +394,13 @@ __global__ void __launch_bounds__(64 * Win<B>::MAXW) k_forward(const int4 *__res
         const bool whole = m0.z == 1;
 
         // operands of the epilogue, fetched up front
-        float gpre[kRowsPerWave];
+        float gpre[kRowsPerWave], upre[kRowsPerWave];
         FOR_OWN_ROWS(j, row) {
             const int c = c0 + row;
-            gpre[j] = (em && whole && r < geo.gamma && c < geo.xi)
-                          ? g[(size_t)m2.x + (size_t)r + (size_t)geo.gamma * c] : 0.0f;
+            const bool in = mode != kFwdPlain && whole && r < geo.gamma && c < geo.xi;
+            const size_t i = (size_t)r + (size_t)geo.gamma * c;
+            gpre[j] = in ? g[(size_t)m2.x + i] : 0.0f;
+            upre[j] = (in && mode == kFwdVjp) ? uaux[(size_t)m2.y + i] : 0.0f;
         }
 
         float acc[4][4];
@@ -420,11 +445,9 @@ __global__ void __launch_bounds__(64 * Win<B>::MAXW) k_forward(const int4 *__res
         } else {
             FOR_OWN_ROWS(j, row) {
                 const int c = c0 + row;
-                float v = row_sum(lds, nw, row, lane);
-                if (r < geo.gamma && c < geo.xi) {
-                    if (em) v = v > 0.0f ? gpre[j] / v : 0.0f;
-                    out[(size_t)m2.y + (size_t)r + (size_t)geo.gamma * c] = v;
-                }
+                const float v = row_sum(lds, nw, row, lane);
+                if (r < geo.gamma && c < geo.xi)
+                    out[(size_t)m2.y + (size_t)r + (size_t)geo.gamma * c] = fwd_epilogue(mode, v, gpre[j], upre[j]);
             }
         }
         __syncthreads();   // the next unit reuses the LDS regions
@@ -435,8 +458,8 @@ __global__ void __launch_bounds__(64 * Win<B>::MAXW) k_forward(const int4 *__res
 // forward epilogue.  One workgroup (4 waves, 4 rows each) per split tile.
 __global__ void __launch_bounds__(256) k_finish_split(const int4 *__restrict__ split_meta,
                                                       const float *__restrict__ partials,
-                                                      const float *__restrict__ g, float *__restrict__ out,
-                                                      int em) {
+                                                      const float *__restrict__ g, const float *__restrict__ uaux,
+                                                      float *__restrict__ out, int mode) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int4 s0 = split_meta[2 * blockIdx.x], s1 = split_meta[2 * blockIdx.x + 1];
     const int r = s0.x + lane;
@@ -445,11 +468,11 @@ __global__ void __launch_bounds__(256) k_finish_split(const int4 *__restrict__ s
         const int row = wv + 4 * j, c = s0.y + row;
         if (r >= s1.x || c >= s1.y) continue;
         const size_t i = (size_t)r + (size_t)s1.x * c;
-        const float gv = em ? g[(size_t)s1.z + i] : 0.0f;
+        const float gv = mode != kFwdPlain ? g[(size_t)s1.z + i] : 0.0f;
+        const float uv = mode == kFwdVjp ? uaux[(size_t)s1.w + i] : 0.0f;
         float v = 0.0f;
         for (int ch = 0; ch < s0.z; ++ch) v += partials[((size_t)s0.w + ch) * (TX * TY) + row * TX + lane];
-        if (em) v = v > 0.0f ? gv / v : 0.0f;
-        out[(size_t)s1.w + i] = v;
+        out[(size_t)s1.w + i] = fwd_epilogue(mode, v, gv, uv);
     }
 }
 
@@ -459,8 +482,10 @@ __global__ void __launch_bounds__(64 * Win<B>::MAXW) k_adjoint(const int4 *__res
                                                                const int4 *__restrict__ items, const int stride,
                                                                const int n_units, const float *__restrict__ box_w,
                                                                const float *__restrict__ hsum,
-                                                               const float *__restrict__ u, const float *fin,
-                                                               float *out, const int em) {
+                                                               const float *__restrict__ u, const float *in1,
+                                                               const float *__restrict__ in2, float *out,
+                                                               float *__restrict__ out2, float *__restrict__ flux,
+                                                               const int mode) {
     using Wn = Win<B>;
     extern __shared__ float4 lds4[];
     float *lds = reinterpret_cast<float *>(lds4);
@@ -483,10 +508,14 @@ __global__ void __launch_bounds__(64 * Win<B>::MAXW) k_adjoint(const int4 *__res
         const int x = x0 + lane;
         const size_t sb = (size_t)(unsigned)m0.w;
 
-        float fpre[kRowsPerWave];
+        // operands of the epilogue (in1: f or y; in2: f or zeta), fetched up front
+        float p1[kRowsPerWave], p2[kRowsPerWave];
         FOR_OWN_ROWS(j, row) {
             const int y = y0 + row;
-            fpre[j] = (em && x < geo.a && y < geo.alpha) ? fin[sb + (size_t)x + (size_t)geo.a * y] : 0.0f;
+            const bool in = x < geo.a && y < geo.alpha;
+            const size_t o = sb + (size_t)x + (size_t)geo.a * y;
+            p1[j] = (in && mode != kAdjPlain) ? in1[o] : 0.0f;
+            p2[j] = (in && mode >= kAdjVjpPre) ? in2[o] : 0.0f;
         }
         const float hs = hsum[m0.z];
 
@@ -524,16 +553,309 @@ __global__ void __launch_bounds__(64 * Win<B>::MAXW) k_adjoint(const int4 *__res
         }
 
         park_tile(acc, lds, wv, lx, ly);
+        float fl = 0.0f;   // this lane's share of sum b zeta (kAdjVjpPre)
         FOR_OWN_ROWS(j, row) {
             const int y = y0 + row;
-            float v = row_sum(lds, nw, row, lane);
+            const float v = row_sum(lds, nw, row, lane);
             if (x < geo.a && y < geo.alpha) {
-                if (em) v = hs != 0.0f ? (fpre[j] * v) / hs : 0.0f;
-                out[sb + (size_t)x + (size_t)geo.a * y] = v;
+                const size_t o = sb + (size_t)x + (size_t)geo.a * y;
+                if (mode == kAdjPlain) {
+                    out[o] = v;
+                } else if (mode == kAdjUpdate) {
+                    out[o] = hs != 0.0f ? (p1[j] * v) / hs : 0.0f;
+                } else if (mode == kAdjVjpPre) {
+                    const float bj = hs != 0.0f ? (p1[j] * p2[j]) / hs : 0.0f;
+                    out[o] = v;
+                    out2[o] = bj;
+                    fl = __builtin_fmaf(bj, v, fl);
+                } else {
+                    out[o] = (hs != 0.0f ? (p1[j] * p2[j]) / hs : 0.0f) + v;
+                }
+            }
+        }
+        if (mode == kAdjVjpPre) {
+            // sum over the unit: wavefront butterfly, then the waves in order
+            fl = wave_sum(fl);
+            float *red = lds + nw * (TX * TY);   // past the parked tiles
+            if (lane == 0) red[wv] = fl;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                float t = 0.0f;
+                for (int w2 = 0; w2 < nw; ++w2) t += red[w2];
+                flux[unit] = t;
             }
         }
         __syncthreads();   // the next unit reuses the LDS regions
     }
+}
+
+// ---------------------------------------------------------------------------
+// Derivatives with respect to the calibration values.
+//
+// For box (rA, cA) of wavelength s and its slot (dr, dc), the entry at FPA
+// position p = (rA + dr) + gamma (cA + dc) is the H entry of voxel (x, y) at
+// pixel (p + x + gamma y) mod n, so its derivative gathers
+//   sum over voxels of  u(p + x + gamma y) b(x, y) + e(p + x + gamma y) f(x, y).
+// Units are the back-projection units (frame, wavelength, field-stop tile):
+// each wave takes boxes of the wavelength in turn, stages the u and e windows
+// of the box over the tile (the back projection's windows), correlates them
+// with the lane's 4 x 4 voxels of b and f for every slot, sums each slot over
+// the wavefront, and writes one partial per (unit, box, slot).
+
+constexpr int kVgWaves = 4;
+
+// u and e windows of one (field-stop tile, box) pair, at the same addresses
+// as the back projection's window.  Slots that meet no voxel inside the field
+// stop (xx >= xlim or yy >= ylim) load 0: the buffers hold no defined values
+// outside the pixels the forward kernels write.
+template <int B>
+__device__ __forceinline__ void load_pair(Pending<B> &pu, Pending<B> &pe, __amdgpu_buffer_rsrc_t ur,
+                                          __amdgpu_buffer_rsrc_t er, const Geo &p, int Xs, int Ys, int xlim,
+                                          int ylim, int lane) {
+    using Wn = Win<B>;
+    int q0, xr, yq, y0;
+    floor_divmod(Xs, p.gamma, q0, xr);
+    floor_divmod(Ys + q0, p.xi, yq, y0);
+    if (xr + Wn::SX <= p.gamma) {
+        const unsigned lane_off = lane < xlim ? (unsigned)(xr + lane) * 4u : kOutOfRange;
+        const unsigned row_step = (unsigned)p.gamma * 4u;
+        int y = y0;
+        unsigned row_off = (unsigned)(p.gamma * y0) * 4u;
+#pragma unroll
+        for (int yy = 0; yy < Wn::SY; ++yy) {
+            const bool ok = yy < ylim;
+            pu.v[yy] = bload(ur, ok ? lane_off : kOutOfRange, ok ? row_off : 0u);
+            pe.v[yy] = bload(er, ok ? lane_off : kOutOfRange, ok ? row_off : 0u);
+            ++y;
+            row_off += row_step;
+            if (y == p.xi) {
+                y = 0;
+                row_off = 0;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < Wn::NXT; ++t) {
+            const int k = lane + 64 * t;
+            unsigned off = kOutOfRange;
+            if (k < Wn::E * Wn::SY) {
+                const int e = k % Wn::ED, yy = k / Wn::ED;
+                if (TX + e < xlim && yy < ylim) {
+                    int ye = y0 + yy;
+                    while (ye >= p.xi) ye -= p.xi;
+                    off = (unsigned)(xr + TX + e + p.gamma * ye) * 4u;
+                }
+            }
+            pu.x[t] = bload(ur, off);
+            pe.x[t] = bload(er, off);
+        }
+    } else {
+        int xm = xr + lane, y = y0;
+        while (xm >= p.gamma) {
+            xm -= p.gamma;
+            y = step_mod(y, p.xi);
+        }
+#pragma unroll
+        for (int yy = 0; yy < Wn::SY; ++yy) {
+            const unsigned off = (lane < xlim && yy < ylim) ? (unsigned)(xm + p.gamma * y) * 4u : kOutOfRange;
+            pu.v[yy] = bload(ur, off);
+            pe.v[yy] = bload(er, off);
+            y = step_mod(y, p.xi);
+        }
+#pragma unroll
+        for (int t = 0; t < Wn::NXT; ++t) {
+            const int k = lane + 64 * t;
+            unsigned off = kOutOfRange;
+            if (k < Wn::E * Wn::SY) {
+                const int e = k % Wn::ED, yy = k / Wn::ED;
+                if (TX + e < xlim && yy < ylim) {
+                    int xe = xr + TX + e, ye = y0;
+                    while (xe >= p.gamma) {
+                        xe -= p.gamma;
+                        ye = step_mod(ye, p.xi);
+                    }
+                    ye += yy;
+                    while (ye >= p.xi) ye -= p.xi;
+                    off = (unsigned)(xe + p.gamma * ye) * 4u;
+                }
+            }
+            pu.x[t] = bload(ur, off);
+            pe.x[t] = bload(er, off);
+        }
+    }
+}
+
+// acc[j*B + i] += sum_{k,q < 4} bq[k][q] * Su[(4ly+k+j)*SXP + 4lx+q+i]
+//                             + fq[k][q] * Se[(4ly+k+j)*SXP + 4lx+q+i]
+template <int B>
+__device__ __forceinline__ void correlate_values(float (&acc)[B * B], const float *Su, const float *Se,
+                                                 const float (&bq)[4][4], const float (&fq)[4][4], int lx, int ly) {
+    using Wn = Win<B>;
+#pragma unroll
+    for (int row = 0; row < Wn::NR; ++row) {
+        float su[4 * Wn::NV], se[4 * Wn::NV];
+        const float4 *pu = reinterpret_cast<const float4 *>(Su + (4 * ly + row) * Wn::SXP + 4 * lx);
+        const float4 *pe = reinterpret_cast<const float4 *>(Se + (4 * ly + row) * Wn::SXP + 4 * lx);
+#pragma unroll
+        for (int v = 0; v < Wn::NV; ++v) {
+            const float4 a = pu[v], c = pe[v];
+            su[4 * v + 0] = a.x;
+            su[4 * v + 1] = a.y;
+            su[4 * v + 2] = a.z;
+            su[4 * v + 3] = a.w;
+            se[4 * v + 0] = c.x;
+            se[4 * v + 1] = c.y;
+            se[4 * v + 2] = c.z;
+            se[4 * v + 3] = c.w;
+        }
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            const int k = row - j;
+            if (k < 0 || k >= 4) continue;
+#pragma unroll
+            for (int i = 0; i < B; ++i) {
+                float t = acc[j * B + i];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    t = __builtin_fmaf(bq[k][q], su[q + i], t);
+                    t = __builtin_fmaf(fq[k][q], se[q + i], t);
+                }
+                acc[j * B + i] = t;
+            }
+        }
+    }
+}
+
+template <int B>
+__global__ void __launch_bounds__(64 * kVgWaves) k_value_grad(const int4 *__restrict__ meta,
+                                                              const int4 *__restrict__ items, const int stride,
+                                                              const int n_units, const float *__restrict__ u,
+                                                              const float *__restrict__ e,
+                                                              const float *__restrict__ b,
+                                                              const float *__restrict__ f,
+                                                              float *__restrict__ part) {
+    using Wn = Win<B>;
+    constexpr int BB = B * B;
+    extern __shared__ float4 lds4[];
+    float *lds = reinterpret_cast<float *>(lds4);
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nw = blockDim.x >> 6;
+    float *Su = lds + wv * (2 * Wn::REG);
+    float *Se = Su + Wn::REG;
+    const int lx = lane & 15, ly = lane >> 4;
+
+    for (int unit = blockIdx.x; unit < n_units; unit += gridDim.x) {
+        const int4 m0 = meta[3 * unit], m1 = meta[3 * unit + 1], m2 = meta[3 * unit + 2];
+        const int4 *list = items + (size_t)m0.z * stride;
+        const Geo geo{m1.x, m1.y, m1.z, m1.w};
+        const int x0 = m0.x, y0 = m0.y;
+        const int n = geo.gamma * geo.xi;
+        const __amdgpu_buffer_rsrc_t ur = rsrc(u + (size_t)(unsigned)m2.x, n);
+        const __amdgpu_buffer_rsrc_t er = rsrc(e + (size_t)(unsigned)m2.x, n);
+        const size_t sb = (size_t)(unsigned)m0.w;
+        const int xlim = geo.a - x0 + B - 1, ylim = geo.alpha - y0 + B - 1;
+
+        // this lane's 4 x 4 voxels of b and f (0 outside the field stop)
+        float bq[4][4], fq[4][4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int x = x0 + 4 * lx + q, y = y0 + 4 * ly + k;
+                const bool in = x < geo.a && y < geo.alpha;
+                const size_t o = sb + (size_t)x + (size_t)geo.a * y;
+                bq[k][q] = in ? b[o] : 0.0f;
+                fq[k][q] = in ? f[o] : 0.0f;
+            }
+
+        int k = wv;
+        int4 rec = record(list, k, stride);
+        Pending<B> pu, pe;
+        if (rec.w >= 0) load_pair<B>(pu, pe, ur, er, geo, rec.x + x0, rec.y + y0, xlim, ylim, lane);
+        while (rec.w >= 0) {
+            store_window<B, false>(Su, pu, lane);
+            store_window<B, false>(Se, pe, lane);
+            wave_lds_sync();
+            const int4 nxt = record(list, k + nw, stride);
+            if (nxt.w >= 0) load_pair<B>(pu, pe, ur, er, geo, nxt.x + x0, nxt.y + y0, xlim, ylim, lane);
+            float acc[BB];
+#pragma unroll
+            for (int t = 0; t < BB; ++t) acc[t] = 0.0f;
+            correlate_values<B>(acc, Su, Se, bq, fq, lx, ly);
+            wave_lds_sync();
+            float mine = 0.0f;
+#pragma unroll
+            for (int t = 0; t < BB; ++t) {
+                const float tot = wave_sum(acc[t]);
+                if (lane == t) mine = tot;
+            }
+            if (lane < BB) part[((size_t)unit * stride + k) * BB + lane] = mine;
+            k += nw;
+            rec = nxt;
+        }
+    }
+}
+
+// Per calibration entry: its slot's partials over every unit of its
+// wavelength (all frames sharing the plan), minus (sum of b zeta) / h_s.
+__global__ void __launch_bounds__(256) k_value_finish(const int32_t *__restrict__ entry_slot,
+                                                      const int32_t *__restrict__ box_lam,
+                                                      const int32_t *__restrict__ lam_box0,
+                                                      const int32_t *__restrict__ lam_units_ptr,
+                                                      const int32_t *__restrict__ lam_units, const int stride,
+                                                      const int BB, const float *__restrict__ part,
+                                                      const float *__restrict__ flux, const float *__restrict__ hsum,
+                                                      float *__restrict__ dv, const long long entry0,
+                                                      const long long n, const int accumulate) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int slot = entry_slot[entry0 + t];
+    float v = 0.0f;
+    if (slot >= 0) {
+        const int gb = slot / BB, k = slot - gb * BB;
+        const int gl = box_lam[gb], j = gb - lam_box0[gl];
+        double s = 0.0, fl = 0.0;
+        for (int p = lam_units_ptr[gl]; p < lam_units_ptr[gl + 1]; ++p) {
+            const int un = lam_units[p];
+            s += (double)part[((size_t)un * stride + j) * BB + k];
+            fl += (double)flux[un];
+        }
+        const float hs = hsum[gl];
+        v = (float)(s - (hs != 0.0f ? fl / (double)hs : 0.0));
+    }
+    dv[t] = accumulate ? dv[t] + v : v;
+}
+
+// New calibration values: one workgroup per wavelength [lam0 + blockIdx.x];
+// every slot of its boxes gets the sum (double) of its entries' values, and
+// h_s the sum (double) of the slots.
+__global__ void __launch_bounds__(256) k_set_values(const float *__restrict__ values, const long long entry0,
+                                                    const int32_t *__restrict__ slot_entries_ptr,
+                                                    const int32_t *__restrict__ slot_entries,
+                                                    const int32_t *__restrict__ lam_box0, const int lam0,
+                                                    const int BB, float *__restrict__ box_w,
+                                                    float *__restrict__ box_wf, float *__restrict__ hsum) {
+    __shared__ double red[256];
+    const int gl = lam0 + blockIdx.x;
+    const int s0 = lam_box0[gl] * BB, s1 = lam_box0[gl + 1] * BB;
+    double part = 0.0;
+    for (int slot = s0 + (int)threadIdx.x; slot < s1; slot += blockDim.x) {
+        double acc = 0.0;
+        for (int p = slot_entries_ptr[slot]; p < slot_entries_ptr[slot + 1]; ++p)
+            acc += (double)values[(long long)slot_entries[p] - entry0];
+        const float v = (float)acc;
+        const int gb = slot / BB, k = slot - gb * BB;
+        box_w[slot] = v;
+        box_wf[gb * BB + (BB - 1 - k)] = v;   // the forward kernel's reversed copy
+        part += (double)v;
+    }
+    red[threadIdx.x] = part;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) hsum[gl] = (float)red[0];
 }
 
 template <int B>
@@ -576,29 +898,30 @@ int grid_for(int n_units, size_t lds_bytes, int waves, bool persistent) {
 }
 
 template <int B>
-int forward_B(const DevWork &w, const float *f, const float *g, float *out, bool em, void *workspace,
+int forward_B(const DevWork &w, const float *x, const float *g, const float *u, float *out, int mode, void *workspace,
               hipStream_t st) {
-    const DevList &L = em ? w.fwd_em : w.fwd_full;
+    const DevList &L = mode == kFwdPlain ? w.fwd_full : w.fwd_em;
     if (L.n_units == 0) return 0;
     const size_t lds = (size_t)L.waves * Win<B>::WREG * sizeof(float);
     if (lds > 65536) {
         const int e = enable_large_lds<B>();
         if (e) return e;
     }
-    float *partials = (em && w.n_split > 0) ? (float *)((char *)workspace + w.partials_off) : nullptr;
+    float *partials = (mode != kFwdPlain && w.n_split > 0) ? (float *)((char *)workspace + w.partials_off) : nullptr;
     hipLaunchKernelGGL(k_forward<B>, dim3(grid_for(L.n_units, lds, L.waves, w.persistent)), dim3(64 * L.waves), lds, st,
-                       L.meta, L.items, L.stride, L.n_units, w.box_wf, f, g, out, partials, em ? 1 : 0);
+                       L.meta, L.items, L.stride, L.n_units, w.box_wf, x, g, u, out, partials, mode);
     if (partials) {
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return (int)e;
         hipLaunchKernelGGL(k_finish_split, dim3(w.n_split), dim3(256), 0, st, w.split_meta, (const float *)partials,
-                           g, out, 1);
+                           g, u, out, mode);
     }
     return (int)hipGetLastError();
 }
 
 template <int B>
-int adjoint_B(const DevWork &w, const float *u, const float *fin, float *out, bool em, hipStream_t st) {
+int adjoint_B(const DevWork &w, const float *r, const float *in1, const float *in2, float *out, float *out2,
+              float *flux, int mode, hipStream_t st) {
     const DevList &L = w.adj;
     if (L.n_units == 0) return 0;
     const size_t lds = (size_t)L.waves * Win<B>::WREG * sizeof(float);
@@ -607,7 +930,19 @@ int adjoint_B(const DevWork &w, const float *u, const float *fin, float *out, bo
         if (e) return e;
     }
     hipLaunchKernelGGL(k_adjoint<B>, dim3(grid_for(L.n_units, lds, L.waves, w.persistent)), dim3(64 * L.waves), lds, st,
-                       L.meta, L.items, L.stride, L.n_units, w.box_w, w.h, u, fin, out, em ? 1 : 0);
+                       L.meta, L.items, L.stride, L.n_units, w.box_w, w.h, r, in1, in2, out, out2, flux, mode);
+    return (int)hipGetLastError();
+}
+
+template <int B>
+int value_grad_B(const DevWork &w, const float *u, const float *e, const float *b, const float *f, float *part,
+                 hipStream_t st) {
+    const DevList &L = w.adj;
+    if (L.n_units == 0) return 0;
+    const size_t lds = (size_t)kVgWaves * 2 * Win<B>::REG * sizeof(float);
+    static_assert((size_t)kVgWaves * 2 * Win<8>::REG * sizeof(float) <= 65536, "value kernel LDS");
+    hipLaunchKernelGGL(k_value_grad<B>, dim3(L.n_units), dim3(64 * kVgWaves), lds, st, L.meta, L.items, L.stride,
+                       L.n_units, u, e, b, f, part);
     return (int)hipGetLastError();
 }
 
@@ -616,35 +951,71 @@ int adjoint_B(const DevWork &w, const float *u, const float *fin, float *out, bo
 int max_waves(int B) { return B <= 5 ? Win<1>::MAXW : Win<8>::MAXW; }
 int min_waves() { return kMinWaves; }
 
-int launch_forward(const DevWork &w, const float *f, const float *g, float *out, bool em, void *workspace,
-                   void *stream) {
+int launch_forward(const DevWork &w, const float *x, const float *g, const float *u, float *out, int mode,
+                   void *workspace, void *stream) {
     hipStream_t st = (hipStream_t)stream;
     switch (w.B) {
-        case 1: return forward_B<1>(w, f, g, out, em, workspace, st);
-        case 2: return forward_B<2>(w, f, g, out, em, workspace, st);
-        case 3: return forward_B<3>(w, f, g, out, em, workspace, st);
-        case 4: return forward_B<4>(w, f, g, out, em, workspace, st);
-        case 5: return forward_B<5>(w, f, g, out, em, workspace, st);
-        case 6: return forward_B<6>(w, f, g, out, em, workspace, st);
-        case 7: return forward_B<7>(w, f, g, out, em, workspace, st);
-        case 8: return forward_B<8>(w, f, g, out, em, workspace, st);
+        case 1: return forward_B<1>(w, x, g, u, out, mode, workspace, st);
+        case 2: return forward_B<2>(w, x, g, u, out, mode, workspace, st);
+        case 3: return forward_B<3>(w, x, g, u, out, mode, workspace, st);
+        case 4: return forward_B<4>(w, x, g, u, out, mode, workspace, st);
+        case 5: return forward_B<5>(w, x, g, u, out, mode, workspace, st);
+        case 6: return forward_B<6>(w, x, g, u, out, mode, workspace, st);
+        case 7: return forward_B<7>(w, x, g, u, out, mode, workspace, st);
+        case 8: return forward_B<8>(w, x, g, u, out, mode, workspace, st);
     }
     return (int)hipErrorInvalidValue;
 }
 
-int launch_adjoint(const DevWork &w, const float *u, const float *fin, float *out, bool em, void *stream) {
+int launch_adjoint(const DevWork &w, const float *r, const float *in1, const float *in2, float *out, float *out2,
+                   float *flux, int mode, void *stream) {
     hipStream_t st = (hipStream_t)stream;
     switch (w.B) {
-        case 1: return adjoint_B<1>(w, u, fin, out, em, st);
-        case 2: return adjoint_B<2>(w, u, fin, out, em, st);
-        case 3: return adjoint_B<3>(w, u, fin, out, em, st);
-        case 4: return adjoint_B<4>(w, u, fin, out, em, st);
-        case 5: return adjoint_B<5>(w, u, fin, out, em, st);
-        case 6: return adjoint_B<6>(w, u, fin, out, em, st);
-        case 7: return adjoint_B<7>(w, u, fin, out, em, st);
-        case 8: return adjoint_B<8>(w, u, fin, out, em, st);
+        case 1: return adjoint_B<1>(w, r, in1, in2, out, out2, flux, mode, st);
+        case 2: return adjoint_B<2>(w, r, in1, in2, out, out2, flux, mode, st);
+        case 3: return adjoint_B<3>(w, r, in1, in2, out, out2, flux, mode, st);
+        case 4: return adjoint_B<4>(w, r, in1, in2, out, out2, flux, mode, st);
+        case 5: return adjoint_B<5>(w, r, in1, in2, out, out2, flux, mode, st);
+        case 6: return adjoint_B<6>(w, r, in1, in2, out, out2, flux, mode, st);
+        case 7: return adjoint_B<7>(w, r, in1, in2, out, out2, flux, mode, st);
+        case 8: return adjoint_B<8>(w, r, in1, in2, out, out2, flux, mode, st);
     }
     return (int)hipErrorInvalidValue;
+}
+
+int launch_value_grad(const DevWork &w, const float *u, const float *e, const float *b, const float *f, float *part,
+                      void *stream) {
+    hipStream_t st = (hipStream_t)stream;
+    switch (w.B) {
+        case 1: return value_grad_B<1>(w, u, e, b, f, part, st);
+        case 2: return value_grad_B<2>(w, u, e, b, f, part, st);
+        case 3: return value_grad_B<3>(w, u, e, b, f, part, st);
+        case 4: return value_grad_B<4>(w, u, e, b, f, part, st);
+        case 5: return value_grad_B<5>(w, u, e, b, f, part, st);
+        case 6: return value_grad_B<6>(w, u, e, b, f, part, st);
+        case 7: return value_grad_B<7>(w, u, e, b, f, part, st);
+        case 8: return value_grad_B<8>(w, u, e, b, f, part, st);
+    }
+    return (int)hipErrorInvalidValue;
+}
+
+int launch_value_finish(const DevWork &w, const float *part, const float *flux, float *dv, int64_t entry0,
+                        int64_t n_entries, bool accumulate, void *stream) {
+    if (n_entries <= 0) return 0;
+    const int64_t blocks = (n_entries + 255) / 256;
+    hipLaunchKernelGGL(k_value_finish, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, w.entry_slot,
+                       w.box_lam, w.lam_box0, w.lam_units_ptr, w.lam_units, w.adj.stride, w.B * w.B, part, flux,
+                       (const float *)w.h, dv, (long long)entry0, (long long)n_entries, accumulate ? 1 : 0);
+    return (int)hipGetLastError();
+}
+
+int launch_set_values(const DevWork &w, const float *values, int64_t entry0, int32_t lam0, int32_t lam1,
+                      void *stream) {
+    if (lam1 <= lam0) return 0;
+    hipLaunchKernelGGL(k_set_values, dim3((unsigned)(lam1 - lam0)), dim3(256), 0, (hipStream_t)stream, values,
+                       (long long)entry0, w.slot_entries_ptr, w.slot_entries, w.lam_box0, lam0, w.B * w.B, w.box_w,
+                       w.box_wf, w.h);
+    return (int)hipGetLastError();
 }
 
 }  // namespace ctis

@@ -121,15 +121,19 @@ void circular_window_or(int64_t len, int64_t win, Get get, Set set) {
 }  // namespace
 
 ctis_status build_host_tables(ctis_plan *p, const int64_t *lambda_ptr, const int32_t *fpa_index,
-                              const float *value, int forced_box) {
+                              const float *value, int forced_box, bool keep_zeros) {
     HostTables &T = p->ht;
     const int32_t w = p->w, gamma = p->gamma, xi = p->xi, a = p->a, alpha = p->alpha;
     const int64_t n = p->n;
 
-    // -- 1. merge duplicates (sum in double), drop exact zeros ------------------
+    // -- 1. merge duplicates (sum in double), drop exact zeros unless the
+    //       structure is to be kept (positions, whatever their values) ---------
     std::vector<std::vector<Entry>> ent(w);
     T.nonneg = true;
     T.nnz = 0;
+    T.n_in = lambda_ptr[w];
+    T.dropped = false;
+    std::vector<int32_t> in_merged((size_t)T.n_in, -1);   // input entry -> merged entry of its wavelength
     for (int32_t s = 0; s < w; ++s) {
         const int64_t b = lambda_ptr[s], e = lambda_ptr[s + 1];
         std::vector<std::pair<int64_t, int64_t>> order;   // (index, position)
@@ -145,10 +149,13 @@ ctis_status build_host_tables(ctis_plan *p, const int64_t *lambda_ptr, const int
                 ++k2;
             }
             const float v = (float)acc;
-            if (v != 0.0f) {
+            if (v != 0.0f || keep_zeros) {
                 const int64_t idx = order[k].first;
+                for (size_t kk = k; kk < k2; ++kk) in_merged[(size_t)order[kk].second] = (int32_t)out.size();
                 out.push_back(Entry{idx, (int32_t)(idx % gamma), (int32_t)(idx / gamma), v});
                 if (v < 0.0f) T.nonneg = false;
+            } else {
+                T.dropped = true;
             }
             k = k2;
         }
@@ -183,30 +190,39 @@ ctis_status build_host_tables(ctis_plan *p, const int64_t *lambda_ptr, const int
     T.box_wf.clear();
     T.lambda_box_ptr.assign((size_t)w + 1, 0);
     const int BB = B * B;
+    T.entry_slot.assign((size_t)T.n_in, -1);
     for (int32_t s = 0; s < w; ++s) {
         struct Box {
             int32_t r, c;
             std::vector<float> v;
+            std::vector<std::pair<int32_t, int32_t>> members;   // (merged entry, slot in the box)
         };
         std::vector<Box> boxes;
         for (const auto &cp : comps[s]) {
             auto cl = cells(cp, ent[s], B);
             const size_t base = boxes.size();
             for (auto [ci, cj] : cl) boxes.push_back(Box{cp.rmin + B * ci, cp.cmin + B * cj,
-                                                          std::vector<float>((size_t)BB, 0.0f)});
+                                                          std::vector<float>((size_t)BB, 0.0f), {}});
             for (int32_t t : cp.members) {
                 const int32_t ci = (ent[s][t].r - cp.rmin) / B, cj = (ent[s][t].c - cp.cmin) / B;
                 auto it = std::lower_bound(cl.begin(), cl.end(), std::make_pair(ci, cj), [](auto x, auto y) {
                     return x.second != y.second ? x.second < y.second : x.first < y.first;
                 });
                 Box &bx = boxes[base + (size_t)(it - cl.begin())];
-                bx.v[(size_t)((ent[s][t].c - bx.c) * B + (ent[s][t].r - bx.r))] = ent[s][t].v;
+                const int32_t k = (ent[s][t].c - bx.c) * B + (ent[s][t].r - bx.r);
+                bx.v[(size_t)k] = ent[s][t].v;
+                bx.members.emplace_back(t, k);
             }
         }
         std::sort(boxes.begin(), boxes.end(), [&](const Box &x, const Box &y) {
             return (int64_t)x.r + (int64_t)gamma * x.c < (int64_t)y.r + (int64_t)gamma * y.c;
         });
+        // slot of every merged entry: global box id * B*B + position in the box
+        std::vector<int64_t> merged_slot(ent[s].size(), -1);
         for (const auto &bx : boxes) {
+            const int64_t gb = (int64_t)T.box_lambda.size();
+            if ((gb + 1) * BB > INT32_MAX) return fail(CTIS_E_TOO_LARGE, "too many calibration boxes");
+            for (auto [t, k] : bx.members) merged_slot[(size_t)t] = gb * BB + k;
             T.box_rc.push_back(bx.r);
             T.box_rc.push_back(bx.c);
             T.box_lambda.push_back(s);
@@ -215,9 +231,9 @@ ctis_status build_host_tables(ctis_plan *p, const int64_t *lambda_ptr, const int
                 for (int dr = 0; dr < B; ++dr)
                     T.box_wf.push_back(bx.v[(size_t)((B - 1 - dc) * B + (B - 1 - dr))]);
         }
-        if ((int64_t)T.box_lambda.size() > INT32_MAX)
-            return fail(CTIS_E_TOO_LARGE, "too many calibration boxes");
         T.lambda_box_ptr[(size_t)s + 1] = (int32_t)T.box_lambda.size();
+        for (int64_t t = lambda_ptr[s]; t < lambda_ptr[s + 1]; ++t)
+            if (in_merged[(size_t)t] >= 0) T.entry_slot[(size_t)t] = (int32_t)merged_slot[(size_t)in_merged[(size_t)t]];
     }
     const int32_t nb = (int32_t)T.box_lambda.size();
 
@@ -343,24 +359,47 @@ ctis_status build_work(const std::vector<FrameRef> &frames, bool with_full, Host
     if (frames.empty()) return fail(CTIS_E_ARG, "no frames");
     hw.B = frames[0].plan->ht.B;
     const int B = hw.B;
+    const int BB = B * B;
+    // distinct plans in order of first appearance; frames that share a plan
+    // share its boxes, wavelengths and values
+    std::vector<const ctis_plan *> dplans;
     int32_t box_base = 0, lambda_base = 0, max_chunk_items = 0, max_full_items = 0, max_boxes = 0;
-    std::vector<int32_t> fbox(frames.size()), flam(frames.size());
+    int64_t entry_base = 0;
     for (size_t k = 0; k < frames.size(); ++k) {
-        const HostTables &T = frames[k].plan->ht;
+        const ctis_plan *pl = frames[k].plan;
+        const HostTables &T = pl->ht;
         if (T.B != B) return fail(CTIS_E_ARG, "all frames of a batch need the same box side B");
-        fbox[k] = box_base;
-        flam[k] = lambda_base;
-        box_base += (int32_t)T.box_lambda.size();
-        lambda_base += frames[k].plan->w;
-        hw.box_w.insert(hw.box_w.end(), T.box_w.begin(), T.box_w.end());
-        hw.box_wf.insert(hw.box_wf.end(), T.box_wf.begin(), T.box_wf.end());
-        hw.h.insert(hw.h.end(), T.h.begin(), T.h.end());
+        const auto it = std::find(dplans.begin(), dplans.end(), pl);
+        if (it != dplans.end()) {
+            hw.frame_plan.push_back((int32_t)(it - dplans.begin()));
+        } else {
+            hw.frame_plan.push_back((int32_t)dplans.size());
+            dplans.push_back(pl);
+            hw.plan_box0.push_back(box_base);
+            hw.plan_lam0.push_back(lambda_base);
+            hw.plan_entry0.push_back(entry_base);
+            if ((int64_t)box_base + (int64_t)T.box_lambda.size() > INT32_MAX / BB ||
+                (int64_t)lambda_base + pl->w > INT32_MAX || entry_base + T.n_in > INT32_MAX)
+                return fail(CTIS_E_TOO_LARGE, "too many boxes, wavelengths or entries");
+            box_base += (int32_t)T.box_lambda.size();
+            lambda_base += pl->w;
+            entry_base += T.n_in;
+            hw.box_w.insert(hw.box_w.end(), T.box_w.begin(), T.box_w.end());
+            hw.box_wf.insert(hw.box_wf.end(), T.box_wf.begin(), T.box_wf.end());
+            hw.h.insert(hw.h.end(), T.h.begin(), T.h.end());
+            hw.dropped = hw.dropped || T.dropped;
+        }
         max_chunk_items = std::max(max_chunk_items, std::min(T.max_items, T.chunk));
         max_full_items = std::max(max_full_items, T.max_items);
         max_boxes = std::max(max_boxes, T.max_boxes);
-        hw.u_floats = std::max<int64_t>(hw.u_floats, frames[k].u_base + frames[k].plan->n);
+        hw.u_floats = std::max<int64_t>(hw.u_floats, frames[k].u_base + pl->n);
+        hw.f_floats = std::max<int64_t>(hw.f_floats, frames[k].f_base + pl->m);
     }
-    if ((size_t)box_base * B * B > (size_t)INT32_MAX) return fail(CTIS_E_TOO_LARGE, "too many boxes");
+    std::vector<int32_t> fbox(frames.size()), flam(frames.size());
+    for (size_t k = 0; k < frames.size(); ++k) {
+        fbox[k] = hw.plan_box0[(size_t)hw.frame_plan[k]];
+        flam[k] = hw.plan_lam0[(size_t)hw.frame_plan[k]];
+    }
 
     // forward lists: units of every frame, heaviest first (a stable order)
     auto build_fwd = [&](HostList &L, bool em, int32_t stride) -> ctis_status {
@@ -434,33 +473,87 @@ ctis_status build_work(const std::vector<FrameRef> &frames, bool with_full, Host
     HostList &A = hw.adj;
     A.stride = std::max(1, max_boxes);
     A.items.assign((size_t)4 * lambda_base * A.stride, 0);
-    for (size_t k = 0; k < frames.size(); ++k) {
-        const ctis_plan *pl = frames[k].plan;
+    for (size_t d = 0; d < dplans.size(); ++d) {
+        const ctis_plan *pl = dplans[d];
         const HostTables &T = pl->ht;
         for (int32_t s = 0; s < pl->w; ++s) {
-            const int32_t gs = flam[k] + s;
+            const int32_t gs = hw.plan_lam0[d] + s;
             const int32_t b0 = T.lambda_box_ptr[(size_t)s], b1 = T.lambda_box_ptr[(size_t)s + 1];
             for (int32_t j = 0; j < A.stride; ++j) {
                 int32_t *rec = &A.items[(size_t)4 * ((size_t)gs * A.stride + j)];
                 if (b0 + j < b1) {
                     rec[0] = T.box_rc[2 * (size_t)(b0 + j)];
                     rec[1] = T.box_rc[2 * (size_t)(b0 + j) + 1];
-                    rec[3] = fbox[k] + b0 + j;
+                    rec[3] = hw.plan_box0[d] + b0 + j;
                 } else {
                     rec[3] = -1;
                 }
             }
+        }
+    }
+    std::vector<std::vector<int32_t>> units_of(lambda_base);
+    for (size_t k = 0; k < frames.size(); ++k) {
+        const ctis_plan *pl = frames[k].plan;
+        const HostTables &T = pl->ht;
+        for (int32_t s = 0; s < pl->w; ++s) {
+            const int32_t gs = flam[k] + s;
             for (int32_t vt = 0; vt < T.nbx * T.nby; ++vt) {
+                units_of[(size_t)gs].push_back((int32_t)(A.meta.size() / 12));
                 push4(A.meta, (vt % T.nbx) * kTileFast, (vt / T.nbx) * kTileSlow, gs,
                       (int32_t)(frames[k].f_base + (int64_t)s * pl->ell));
                 push4(A.meta, pl->a, pl->alpha, pl->gamma, pl->xi);
                 push4(A.meta, (int32_t)frames[k].u_base, 0, 0, 0);
+                if (A.meta.size() / 12 > (size_t)INT32_MAX / ((size_t)A.stride * BB))
+                    return fail(CTIS_E_TOO_LARGE, "too many back-projection units");
             }
         }
     }
     A.n_units = (int32_t)(A.meta.size() / 12);
     A.waves = waves_for(max_boxes, B);
+
+    // value tables
+    hw.box_lam.resize((size_t)box_base);
+    hw.lam_box0.assign((size_t)lambda_base + 1, box_base);
+    hw.entry_slot.reserve((size_t)entry_base);
+    for (size_t d = 0; d < dplans.size(); ++d) {
+        const HostTables &T = dplans[d]->ht;
+        for (size_t b = 0; b < T.box_lambda.size(); ++b)
+            hw.box_lam[(size_t)hw.plan_box0[d] + b] = hw.plan_lam0[d] + T.box_lambda[b];
+        for (int32_t s = 0; s < dplans[d]->w; ++s)
+            hw.lam_box0[(size_t)(hw.plan_lam0[d] + s)] = hw.plan_box0[d] + T.lambda_box_ptr[(size_t)s];
+        for (int32_t slot : T.entry_slot) hw.entry_slot.push_back(slot < 0 ? -1 : hw.plan_box0[d] * BB + slot);
+    }
+    hw.lam_units_ptr.assign(1, 0);
+    for (const auto &v : units_of) {
+        hw.lam_units.insert(hw.lam_units.end(), v.begin(), v.end());
+        hw.lam_units_ptr.push_back((int32_t)hw.lam_units.size());
+    }
+    const size_t n_slots = (size_t)box_base * BB;
+    hw.slot_entries_ptr.assign(n_slots + 1, 0);
+    for (int32_t slot : hw.entry_slot)
+        if (slot >= 0) hw.slot_entries_ptr[(size_t)slot + 1]++;
+    for (size_t k = 0; k < n_slots; ++k) hw.slot_entries_ptr[k + 1] += hw.slot_entries_ptr[k];
+    hw.slot_entries.resize((size_t)hw.slot_entries_ptr[n_slots]);
+    {
+        std::vector<int32_t> pos(hw.slot_entries_ptr.begin(), hw.slot_entries_ptr.end() - 1);
+        for (size_t t = 0; t < hw.entry_slot.size(); ++t)
+            if (hw.entry_slot[t] >= 0) hw.slot_entries[(size_t)pos[(size_t)hw.entry_slot[t]]++] = (int32_t)t;
+    }
     return CTIS_OK;
+}
+
+Layout layout_for(const HostWork &hw) {
+    auto up256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    Layout L{};
+    L.partials_off = up256((size_t)hw.u_floats * sizeof(float));
+    L.em_bytes = L.partials_off + (size_t)hw.partial_slots * kTileFast * kTileSlow * sizeof(float);
+    L.e_off = up256(L.em_bytes);
+    L.zeta_off = L.e_off + up256((size_t)hw.u_floats * sizeof(float));
+    L.b_off = L.zeta_off + up256((size_t)hw.f_floats * sizeof(float));
+    L.hpart_off = L.b_off + up256((size_t)hw.f_floats * sizeof(float));
+    L.vg_off = L.hpart_off + up256((size_t)hw.adj.n_units * sizeof(float));
+    L.vjp_bytes = L.vg_off + up256((size_t)hw.adj.n_units * hw.adj.stride * hw.B * hw.B * sizeof(float));
+    return L;
 }
 
 ctis_status upload_work(const HostWork &hw, DevWork &dw) {
@@ -480,6 +573,13 @@ ctis_status upload_work(const HostWork &hw, DevWork &dw) {
         {hw.box_w.data(), hw.box_w.size() * 4, 0},
         {hw.box_wf.data(), hw.box_wf.size() * 4, 0},
         {hw.h.data(), hw.h.size() * 4, 0},
+        {hw.entry_slot.data(), hw.entry_slot.size() * 4, 0},
+        {hw.box_lam.data(), hw.box_lam.size() * 4, 0},
+        {hw.lam_box0.data(), hw.lam_box0.size() * 4, 0},
+        {hw.lam_units_ptr.data(), hw.lam_units_ptr.size() * 4, 0},
+        {hw.lam_units.data(), hw.lam_units.size() * 4, 0},
+        {hw.slot_entries_ptr.data(), hw.slot_entries_ptr.size() * 4, 0},
+        {hw.slot_entries.data(), hw.slot_entries.size() * 4, 0},
     };
     size_t total = 0;
     for (auto &pt : parts) {
@@ -516,12 +616,28 @@ ctis_status upload_work(const HostWork &hw, DevWork &dw) {
     dw.adj.n_units = hw.adj.n_units;
     dw.adj.stride = hw.adj.stride;
     dw.adj.waves = hw.adj.waves;
-    dw.box_w = (const float *)at(7);
-    dw.box_wf = (const float *)at(8);
-    dw.h = (const float *)at(9);
-    auto up256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    dw.partials_off = up256((size_t)hw.u_floats * sizeof(float));
-    dw.workspace_bytes = dw.partials_off + (size_t)hw.partial_slots * kTileFast * kTileSlow * sizeof(float);
+    dw.box_w = (float *)at(7);
+    dw.box_wf = (float *)at(8);
+    dw.h = (float *)at(9);
+    dw.entry_slot = (const int32_t *)at(10);
+    dw.box_lam = (const int32_t *)at(11);
+    dw.lam_box0 = (const int32_t *)at(12);
+    dw.lam_units_ptr = (const int32_t *)at(13);
+    dw.lam_units = (const int32_t *)at(14);
+    dw.slot_entries_ptr = (const int32_t *)at(15);
+    dw.slot_entries = (const int32_t *)at(16);
+    dw.n_entries = (int64_t)hw.entry_slot.size();
+    dw.n_lambda = (int32_t)hw.h.size();
+    dw.n_boxes = (int32_t)hw.box_lam.size();
+    const Layout L = layout_for(hw);
+    dw.partials_off = L.partials_off;
+    dw.workspace_bytes = L.em_bytes;
+    dw.e_off = L.e_off;
+    dw.zeta_off = L.zeta_off;
+    dw.b_off = L.b_off;
+    dw.hpart_off = L.hpart_off;
+    dw.vg_off = L.vg_off;
+    dw.vjp_workspace_bytes = L.vjp_bytes;
     dw.mem = mem;
     return CTIS_OK;
 }

@@ -18,6 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libctis.so")
 
 CTIS_PLAN_HOST_ONLY = 0x1
+CTIS_PLAN_KEEP_ZEROS = 0x2
 
 STATUS_NAMES = {0: "CTIS_OK", 1: "CTIS_E_ARG", 2: "CTIS_E_INDEX", 3: "CTIS_E_VALUE",
                 4: "CTIS_E_TOO_LARGE", 5: "CTIS_E_NOMEM", 6: "CTIS_E_HIP",
@@ -28,7 +29,9 @@ EXPORTED = ["ctis_plan_create", "ctis_plan_destroy", "ctis_plan_get_info",
             "ctis_plan_lambda_sums", "ctis_plan_export_boxes", "ctis_plan_export_worklist",
             "ctis_forward", "ctis_adjoint", "ctis_em_iterate", "ctis_em_forward_ratio", "ctis_em_adjoint_update", "ctis_status_str",
             "ctis_last_error", "ctis_version", "ctis_batch_create", "ctis_batch_destroy",
-            "ctis_batch_get_info", "ctis_batch_forward", "ctis_batch_adjoint", "ctis_batch_em_iterate"]
+            "ctis_batch_get_info", "ctis_batch_forward", "ctis_batch_adjoint", "ctis_batch_em_iterate",
+            "ctis_em_vjp", "ctis_plan_set_values", "ctis_batch_em_vjp", "ctis_batch_set_values",
+            "ctis_batch_plan_entries"]
 
 
 def CTIS_PLAN_BOX(b: int) -> int:
@@ -52,7 +55,9 @@ class _Info(ctypes.Structure):
                 ("n_tiles", ctypes.c_int32), ("n_active_tiles", ctypes.c_int32),
                 ("n_items", ctypes.c_int64), ("workspace_bytes", ctypes.c_size_t),
                 ("nonnegative", ctypes.c_int32), ("device", ctypes.c_int32),
-                ("waves_forward", ctypes.c_int32), ("waves_adjoint", ctypes.c_int32)]
+                ("waves_forward", ctypes.c_int32), ("waves_adjoint", ctypes.c_int32),
+                ("n_entries", ctypes.c_int64), ("vjp_workspace_bytes", ctypes.c_size_t),
+                ("dropped", ctypes.c_int32)]
 
 
 class _BatchInfo(ctypes.Structure):
@@ -60,7 +65,8 @@ class _BatchInfo(ctypes.Structure):
                 ("m_total", ctypes.c_int64), ("n_total", ctypes.c_int64),
                 ("forward_units", ctypes.c_int64), ("adjoint_units", ctypes.c_int64),
                 ("waves_forward", ctypes.c_int32), ("waves_adjoint", ctypes.c_int32),
-                ("workspace_bytes", ctypes.c_size_t)]
+                ("workspace_bytes", ctypes.c_size_t), ("n_plans", ctypes.c_int32),
+                ("n_entries", ctypes.c_int64), ("vjp_workspace_bytes", ctypes.c_size_t)]
 
 
 @dataclasses.dataclass(frozen=True)
@@ -87,6 +93,9 @@ class PlanInfo:
     device: int
     waves_forward: int
     waves_adjoint: int
+    n_entries: int
+    vjp_workspace_bytes: int
+    dropped: bool
 
 
 _lock = threading.Lock()
@@ -140,6 +149,16 @@ def load_library(path: str | None = None):
         L.ctis_batch_adjoint.restype = st
         L.ctis_batch_em_iterate.argtypes = [vp, vp, vp, i32, vp, sz, vp]
         L.ctis_batch_em_iterate.restype = st
+        L.ctis_em_vjp.argtypes = [vp, vp, vp, vp, vp, vp, i32, vp, sz, vp]
+        L.ctis_em_vjp.restype = st
+        L.ctis_plan_set_values.argtypes = [vp, vp, vp]
+        L.ctis_plan_set_values.restype = st
+        L.ctis_batch_em_vjp.argtypes = [vp, vp, vp, vp, vp, vp, i32, vp, sz, vp]
+        L.ctis_batch_em_vjp.restype = st
+        L.ctis_batch_set_values.argtypes = [vp, i32, vp, vp]
+        L.ctis_batch_set_values.restype = st
+        L.ctis_batch_plan_entries.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        L.ctis_batch_plan_entries.restype = st
         L.ctis_status_str.argtypes = [st]
         L.ctis_status_str.restype = ctypes.c_char_p
         L.ctis_last_error.argtypes = []
@@ -177,7 +196,7 @@ class Plan:
     """
 
     def __init__(self, a, alpha, w, gamma, xi, lambda_ptr, fpa_index, value, *,
-                 box: int = 0, host_only: bool = False, device=None):
+                 box: int = 0, host_only: bool = False, keep_zeros: bool = False, device=None):
         self._L = load_library()
         self._handle = None
         ptr = np.ascontiguousarray(lambda_ptr, dtype=np.int64)
@@ -187,7 +206,8 @@ class Plan:
             raise ValueError("lambda_ptr must have w+1 entries")
         if ptr.size and ptr[-1] > min(idx.size, val.size):
             raise ValueError("fpa_index/value shorter than lambda_ptr[w]")
-        flags = CTIS_PLAN_BOX(box) | (CTIS_PLAN_HOST_ONLY if host_only else 0)
+        flags = (CTIS_PLAN_BOX(box) | (CTIS_PLAN_HOST_ONLY if host_only else 0)
+                 | (CTIS_PLAN_KEEP_ZEROS if keep_zeros else 0))
         self.device = None
         if not host_only:
             torch = _torch()
@@ -236,6 +256,7 @@ class Plan:
         _check(self._L, self._L.ctis_plan_get_info(self._handle, ctypes.byref(inf)), "ctis_plan_get_info")
         d = {k: getattr(inf, k) for k, _ in _Info._fields_}
         d["nonnegative"] = bool(d["nonnegative"])
+        d["dropped"] = bool(d["dropped"])
         return PlanInfo(**d)
 
     def lambda_sums(self) -> np.ndarray:
@@ -351,6 +372,49 @@ class Plan:
         _check(self._L, st, "ctis_em_iterate")
         return f
 
+    # -- derivatives ------------------------------------------------------------------
+    def vjp_workspace(self):
+        """Workspace for em_vjp (also valid for em)."""
+        torch = _torch()
+        return torch.empty(max(self.info.vjp_workspace_bytes // 4, 64), dtype=torch.float32, device=self.device)
+
+    def set_values(self, values):
+        """New calibration values (one per entry given at creation, device
+        float32) on the same structure."""
+        self._need_device()
+        torch = _torch()
+        v = self._dev_tensor(values, self.info.n_entries, "values") if self.info.n_entries else None
+        st = self._L.ctis_plan_set_values(self._handle, ctypes.c_void_p(v.data_ptr()) if v is not None else None,
+                                          _stream(torch, self.device))
+        _check(self._L, st, "ctis_plan_set_values")
+
+    def em_vjp(self, g, f, y, df=None, dvalues=None, accumulate: bool = False, workspace=None):
+        """Reverse-mode derivative of one EM iteration at input f for the
+        upstream gradient y = dL/df'.  Returns dL/df (into ``df`` if given; it
+        may be ``y`` itself) and, if ``dvalues`` is given, writes (or adds, with
+        ``accumulate``) dL/dv per calibration entry into it."""
+        self._need_device()
+        torch = _torch()
+        g = self._dev_tensor(g, self.info.n, "g")
+        f = self._dev_tensor(f, self.info.m, "f")
+        y = self._dev_tensor(y, self.info.m, "y")
+        if df is None:
+            df = torch.empty(self.shape_f, dtype=torch.float32, device=self.device)
+        if workspace is None:
+            workspace = self.vjp_workspace()
+        wp, wb = self._ws(workspace)
+        dvp = None
+        if dvalues is not None:
+            if not (dvalues.is_contiguous() and dvalues.dtype == torch.float32
+                    and dvalues.numel() == self.info.n_entries):
+                raise ValueError("dvalues must be a contiguous float32 tensor with one element per entry")
+            dvp = ctypes.c_void_p(dvalues.data_ptr())
+        st = self._L.ctis_em_vjp(self._handle, ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(f.data_ptr()),
+                                 ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(df.data_ptr()), dvp,
+                                 1 if accumulate else 0, wp, wb, _stream(torch, self.device))
+        _check(self._L, st, "ctis_em_vjp")
+        return df
+
 
 class Batch:
     """Frames with their own plans (uneven sizes), reconstructed together: one
@@ -438,3 +502,47 @@ class Batch:
                                            workspace.numel() * workspace.element_size(), _stream(torch, self.device))
         _check(self._L, st, "ctis_batch_em_iterate")
         return f_all
+
+    # -- derivatives ------------------------------------------------------------------
+    def vjp_workspace(self):
+        torch = _torch()
+        return torch.empty(max(self.info["vjp_workspace_bytes"] // 4, 64), dtype=torch.float32, device=self.device)
+
+    def plan_entries(self, k: int):
+        """(offset, count) of frame k's plan's entries in the batch's value arrays."""
+        off, cnt = ctypes.c_int64(), ctypes.c_int64()
+        _check(self._L, self._L.ctis_batch_plan_entries(self._handle, int(k), ctypes.byref(off), ctypes.byref(cnt)),
+               "ctis_batch_plan_entries")
+        return off.value, cnt.value
+
+    def set_values(self, k: int, values):
+        """New values for the plan of frame k (and the frames sharing it)."""
+        torch = _torch()
+        v = torch.as_tensor(values, dtype=torch.float32, device=self.device).contiguous()
+        if v.numel() != self.plan_entries(k)[1]:
+            raise ValueError("values must have one element per entry of the frame's plan")
+        st = self._L.ctis_batch_set_values(self._handle, int(k), ctypes.c_void_p(v.data_ptr()) if v.numel() else None,
+                                           _stream(torch, self.device))
+        _check(self._L, st, "ctis_batch_set_values")
+
+    def em_vjp(self, g_all, f_all, y_all, df_all=None, dvalues=None, accumulate: bool = False, workspace=None):
+        """Batch form of Plan.em_vjp; dvalues holds the entries of the batch's
+        distinct plans back to back (see plan_entries)."""
+        torch = _torch()
+        if df_all is None:
+            df_all = torch.empty(int(self.f_offsets[-1]), dtype=torch.float32, device=self.device)
+        if workspace is None:
+            workspace = self.vjp_workspace()
+        dvp = None
+        if dvalues is not None:
+            if not (dvalues.is_contiguous() and dvalues.dtype == torch.float32
+                    and dvalues.numel() == self.info["n_entries"]):
+                raise ValueError("dvalues must be a contiguous float32 tensor with n_entries elements")
+            dvp = ctypes.c_void_p(dvalues.data_ptr())
+        st = self._L.ctis_batch_em_vjp(self._handle, ctypes.c_void_p(g_all.data_ptr()),
+                                       ctypes.c_void_p(f_all.data_ptr()), ctypes.c_void_p(y_all.data_ptr()),
+                                       ctypes.c_void_p(df_all.data_ptr()), dvp, 1 if accumulate else 0,
+                                       ctypes.c_void_p(workspace.data_ptr()),
+                                       workspace.numel() * workspace.element_size(), _stream(torch, self.device))
+        _check(self._L, st, "ctis_batch_em_vjp")
+        return df_all

@@ -248,6 +248,25 @@ def batched_configs(n_frames: int = 64, cfg_id: int = 4):
     return out
 
 
+# ---------------------------------------------------------------------------
+# differentiable unrolled EM: frames of the c2 shape sharing one calibration
+
+def differentiable_cases(n_frames: int = 8, iters: int = 10, cfg_id: int = 5):
+    """Frames for the differentiable reconstruction: a = alpha = 64, w = 32,
+    FPA 512 (the c2 shape and kernel model), ``iters`` unrolled EM
+    iterations, Poisson noise at 1e4 peak photons.  All frames share the
+    calibration of frame 0 (one plan); each has its own f_true and noise."""
+    base = CONFIGS[2]
+    cfg = Config(f"c5-differentiable {n_frames} frames a=alpha=64 w=32 FPA512 K={iters}",
+                 base.geometry, base.kernel, iters=iters, noise=base.noise, photons=base.photons)
+    ptr, idx, val = make_kernels(cfg.geometry, cfg.kernel, rng_for(cfg_id, 0))
+    cases = []
+    for k in range(n_frames):
+        rng = rng_for(cfg_id, k + 1)
+        cases.append(Case(cfg, ptr, idx, val, make_ftrue(cfg.geometry, rng), rng))
+    return cases
+
+
 def random_kernels(geo: Geometry, nnz_per_lambda: int, rng: np.random.Generator,
                    nonneg: bool = True, clustered: bool = False):
     """Arbitrary sparse calibration images (for edge-case tests): uniform random

@@ -231,3 +231,34 @@ def test_config_plans_c1_c2_c3(oracle_mod, lib):
         np.testing.assert_allclose(p.lambda_sums(),
                                    np.add.reduceat(case.value.astype(np.float64), case.lambda_ptr[:-1]),
                                    rtol=1e-6)
+
+
+@pytest.mark.parametrize("box", [0, 1, 3, 5])
+def test_keep_zeros_keeps_every_position_in_a_box(oracle_mod, lib, box):
+    """With CTIS_PLAN_KEEP_ZEROS the structure is the set of given positions:
+    an explicit zero and a duplicate pair that cancels stay inside boxes (as
+    zero-valued slots); without it they are dropped and the plan says so."""
+    geo = W.Geometry(9, 6, 3, 40, 30)
+    rng = np.random.default_rng(box + 7)
+    ptr, idx, val = W.random_kernels(geo, 14, rng, clustered=True)
+    val[2] = 0.0
+    idx[4] = idx[3]
+    val[4] = -val[3]
+    dropped = ctis.Plan(geo.a, geo.alpha, geo.w, geo.gamma, geo.xi, ptr, idx, val, box=box, host_only=True)
+    kept = ctis.Plan(geo.a, geo.alpha, geo.w, geo.gamma, geo.xi, ptr, idx, val, box=box, host_only=True,
+                     keep_zeros=True)
+    assert dropped.info.dropped and not kept.info.dropped
+    assert kept.info.n_entries == dropped.info.n_entries == int(ptr[-1])
+    distinct = sum(np.unique(idx[ptr[s]:ptr[s + 1]]).size for s in range(geo.w))
+    assert kept.info.nnz == distinct and dropped.info.nnz < distinct
+    # the values are the merged calibration either way
+    np.testing.assert_array_equal(reconstruct_calibration(kept, geo), reconstruct_calibration(dropped, geo))
+    lam, rc, _ = kept.boxes()
+    B = kept.info.box
+    for s in range(geo.w):
+        for i in idx[ptr[s]:ptr[s + 1]]:
+            r, c = int(i) % geo.gamma, int(i) // geo.gamma
+            inside = [(lam[k] == s and rc[k, 0] <= r < rc[k, 0] + B and rc[k, 1] <= c < rc[k, 1] + B)
+                      for k in range(lam.size)]
+            assert sum(inside) >= 1, (s, r, c)
+    assert kept.info.vjp_workspace_bytes > kept.info.workspace_bytes > 0
