@@ -4,9 +4,10 @@
 One step = one full EM solve of the workload (the datacube reset to all ones,
 then the configuration's iteration count of fused forward+ratio and
 adjoint+update kernels), with the plan and the frame already resident in GPU
-memory.  The JSON line reports EM iterations/s (the headline), voxel updates/s,
-the roofline position of the dominant kernel (HIP-event durations of every
-launch, measured in a second timed pass over the same steps), and the FP64
+memory; by default the solve is captured once in a HIP graph and each step
+replays it (``--launch stream`` launches the kernels one by one instead).  The JSON line reports EM iterations/s (the headline), voxel updates/s,
+the roofline position of the dominant kernel (its average duration over a HIP
+graph of back-to-back launches, HIP events around the replays), and the FP64
 oracle's rate on the host cores over a bounded sample of the same workload.
 
     python bench.py [--steps K] [--warmup W] [--config 2]
@@ -90,6 +91,9 @@ def main(argv=None) -> int:
     ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5],
                     help="1-3: one frame; 4: 64 uneven frames, batched vs sequential; "
                          "5: gradients of 10 unrolled EM iterations, 8 frames sharing one plan")
+    ap.add_argument("--launch", choices=["graph", "stream"], default="graph",
+                    help="graph: each step is one replay of a HIP graph holding the whole solve; "
+                         "stream: the solve's kernels are launched one by one on the stream")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -142,52 +146,72 @@ def main(argv=None) -> int:
     ws = plan.workspace()
     torch.cuda.synchronize()
 
-    def step():
+    def solve():
         f.fill_(1.0)
         plan.em(g, K, f=f, workspace=ws)
 
-    progress(f"warmup {args.warmup} steps")
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    progress(f"timing {args.steps} steps of {K} EM iterations")
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    e0.record()
-    for _ in range(args.steps):
+
+    def timed(run, steps):
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        e0.record()
+        for _ in range(steps):
+            run()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1), time.perf_counter() - w0
+
+    def graph_of(fn):
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            fn()                                   # warm-up outside the capture
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        gr = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gr):
+            fn()
+        return gr
+
+    solve_graph = graph_of(solve)
+    step = solve_graph.replay if args.launch == "graph" else solve
+    progress(f"warmup {args.warmup} steps ({args.launch} launch)")
+    for _ in range(args.warmup):
         step()
-    e1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    ms = e0.elapsed_time(e1)
+    progress(f"timing {args.steps} steps of {K} EM iterations")
+    ms, wall = timed(step, args.steps)
     sec = ms / 1e3
     it_s = args.steps * K / sec
     f_out = f.clone()
     if not torch.isfinite(f_out).all() or (f_out < 0).any():
         print("bench.py: EM produced a negative or non-finite value", file=sys.stderr)
         return 1
+    other = solve if args.launch == "graph" else solve_graph.replay
+    other_ms, _ = timed(other, args.steps)
+    other_it_s = args.steps * K / (other_ms / 1e3)
 
-    # per-kernel durations: each of the two EM kernels launched back to back on
-    # the benchmark stream (the same launches the EM loop makes, on fixed
-    # inputs), HIP events around the whole run
+    # per-kernel durations: each of the two EM kernels launched back to back
+    # (the launches the EM loop makes, on fixed inputs) inside one HIP graph
+    # of `reps` launches, HIP events around its replays on the stream the
+    # graph runs on; the same launches one by one on the stream for comparison
     progress("per-kernel timing pass")
-    launches = args.steps * K
+    reps = 100
     f_in = f_out.clone()
     f_tmp = torch.empty_like(f_in)
     plan.em_forward_ratio(f_in, g, ws)
-    avg = {}
+    avg, avg_stream = {}, {}
     for name, launch in (("forward_ratio", lambda: plan.em_forward_ratio(f_in, g, ws)),
                          ("adjoint_update", lambda: plan.em_adjoint_update(ws, f_in, f_tmp))):
-        launch()
-        torch.cuda.synchronize()
-        e0.record()
-        for _ in range(launches):
-            launch()
-        e1.record()
-        torch.cuda.synchronize()
-        avg[name] = e0.elapsed_time(e1) * 1e-3 / launches
+        def many(launch=launch):
+            for _ in range(reps):
+                launch()
+        gr = graph_of(many)
+        t, _ = timed(gr.replay, 5)
+        avg[name] = t * 1e-3 / (5 * reps)
+        t, _ = timed(many, 5)
+        avg_stream[name] = t * 1e-3 / (5 * reps)
     m, n_supp = info.m, info.n_support
     bytes_ = {"forward_ratio": 4 * (m + 2 * n_supp), "adjoint_update": 4 * (2 * m + n_supp)}
     flops_ = {k: 2 * info.ell * info.nnz for k in bytes_}
@@ -205,8 +229,10 @@ def main(argv=None) -> int:
                 "frac": achieved / FP32_VALU_PEAK_TFLOPS, "traffic": traffic,
                 "frac_of_unpacked_fp32": achieved / FP32_VALU_UNPACKED_TFLOPS}
     roof.update({"kernel": dom, "avg_launch_us": avg[dom] * 1e6,
+                 "avg_launch_us_stream_launched": avg_stream[dom] * 1e6,
                  "algorithmic_bytes_per_launch": bytes_[dom], "algorithmic_flop_per_launch": flops_[dom],
                  "other_kernel": {k: {"avg_launch_us": avg[k] * 1e6,
+                                      "avg_launch_us_stream_launched": avg_stream[k] * 1e6,
                                       "achieved_GBps": bytes_[k] / avg[k] / 1e9}
                                   for k in avg if k != dom}})
 
@@ -230,6 +256,8 @@ def main(argv=None) -> int:
         "voxel_updates_per_s": it_s * m,
         "frames_per_s": args.steps / sec,
         "wall_s": wall,
+        "launch": args.launch,
+        ("stream_launch_em_iters_per_s" if args.launch == "graph" else "graph_launch_em_iters_per_s"): other_it_s,
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

@@ -11,8 +11,8 @@
 // nonzeros.  A wavefront owns a 64 x 16 output tile (fast x slow axis) with a
 // 4 x 4 register micro-tile per lane, stages the (64+B-1) x (16+B-1) input
 // window of one box into its own LDS region, and correlates it with the box's
-// values.  Each wave keeps the next two boxes' windows in flight in
-// registers while it computes the current one.  The waves of a workgroup split the boxes of one tile and meet
+// values.  Each wave keeps the next box's window in flight in registers
+// while it computes the current one.  The waves of a workgroup split the boxes of one tile and meet
 // in an LDS reduction in a fixed order (deterministic results); the reduced
 // tile leaves row by row, so every epilogue load and store is a contiguous
 // 256-byte wavefront access.
@@ -103,7 +103,8 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // Sum over the 64 lanes of a wavefront (every lane gets the total; a fixed
 // butterfly order, so the result does not depend on timing).
-__device__ __forceinline__ float wave_sum(float v) {
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
@@ -113,10 +114,10 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const float *base, int nf
     return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, nfloats * 4, kRsrcWord3);
 }
 
-// raw 32-bit buffer load, reinterpreted as float (the builtin returns the
-// bits); byte offset = voff (per lane) + soff (wave-uniform)
-__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff = 0) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+// raw 32-bit buffer load at byte offset `off`, reinterpreted as float (the
+// builtin returns the bits)
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
 }
 
 // Frame geometry of a work unit.
@@ -131,10 +132,10 @@ __device__ __forceinline__ void load_values(Pending<B> &pd, const float *__restr
 }
 
 // Forward window of one (tile, box) item, rec = (Xs, Ys, f_off, box):
-// slot (xx, yy) <- fE((Xs + xx) + gamma*(Ys + yy) mod n).
-// Interior windows (no window row crosses the end of an FPA column, so the
-// slow-axis index of a row is the same for every lane) take the row offset
-// as the buffer's scalar offset; other windows decode every slot.
+// slot (xx, yy) <- fE((Xs + xx) + gamma*(Ys + yy) mod n).  Each lane decodes
+// its column once (the window origin needs two scalar divisions) and then
+// steps row by row.  (Taking the row offset of windows that stay inside one
+// FPA column as the buffer's scalar offset was measured slower.)
 template <int B>
 __device__ __forceinline__ void load_forward(Pending<B> &pd, const float *f, const float *__restrict__ wtab,
                                              const Geo &p, int4 rec, int lane) {
@@ -144,68 +145,34 @@ __device__ __forceinline__ void load_forward(Pending<B> &pd, const float *f, con
     int q0, xr, yq, y0;
     floor_divmod(Xs, p.gamma, q0, xr);
     floor_divmod(Ys + q0, p.xi, yq, y0);
-    if (xr + Wn::SX <= p.gamma) {
-        const int xm = xr + lane;
-        const unsigned lane_off = xm < p.a ? (unsigned)xm * 4u : kOutOfRange;
-        const unsigned row_step = (unsigned)p.a * 4u;
-        int y = y0;
-        unsigned row_off = (unsigned)(p.a * y0) * 4u;
+    int xm = xr + lane, y = y0;
+    while (xm >= p.gamma) {
+        xm -= p.gamma;
+        y = step_mod(y, p.xi);
+    }
+    const bool vx = xm < p.a;
 #pragma unroll
-        for (int yy = 0; yy < Wn::SY; ++yy) {
-            // rows outside the field stop: every lane out of range (and a
-            // scalar offset of 0, so no address leaves the block)
-            const bool row_ok = y < p.alpha;
-            pd.v[yy] = bload(fr, row_ok ? lane_off : kOutOfRange, row_ok ? row_off : 0u);
-            ++y;
-            row_off += row_step;
-            if (y == p.xi) {
-                y = 0;
-                row_off = 0;
+    for (int yy = 0; yy < Wn::SY; ++yy) {
+        const bool ok = vx && (y < p.alpha);
+        pd.v[yy] = bload(fr, ok ? (unsigned)(xm + p.a * y) * 4u : kOutOfRange);
+        y = step_mod(y, p.xi);
+    }
+#pragma unroll
+    for (int t = 0; t < Wn::NXT; ++t) {
+        const int k = lane + 64 * t;
+        unsigned off = kOutOfRange;
+        if (k < Wn::E * Wn::SY) {
+            const int e = k % Wn::ED, yy = k / Wn::ED;
+            int xe = xr + TX + e, ye = y0;
+            while (xe >= p.gamma) {
+                xe -= p.gamma;
+                ye = step_mod(ye, p.xi);
             }
+            ye += yy;
+            while (ye >= p.xi) ye -= p.xi;
+            if (xe < p.a && ye < p.alpha) off = (unsigned)(xe + p.a * ye) * 4u;
         }
-#pragma unroll
-        for (int t = 0; t < Wn::NXT; ++t) {
-            const int k = lane + 64 * t;
-            unsigned off = kOutOfRange;
-            if (k < Wn::E * Wn::SY) {
-                const int e = k % Wn::ED, yy = k / Wn::ED;
-                const int xe = xr + TX + e;
-                int ye = y0 + yy;
-                while (ye >= p.xi) ye -= p.xi;
-                if (xe < p.a && ye < p.alpha) off = (unsigned)(xe + p.a * ye) * 4u;
-            }
-            pd.x[t] = bload(fr, off);
-        }
-    } else {
-        int xm = xr + lane, y = y0;
-        while (xm >= p.gamma) {
-            xm -= p.gamma;
-            y = step_mod(y, p.xi);
-        }
-        const bool vx = xm < p.a;
-#pragma unroll
-        for (int yy = 0; yy < Wn::SY; ++yy) {
-            const bool ok = vx && (y < p.alpha);
-            pd.v[yy] = bload(fr, ok ? (unsigned)(xm + p.a * y) * 4u : kOutOfRange);
-            y = step_mod(y, p.xi);
-        }
-#pragma unroll
-        for (int t = 0; t < Wn::NXT; ++t) {
-            const int k = lane + 64 * t;
-            unsigned off = kOutOfRange;
-            if (k < Wn::E * Wn::SY) {
-                const int e = k % Wn::ED, yy = k / Wn::ED;
-                int xe = xr + TX + e, ye = y0;
-                while (xe >= p.gamma) {
-                    xe -= p.gamma;
-                    ye = step_mod(ye, p.xi);
-                }
-                ye += yy;
-                while (ye >= p.xi) ye -= p.xi;
-                if (xe < p.a && ye < p.alpha) off = (unsigned)(xe + p.a * ye) * 4u;
-            }
-            pd.x[t] = bload(fr, off);
-        }
+        pd.x[t] = bload(fr, off);
     }
     load_values<B>(pd, wtab, rec.w, lane);
 }
@@ -215,7 +182,6 @@ __device__ __forceinline__ void load_forward(Pending<B> &pd, const float *f, con
 // (xx >= a + B - 1 - x0 or yy >= alpha + B - 1 - y0) only ever meet output
 // voxels outside the field stop, which are never written, so they need no
 // masking; their addresses are still reduced mod n and stay in bounds.
-// Interior windows take the row offset as the buffer's scalar offset.
 template <int B>
 __device__ __forceinline__ void load_adjoint(Pending<B> &pd, __amdgpu_buffer_rsrc_t ur,
                                              const float *__restrict__ wtab, const Geo &p, int Xs, int Ys,
@@ -224,61 +190,32 @@ __device__ __forceinline__ void load_adjoint(Pending<B> &pd, __amdgpu_buffer_rsr
     int q0, xr, yq, y0;
     floor_divmod(Xs, p.gamma, q0, xr);
     floor_divmod(Ys + q0, p.xi, yq, y0);
-    if (xr + Wn::SX <= p.gamma) {
-        const unsigned lane_off = (unsigned)(xr + lane) * 4u;
-        const unsigned row_step = (unsigned)p.gamma * 4u;
-        int y = y0;
-        unsigned row_off = (unsigned)(p.gamma * y0) * 4u;
+    int xm = xr + lane, y = y0;
+    while (xm >= p.gamma) {
+        xm -= p.gamma;
+        y = step_mod(y, p.xi);
+    }
 #pragma unroll
-        for (int yy = 0; yy < Wn::SY; ++yy) {
-            pd.v[yy] = bload(ur, lane_off, row_off);
-            ++y;
-            row_off += row_step;
-            if (y == p.xi) {
-                y = 0;
-                row_off = 0;
+    for (int yy = 0; yy < Wn::SY; ++yy) {
+        pd.v[yy] = bload(ur, (unsigned)(xm + p.gamma * y) * 4u);
+        y = step_mod(y, p.xi);
+    }
+#pragma unroll
+    for (int t = 0; t < Wn::NXT; ++t) {
+        const int k = lane + 64 * t;
+        unsigned off = kOutOfRange;
+        if (k < Wn::E * Wn::SY) {
+            const int e = k % Wn::ED, yy = k / Wn::ED;
+            int xe = xr + TX + e, ye = y0;
+            while (xe >= p.gamma) {
+                xe -= p.gamma;
+                ye = step_mod(ye, p.xi);
             }
+            ye += yy;
+            while (ye >= p.xi) ye -= p.xi;
+            off = (unsigned)(xe + p.gamma * ye) * 4u;
         }
-#pragma unroll
-        for (int t = 0; t < Wn::NXT; ++t) {
-            const int k = lane + 64 * t;
-            unsigned off = kOutOfRange;
-            if (k < Wn::E * Wn::SY) {
-                const int e = k % Wn::ED, yy = k / Wn::ED;
-                int ye = y0 + yy;
-                while (ye >= p.xi) ye -= p.xi;
-                off = (unsigned)(xr + TX + e + p.gamma * ye) * 4u;
-            }
-            pd.x[t] = bload(ur, off);
-        }
-    } else {
-        int xm = xr + lane, y = y0;
-        while (xm >= p.gamma) {
-            xm -= p.gamma;
-            y = step_mod(y, p.xi);
-        }
-#pragma unroll
-        for (int yy = 0; yy < Wn::SY; ++yy) {
-            pd.v[yy] = bload(ur, (unsigned)(xm + p.gamma * y) * 4u);
-            y = step_mod(y, p.xi);
-        }
-#pragma unroll
-        for (int t = 0; t < Wn::NXT; ++t) {
-            const int k = lane + 64 * t;
-            unsigned off = kOutOfRange;
-            if (k < Wn::E * Wn::SY) {
-                const int e = k % Wn::ED, yy = k / Wn::ED;
-                int xe = xr + TX + e, ye = y0;
-                while (xe >= p.gamma) {
-                    xe -= p.gamma;
-                    ye = step_mod(ye, p.xi);
-                }
-                ye += yy;
-                while (ye >= p.xi) ye -= p.xi;
-                off = (unsigned)(xe + p.gamma * ye) * 4u;
-            }
-            pd.x[t] = bload(ur, off);
-        }
+        pd.x[t] = bload(ur, off);
     }
     load_values<B>(pd, wtab, box, lane);
 }
@@ -386,8 +323,7 @@ __global__ void __launch_bounds__(64 * Win<B>::MAXW) k_forward(const int4 *__res
         int k = wv;
         int4 rec0 = record(list, k, stride);
         int4 rec1 = record(list, k + nw, stride);
-        int4 rec2 = record(list, k + 2 * nw, stride);
-        const int4 m0 = meta[3 * unit], m1 = meta[3 * unit + 1], m2 = meta[3 * unit + 2];
+                const int4 m0 = meta[3 * unit], m1 = meta[3 * unit + 1], m2 = meta[3 * unit + 2];
         const Geo geo{m1.x, m1.y, m1.z, m1.w};
         const int r0 = m0.x, c0 = m0.y;
         const int r = r0 + lane;
@@ -411,31 +347,18 @@ __global__ void __launch_bounds__(64 * Win<B>::MAXW) k_forward(const int4 *__res
 
         // two windows in flight: pa holds item k, pb item k + nw; while item k
         // is computed, item k + 2nw is fetched into the buffer item k came from
-        Pending<B> pa, pb;
+        Pending<B> pa;
         if (rec0.w >= 0) load_forward<B>(pa, f, box_wf, geo, rec0, lane);
-        if (rec1.w >= 0) load_forward<B>(pb, f, box_wf, geo, rec1, lane);
         while (rec0.w >= 0) {
             store_window<B>(S, pa, lane);
             wave_lds_sync();
-            int4 rec3 = record(list, k + 3 * nw, stride);
-            if (rec2.w >= 0) load_forward<B>(pa, f, box_wf, geo, rec2, lane);
+            k += nw;
+            const int4 rec3 = record(list, k + nw, stride);
+            if (rec1.w >= 0) load_forward<B>(pa, f, box_wf, geo, rec1, lane);
             correlate<B>(acc, S, lx, ly);
             wave_lds_sync();
-            k += nw;
             rec0 = rec1;
-            rec1 = rec2;
-            rec2 = rec3;
-            if (rec0.w < 0) break;
-            store_window<B>(S, pb, lane);
-            wave_lds_sync();
-            rec3 = record(list, k + 3 * nw, stride);
-            if (rec2.w >= 0) load_forward<B>(pb, f, box_wf, geo, rec2, lane);
-            correlate<B>(acc, S, lx, ly);
-            wave_lds_sync();
-            k += nw;
-            rec0 = rec1;
-            rec1 = rec2;
-            rec2 = rec3;
+            rec1 = rec3;
         }
 
         park_tile(acc, lds, wv, lx, ly);
@@ -501,8 +424,7 @@ __global__ void __launch_bounds__(64 * Win<B>::MAXW) k_adjoint(const int4 *__res
         int k = wv;
         int4 rec0 = record(list, k, stride);
         int4 rec1 = record(list, k + nw, stride);
-        int4 rec2 = record(list, k + 2 * nw, stride);
-        const Geo geo{m1.x, m1.y, m1.z, m1.w};
+                const Geo geo{m1.x, m1.y, m1.z, m1.w};
         const int x0 = m0.x, y0 = m0.y;
         const __amdgpu_buffer_rsrc_t ur = rsrc(u + (size_t)(unsigned)m2.x, geo.gamma * geo.xi);
         const int x = x0 + lane;
@@ -525,31 +447,18 @@ __global__ void __launch_bounds__(64 * Win<B>::MAXW) k_adjoint(const int4 *__res
 #pragma unroll
             for (int q = 0; q < 4; ++q) acc[a][q] = 0.0f;
 
-        Pending<B> pa, pb;
+        Pending<B> pa;
         if (rec0.w >= 0) load_adjoint<B>(pa, ur, box_w, geo, rec0.x + x0, rec0.y + y0, rec0.w, lane);
-        if (rec1.w >= 0) load_adjoint<B>(pb, ur, box_w, geo, rec1.x + x0, rec1.y + y0, rec1.w, lane);
         while (rec0.w >= 0) {
             store_window<B>(S, pa, lane);
             wave_lds_sync();
-            int4 rec3 = record(list, k + 3 * nw, stride);
-            if (rec2.w >= 0) load_adjoint<B>(pa, ur, box_w, geo, rec2.x + x0, rec2.y + y0, rec2.w, lane);
+            k += nw;
+            const int4 rec3 = record(list, k + nw, stride);
+            if (rec1.w >= 0) load_adjoint<B>(pa, ur, box_w, geo, rec1.x + x0, rec1.y + y0, rec1.w, lane);
             correlate<B>(acc, S, lx, ly);
             wave_lds_sync();
-            k += nw;
             rec0 = rec1;
-            rec1 = rec2;
-            rec2 = rec3;
-            if (rec0.w < 0) break;
-            store_window<B>(S, pb, lane);
-            wave_lds_sync();
-            rec3 = record(list, k + 3 * nw, stride);
-            if (rec2.w >= 0) load_adjoint<B>(pb, ur, box_w, geo, rec2.x + x0, rec2.y + y0, rec2.w, lane);
-            correlate<B>(acc, S, lx, ly);
-            wave_lds_sync();
-            k += nw;
-            rec0 = rec1;
-            rec1 = rec2;
-            rec2 = rec3;
+            rec1 = rec3;
         }
 
         park_tile(acc, lds, wv, lx, ly);
@@ -616,71 +525,37 @@ __device__ __forceinline__ void load_pair(Pending<B> &pu, Pending<B> &pe, __amdg
     int q0, xr, yq, y0;
     floor_divmod(Xs, p.gamma, q0, xr);
     floor_divmod(Ys + q0, p.xi, yq, y0);
-    if (xr + Wn::SX <= p.gamma) {
-        const unsigned lane_off = lane < xlim ? (unsigned)(xr + lane) * 4u : kOutOfRange;
-        const unsigned row_step = (unsigned)p.gamma * 4u;
-        int y = y0;
-        unsigned row_off = (unsigned)(p.gamma * y0) * 4u;
+    int xm = xr + lane, y = y0;
+    while (xm >= p.gamma) {
+        xm -= p.gamma;
+        y = step_mod(y, p.xi);
+    }
 #pragma unroll
-        for (int yy = 0; yy < Wn::SY; ++yy) {
-            const bool ok = yy < ylim;
-            pu.v[yy] = bload(ur, ok ? lane_off : kOutOfRange, ok ? row_off : 0u);
-            pe.v[yy] = bload(er, ok ? lane_off : kOutOfRange, ok ? row_off : 0u);
-            ++y;
-            row_off += row_step;
-            if (y == p.xi) {
-                y = 0;
-                row_off = 0;
-            }
-        }
+    for (int yy = 0; yy < Wn::SY; ++yy) {
+        const unsigned off = (lane < xlim && yy < ylim) ? (unsigned)(xm + p.gamma * y) * 4u : kOutOfRange;
+        pu.v[yy] = bload(ur, off);
+        pe.v[yy] = bload(er, off);
+        y = step_mod(y, p.xi);
+    }
 #pragma unroll
-        for (int t = 0; t < Wn::NXT; ++t) {
-            const int k = lane + 64 * t;
-            unsigned off = kOutOfRange;
-            if (k < Wn::E * Wn::SY) {
-                const int e = k % Wn::ED, yy = k / Wn::ED;
-                if (TX + e < xlim && yy < ylim) {
-                    int ye = y0 + yy;
-                    while (ye >= p.xi) ye -= p.xi;
-                    off = (unsigned)(xr + TX + e + p.gamma * ye) * 4u;
+    for (int t = 0; t < Wn::NXT; ++t) {
+        const int k = lane + 64 * t;
+        unsigned off = kOutOfRange;
+        if (k < Wn::E * Wn::SY) {
+            const int e = k % Wn::ED, yy = k / Wn::ED;
+            if (TX + e < xlim && yy < ylim) {
+                int xe = xr + TX + e, ye = y0;
+                while (xe >= p.gamma) {
+                    xe -= p.gamma;
+                    ye = step_mod(ye, p.xi);
                 }
+                ye += yy;
+                while (ye >= p.xi) ye -= p.xi;
+                off = (unsigned)(xe + p.gamma * ye) * 4u;
             }
-            pu.x[t] = bload(ur, off);
-            pe.x[t] = bload(er, off);
         }
-    } else {
-        int xm = xr + lane, y = y0;
-        while (xm >= p.gamma) {
-            xm -= p.gamma;
-            y = step_mod(y, p.xi);
-        }
-#pragma unroll
-        for (int yy = 0; yy < Wn::SY; ++yy) {
-            const unsigned off = (lane < xlim && yy < ylim) ? (unsigned)(xm + p.gamma * y) * 4u : kOutOfRange;
-            pu.v[yy] = bload(ur, off);
-            pe.v[yy] = bload(er, off);
-            y = step_mod(y, p.xi);
-        }
-#pragma unroll
-        for (int t = 0; t < Wn::NXT; ++t) {
-            const int k = lane + 64 * t;
-            unsigned off = kOutOfRange;
-            if (k < Wn::E * Wn::SY) {
-                const int e = k % Wn::ED, yy = k / Wn::ED;
-                if (TX + e < xlim && yy < ylim) {
-                    int xe = xr + TX + e, ye = y0;
-                    while (xe >= p.gamma) {
-                        xe -= p.gamma;
-                        ye = step_mod(ye, p.xi);
-                    }
-                    ye += yy;
-                    while (ye >= p.xi) ye -= p.xi;
-                    off = (unsigned)(xe + p.gamma * ye) * 4u;
-                }
-            }
-            pu.x[t] = bload(ur, off);
-            pe.x[t] = bload(er, off);
-        }
+        pu.x[t] = bload(ur, off);
+        pe.x[t] = bload(er, off);
     }
 }
 
@@ -796,8 +671,9 @@ __global__ void __launch_bounds__(64 * kVgWaves) k_value_grad(const int4 *__rest
     }
 }
 
-// Per calibration entry: its slot's partials over every unit of its
-// wavelength (all frames sharing the plan), minus (sum of b zeta) / h_s.
+// Per calibration entry (one wavefront each, lanes over the units): its
+// slot's partials over every unit of its wavelength (all frames sharing the
+// plan), minus (sum of b zeta) / h_s; sums in double, butterfly order fixed.
 __global__ void __launch_bounds__(256) k_value_finish(const int32_t *__restrict__ entry_slot,
                                                       const int32_t *__restrict__ box_lam,
                                                       const int32_t *__restrict__ lam_box0,
@@ -807,23 +683,26 @@ __global__ void __launch_bounds__(256) k_value_finish(const int32_t *__restrict_
                                                       const float *__restrict__ flux, const float *__restrict__ hsum,
                                                       float *__restrict__ dv, const long long entry0,
                                                       const long long n, const int accumulate) {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
+    const int lane = threadIdx.x & 63;
+    const long long t = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (t >= n) return;   // the whole wavefront leaves together
     const int slot = entry_slot[entry0 + t];
     float v = 0.0f;
     if (slot >= 0) {
         const int gb = slot / BB, k = slot - gb * BB;
         const int gl = box_lam[gb], j = gb - lam_box0[gl];
         double s = 0.0, fl = 0.0;
-        for (int p = lam_units_ptr[gl]; p < lam_units_ptr[gl + 1]; ++p) {
+        for (int p = lam_units_ptr[gl] + lane; p < lam_units_ptr[gl + 1]; p += 64) {
             const int un = lam_units[p];
             s += (double)part[((size_t)un * stride + j) * BB + k];
             fl += (double)flux[un];
         }
+        s = wave_sum(s);
+        fl = wave_sum(fl);
         const float hs = hsum[gl];
         v = (float)(s - (hs != 0.0f ? fl / (double)hs : 0.0));
     }
-    dv[t] = accumulate ? dv[t] + v : v;
+    if (lane == 0) dv[t] = accumulate ? dv[t] + v : v;
 }
 
 // New calibration values: one workgroup per wavelength [lam0 + blockIdx.x];
@@ -1002,7 +881,7 @@ int launch_value_grad(const DevWork &w, const float *u, const float *e, const fl
 int launch_value_finish(const DevWork &w, const float *part, const float *flux, float *dv, int64_t entry0,
                         int64_t n_entries, bool accumulate, void *stream) {
     if (n_entries <= 0) return 0;
-    const int64_t blocks = (n_entries + 255) / 256;
+    const int64_t blocks = (n_entries + 3) / 4;   // 4 entries (wavefronts) per workgroup
     hipLaunchKernelGGL(k_value_finish, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, w.entry_slot,
                        w.box_lam, w.lam_box0, w.lam_units_ptr, w.lam_units, w.adj.stride, w.B * w.B, part, flux,
                        (const float *)w.h, dv, (long long)entry0, (long long)n_entries, accumulate ? 1 : 0);

@@ -341,6 +341,19 @@ int32_t waves_for(int32_t work, int B) {
     return std::max(min_waves(), std::min(max_waves(B), (work + 1) / 2));
 }
 
+// Back projection: while its units fit on the chip at once (one workgroup
+// per compute unit of the MI355X's 256), the launch is latency-bound and
+// every box of a wavelength gets its own wavefront (all windows in flight
+// together); with more units than compute units the fewest waves per
+// workgroup keep the most units resident.  Both measured on the c2 and c3
+// shapes.
+constexpr int64_t kChipCUs = 256;
+
+int32_t adjoint_waves(int64_t units, int32_t boxes, int B) {
+    if (units > kChipCUs) return min_waves();
+    return std::max(min_waves(), std::min(max_waves(B), boxes));
+}
+
 void push4(std::vector<int32_t> &v, int32_t a, int32_t b, int32_t c, int32_t d) {
     v.push_back(a);
     v.push_back(b);
@@ -509,7 +522,7 @@ ctis_status build_work(const std::vector<FrameRef> &frames, bool with_full, Host
         }
     }
     A.n_units = (int32_t)(A.meta.size() / 12);
-    A.waves = waves_for(max_boxes, B);
+    A.waves = adjoint_waves(A.n_units, max_boxes, B);
 
     // value tables
     hw.box_lam.resize((size_t)box_base);
