@@ -354,6 +354,17 @@ int32_t adjoint_waves(int64_t units, int32_t boxes, int B) {
     return std::max(min_waves(), std::min(max_waves(B), boxes));
 }
 
+// Forward: in the latency-bound regime (units fit on the chip) one wave per
+// two boxes of the heaviest unit; with more units than compute units about
+// one wave per four boxes of the average unit (measured: a 1024^2 frame with
+// ~62 boxes per tile runs fastest with 16 waves, 64 uneven frames with ~16
+// boxes per tile with 4).
+int32_t forward_waves(int64_t units, int64_t items, int32_t max_items, int B) {
+    if (units <= kChipCUs) return waves_for(max_items, B);
+    const int64_t avg = units > 0 ? (items + units / 2) / units : 0;
+    return std::max(min_waves(), std::min<int32_t>(max_waves(B), (int32_t)((avg + 2) / 4)));
+}
+
 void push4(std::vector<int32_t> &v, int32_t a, int32_t b, int32_t c, int32_t d) {
     v.push_back(a);
     v.push_back(b);
@@ -364,6 +375,57 @@ void push4(std::vector<int32_t> &v, int32_t a, int32_t b, int32_t c, int32_t d) 
 struct UnitRef {
     int32_t frame, tile, chunk, n_chunks, slot, work;
 };
+
+// XCD-aware unit order for batches.  The MI355X deals workgroups to its 8
+// XCDs (each with its own L2) round-robin by workgroup index, so unit
+// position p runs on XCD p mod 8 (also under the persistent grid, whose size
+// is a multiple of 8).  Frames read only their own f, g and u, so each frame
+// is given one XCD -- greedily by work, largest frame first to the least
+// loaded XCD -- and position 8k + x takes the next unit of XCD x's frames (in
+// their incoming order); a position whose list has run out takes the last
+// unit of the fullest remaining list, trading that unit's locality for
+// balance.  With fewer frames than XCDs the order is left as it is.
+constexpr int kXcds = 8;
+
+template <class Unit, class FrameOf, class WorkOf>
+std::vector<Unit> xcd_order(const std::vector<Unit> &units, size_t n_frames, FrameOf frame_of, WorkOf work_of) {
+    if (n_frames < (size_t)kXcds) return units;
+    std::vector<int64_t> fwork(n_frames, 0);
+    for (const Unit &u : units) fwork[(size_t)frame_of(u)] += work_of(u);
+    std::vector<size_t> order(n_frames);
+    std::iota(order.begin(), order.end(), size_t(0));
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return fwork[x] > fwork[y]; });
+    std::vector<int64_t> load(kXcds, 0);
+    std::vector<int> frame_xcd(n_frames, 0);
+    for (size_t f : order) {
+        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        frame_xcd[f] = x;
+        load[(size_t)x] += fwork[f];
+    }
+    std::vector<std::vector<Unit>> bins(kXcds);
+    for (const Unit &u : units) bins[(size_t)frame_xcd[(size_t)frame_of(u)]].push_back(u);
+    std::vector<size_t> head(kXcds, 0), tail(kXcds);
+    for (int x = 0; x < kXcds; ++x) tail[(size_t)x] = bins[(size_t)x].size();
+    std::vector<Unit> out;
+    out.reserve(units.size());
+    while (out.size() < units.size()) {
+        for (int x = 0; x < kXcds && out.size() < units.size(); ++x) {
+            if (head[(size_t)x] < tail[(size_t)x]) {
+                out.push_back(bins[(size_t)x][head[(size_t)x]++]);
+                continue;
+            }
+            size_t best = 0;
+            int src = -1;
+            for (int y = 0; y < kXcds; ++y)
+                if (tail[(size_t)y] - head[(size_t)y] > best) {
+                    best = tail[(size_t)y] - head[(size_t)y];
+                    src = y;
+                }
+            out.push_back(bins[(size_t)src][--tail[(size_t)src]]);
+        }
+    }
+    return out;
+}
 
 }  // namespace
 
@@ -438,6 +500,8 @@ ctis_status build_work(const std::vector<FrameRef> &frames, bool with_full, Host
             }
         }
         std::stable_sort(units.begin(), units.end(), [](const UnitRef &x, const UnitRef &y) { return x.work > y.work; });
+        units = xcd_order(units, frames.size(), [](const UnitRef &u) { return u.frame; },
+                          [](const UnitRef &u) { return (int64_t)u.work; });
         L.stride = std::max(1, stride);
         L.meta.clear();
         L.items.clear();
@@ -469,6 +533,11 @@ ctis_status build_work(const std::vector<FrameRef> &frames, bool with_full, Host
     };
     int32_t chunk = 1 << 30;
     for (const FrameRef &fr : frames) chunk = std::min(chunk, fr.plan->ht.chunk);
+    auto count_items = [](const HostList &L) {
+        int64_t n = 0;
+        for (size_t k = 3; k < L.items.size(); k += 4) n += L.items[k] >= 0;
+        return n;
+    };
     ctis_status st = CTIS_OK;
     if (with_full) {
         const int32_t saved_slots = hw.partial_slots, saved_split = hw.n_split;
@@ -476,11 +545,11 @@ ctis_status build_work(const std::vector<FrameRef> &frames, bool with_full, Host
         if (st != CTIS_OK) return st;
         hw.partial_slots = saved_slots;
         hw.n_split = saved_split;
-        hw.fwd_full.waves = waves_for(max_full_items, B);
+        hw.fwd_full.waves = forward_waves(hw.fwd_full.n_units, count_items(hw.fwd_full), max_full_items, B);
     }
     st = build_fwd(hw.fwd_em, true, chunk);
     if (st != CTIS_OK) return st;
-    hw.fwd_em.waves = waves_for(max_chunk_items, B);
+    hw.fwd_em.waves = forward_waves(hw.fwd_em.n_units, count_items(hw.fwd_em), max_chunk_items, B);
 
     // adjoint: units (frame, wavelength, field-stop tile); records per global wavelength
     HostList &A = hw.adj;
@@ -504,22 +573,33 @@ ctis_status build_work(const std::vector<FrameRef> &frames, bool with_full, Host
             }
         }
     }
-    std::vector<std::vector<int32_t>> units_of(lambda_base);
+    struct AdjRef {
+        int32_t frame, s, vt, work;
+    };
+    std::vector<AdjRef> adj_units;
     for (size_t k = 0; k < frames.size(); ++k) {
         const ctis_plan *pl = frames[k].plan;
         const HostTables &T = pl->ht;
         for (int32_t s = 0; s < pl->w; ++s) {
-            const int32_t gs = flam[k] + s;
-            for (int32_t vt = 0; vt < T.nbx * T.nby; ++vt) {
-                units_of[(size_t)gs].push_back((int32_t)(A.meta.size() / 12));
-                push4(A.meta, (vt % T.nbx) * kTileFast, (vt / T.nbx) * kTileSlow, gs,
-                      (int32_t)(frames[k].f_base + (int64_t)s * pl->ell));
-                push4(A.meta, pl->a, pl->alpha, pl->gamma, pl->xi);
-                push4(A.meta, (int32_t)frames[k].u_base, 0, 0, 0);
-                if (A.meta.size() / 12 > (size_t)INT32_MAX / ((size_t)A.stride * BB))
-                    return fail(CTIS_E_TOO_LARGE, "too many back-projection units");
-            }
+            const int32_t nb = T.lambda_box_ptr[(size_t)s + 1] - T.lambda_box_ptr[(size_t)s];
+            for (int32_t vt = 0; vt < T.nbx * T.nby; ++vt) adj_units.push_back(AdjRef{(int32_t)k, s, vt, nb});
         }
+    }
+    if (adj_units.size() > (size_t)INT32_MAX / ((size_t)A.stride * BB))
+        return fail(CTIS_E_TOO_LARGE, "too many back-projection units");
+    adj_units = xcd_order(adj_units, frames.size(), [](const AdjRef &u) { return u.frame; },
+                          [](const AdjRef &u) { return (int64_t)u.work; });
+    std::vector<std::vector<int32_t>> units_of(lambda_base);
+    for (const AdjRef &au : adj_units) {
+        const FrameRef &fr = frames[(size_t)au.frame];
+        const ctis_plan *pl = fr.plan;
+        const HostTables &T = pl->ht;
+        const int32_t gs = flam[(size_t)au.frame] + au.s;
+        units_of[(size_t)gs].push_back((int32_t)(A.meta.size() / 12));
+        push4(A.meta, (au.vt % T.nbx) * kTileFast, (au.vt / T.nbx) * kTileSlow, gs,
+              (int32_t)(fr.f_base + (int64_t)au.s * pl->ell));
+        push4(A.meta, pl->a, pl->alpha, pl->gamma, pl->xi);
+        push4(A.meta, (int32_t)fr.u_base, 0, 0, 0);
     }
     A.n_units = (int32_t)(A.meta.size() / 12);
     A.waves = adjoint_waves(A.n_units, max_boxes, B);
