@@ -351,17 +351,23 @@ class Plan:
         _check(self._L, st, "ctis_em_adjoint_update")
         return f_out
 
-    def em(self, g, iters: int, f0=None, f=None, workspace=None):
-        """EM iterations.  Returns f after ``iters`` updates of f0 (default ones).
-        If ``f`` is given it is updated in place (and returned)."""
+    def em(self, g, iters: int, f0=None, f=None, workspace=None, start: str = "ones"):
+        """EM iterations.  Returns f after ``iters`` updates of f0.  Without f0
+        the start is all ones (``start="ones"``) or H^T g (``start="adjoint"``;
+        Sec. 2 names both).  If ``f`` is given it is updated in place (and
+        returned) and ``f0``/``start`` are ignored."""
         self._need_device()
         torch = _torch()
         g = self._dev_tensor(g, self.info.n, "g")
+        if start not in ("ones", "adjoint"):
+            raise ValueError("start must be 'ones' or 'adjoint'")
         if f is None:
-            if f0 is None:
-                f = torch.ones(self.shape_f, dtype=torch.float32, device=self.device)
-            else:
+            if f0 is not None:
                 f = self._dev_tensor(f0, self.info.m, "f0").clone()
+            elif start == "adjoint":
+                f = self.adjoint(g)
+            else:
+                f = torch.ones(self.shape_f, dtype=torch.float32, device=self.device)
         elif not (f.is_contiguous() and f.dtype == torch.float32 and f.device == self.device):
             raise ValueError("f must be a contiguous float32 tensor on the plan's device")
         if workspace is None:
@@ -489,11 +495,17 @@ class Batch:
         _check(self._L, st, "ctis_batch_adjoint")
         return out
 
-    def em(self, g_all, iters: int, f_all=None, workspace=None):
-        """EM of every frame in place on f_all (default: a new all-ones f_all)."""
+    def em(self, g_all, iters: int, f_all=None, workspace=None, start: str = "ones"):
+        """EM of every frame in place on f_all (default: a new f_all, all ones
+        or, with ``start="adjoint"``, H^T g of each frame)."""
         torch = _torch()
+        if start not in ("ones", "adjoint"):
+            raise ValueError("start must be 'ones' or 'adjoint'")
         if f_all is None:
-            f_all = torch.ones(int(self.f_offsets[-1]), dtype=torch.float32, device=self.device)
+            if start == "adjoint":
+                f_all = self.adjoint(g_all)
+            else:
+                f_all = torch.ones(int(self.f_offsets[-1]), dtype=torch.float32, device=self.device)
         if workspace is None:
             workspace = self.workspace()
         st = self._L.ctis_batch_em_iterate(self._handle, ctypes.c_void_p(g_all.data_ptr()),

@@ -157,6 +157,21 @@ def test_c1_em_parity_and_invariants(torch, c1):
     np.testing.assert_allclose(flux, g.astype(np.float64).sum(), rtol=1e-5)
 
 
+def test_em_from_the_adjoint_start(torch, ctis, c1):
+    """The other start Sec. 2 names, f^(1) = H^T g: GPU EM from it against the
+    oracle's EM from its own H^T g, for a plan and for a batch."""
+    case, o, p, g = c1
+    K = 10
+    ref = o.em(g, K, f0=o.adjoint(g))
+    gd = torch.from_numpy(g).cuda()
+    e = rel_l2(p.em(gd, K, start="adjoint").cpu().numpy(), ref)
+    log(f"c1 EM from H^T g: rel-L2 {e:.2e}")
+    assert e <= EM_TOL
+    b = ctis.Batch([p, p])
+    fb = b.em(torch.cat([gd.reshape(-1), gd.reshape(-1)]), K, start="adjoint").cpu().numpy()
+    assert rel_l2(fb[: case.geometry.m], ref) <= EM_TOL and rel_l2(fb[case.geometry.m:], ref) <= EM_TOL
+
+
 def test_adjoint_identity_gpu(torch, c1):
     case, o, p, _ = c1
     rng = np.random.default_rng(9)
