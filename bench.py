@@ -91,6 +91,9 @@ def main(argv=None) -> int:
     ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5],
                     help="1-3: one frame; 4: 64 uneven frames, batched vs sequential; "
                          "5: gradients of 10 unrolled EM iterations, 8 frames sharing one plan")
+    ap.add_argument("--path", choices=["gather", "fourier"], default="gather",
+                    help="gather: projections as gathers over the calibration nonzeros; fourier: the paper's "
+                         "FFT form (configs 1-3)")
     ap.add_argument("--launch", choices=["graph", "stream"], default="graph",
                     help="graph: each step is one replay of a HIP graph holding the whole solve; "
                          "stream: the solve's kernels are launched one by one on the stream")
@@ -130,6 +133,8 @@ def main(argv=None) -> int:
         return bench_batched(args, torch, ctis, W, dev)
     if args.config == 5:
         return bench_differentiable(args, torch, ctis, W, dev)
+    if args.path == "fourier":
+        return bench_fourier(args, torch, ctis, W, dev)
     case = W.make_case(args.config)
     cfg = case.cfg
     geo = case.geometry
@@ -379,6 +384,101 @@ def bench_batched(args, torch, ctis, W, dev) -> int:
                      "kernel": "forward_ratio + adjoint_update (one EM iteration of all frames)",
                      "algorithmic_bytes_per_iteration": bytes_it,
                      "algorithmic_flop_per_iteration": 2 * flops},
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def _graph_of(torch, fn):
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        fn()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    gr = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gr):
+        fn()
+    return gr
+
+
+def bench_fourier(args, torch, ctis, W, dev) -> int:
+    """The same single-frame EM solve through the Fourier (WBH) projections:
+    per iteration w/2 + 1 forward and w/2 + 1 inverse complex FFTs of length
+    n (two FFT passes each), with the gather path's rate beside it."""
+    case = W.make_case(args.config)
+    cfg, geo, K = case.cfg, case.geometry, case.cfg.iters
+    progress(f"fourier {cfg.name}: plan and spectra")
+    plan = ctis.Plan.from_case(case)
+    F = ctis.Fourier(plan)
+    clean = plan.forward(torch.from_numpy(case.f_true.astype(np.float32)).to(dev)).double().cpu().numpy()
+    g = torch.from_numpy(case.noisy(clean)).to(dev)
+    f = torch.empty(plan.shape_f, dtype=torch.float32, device=dev)
+    ws = F.workspace()
+    wsg = plan.workspace()
+
+    def solve():
+        f.fill_(1.0)
+        F.em(g, K, f=f, workspace=ws)
+
+    def solve_gather():
+        f.fill_(1.0)
+        plan.em(g, K, f=f, workspace=wsg)
+
+    gr = _graph_of(torch, solve)
+    for _ in range(args.warmup):
+        gr.replay()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        gr.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    it_s = args.steps * K / (ms / 1e3)
+    if not torch.isfinite(f).all():
+        print("bench.py: Fourier EM produced a non-finite value", file=sys.stderr)
+        return 1
+    grg = _graph_of(torch, solve_gather)
+    grg.replay()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        grg.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    gather_it_s = args.steps * K / (e0.elapsed_time(e1) / 1e3)
+    P, N, m = F.info["pairs"], geo.n, geo.m
+    # algorithmic bytes of one Fourier EM iteration (FFT passes read and write n
+    # complex values; the fused loads and stores add f, g, u and the spectra):
+    # 12 m + 72 P n + 52 n
+    bytes_it = 12 * m + 72 * P * N + 52 * N
+    it_us = ms * 1e3 / (args.steps * K)
+    achieved = bytes_it / (it_us * 1e-6) / 1e9
+    line = {
+        "metric": METRIC,
+        "value": it_s,
+        "unit": "EM iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": cfg.name + " (Fourier projections)", "n": N, "fft": f"{F.info['n1']}x{F.info['n2']}",
+                   "pairs": P, "em_iters_per_step": K},
+        "voxel_updates_per_s": it_s * m,
+        "gather_path_em_iters_per_s": gather_it_s,
+        "fourier_vs_gather": it_s / gather_it_s,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "one Fourier EM iteration (8 FFT pass launches)", "avg_iteration_us": it_us,
+                     "algorithmic_bytes_per_iteration": bytes_it},
     }
     print(json.dumps(line), flush=True)
     return 0

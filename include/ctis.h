@@ -342,6 +342,48 @@ ctis_status ctis_batch_set_values(ctis_batch *batch, int32_t frame, const float 
  * [*offset, *offset + *count). */
 ctis_status ctis_batch_plan_entries(const ctis_batch *batch, int32_t frame, int64_t *offset, int64_t *count);
 
+/*
+ * The Fourier (WBH) form of the projections, for calibrations dense enough
+ * that the FFT beats the gather over nonzeros (Sec. 3: the circulant blocks
+ * C_s are diagonalised by the length-n DFT over the vectorised FPA, eqs.
+ * (forward) and (backwards); Sec. 3 algorithm for the stage order of EM).
+ * Needs n = gamma*xi a power of two in 2^4..2^20.  Two wavelengths share one
+ * complex length-n FFT; each EM iteration is w/2 + 1 forward and w/2 + 1
+ * inverse complex FFTs (the work of 2w + 2 real FFTs).  Results equal those
+ * of the gather path up to FFT rounding.
+ *
+ * ctis_fourier_create computes the spectra e_t = F(c_{2t} - i c_{2t+1}) of the
+ * plan's calibration on the current device (it synchronises the device before
+ * returning) and keeps a pointer to the plan, which must outlive it.  The
+ * spectra take info.spectra_bytes of device memory; the calls take a
+ * workspace of info.workspace_bytes (256-byte aligned).  Layouts of f, g, r, z
+ * as for the gather path.  Errors: CTIS_E_ARG (n not a power of two in range,
+ * host-only plan, other device), CTIS_E_NOMEM, CTIS_E_HIP, CTIS_E_WORKSPACE,
+ * CTIS_E_NEGATIVE (EM with a negative value).
+ */
+typedef struct ctis_fourier ctis_fourier;
+
+typedef struct {
+    int64_t n;                 /* FFT length (gamma*xi)                          */
+    int32_t n1, n2;            /* four-step factors, n = n1*n2                   */
+    int32_t pairs;             /* wavelength pairs, ceil(w/2)                    */
+    size_t spectra_bytes;      /* device memory held by the Fourier plan        */
+    size_t workspace_bytes;    /* workspace of the projection and EM calls      */
+} ctis_fourier_info;
+
+ctis_status ctis_fourier_create(ctis_fourier **out, const ctis_plan *plan);
+void ctis_fourier_destroy(ctis_fourier *fourier);
+ctis_status ctis_fourier_get_info(const ctis_fourier *fourier, ctis_fourier_info *info);
+/* g_out = H f (DEVICE, n floats). */
+ctis_status ctis_fourier_forward(const ctis_fourier *fourier, const float *f, float *g_out, void *workspace,
+                                 size_t workspace_bytes, void *stream);
+/* z_out = H^T r (DEVICE, m floats). */
+ctis_status ctis_fourier_adjoint(const ctis_fourier *fourier, const float *r, float *z_out, void *workspace,
+                                 size_t workspace_bytes, void *stream);
+/* iters EM iterations in place on f (same rules as ctis_em_iterate). */
+ctis_status ctis_fourier_em_iterate(const ctis_fourier *fourier, const float *g, float *f, int32_t iters,
+                                    void *workspace, size_t workspace_bytes, void *stream);
+
 /* Static description of a status code. */
 const char *ctis_status_str(ctis_status status);
 

@@ -1,0 +1,60 @@
+// Internal types of the Fourier (WBH) path: the pass descriptor shared by the
+// FFT kernel (fourier.hip) and the C ABI glue (fourier.cpp).
+#pragma once
+
+#include "ctis_internal.h"
+
+namespace ctis {
+namespace fourier {
+
+// Load modes (pass A reads element i of the batch's sequence, i = N2 n1 + n2
+// in natural order):
+enum Load : int {
+    kLoadComplex = 0,   // in[batch n + i]
+    kLoadEmbedPair = 1, // (fE_{2t}(i), fE_{2t+1}(i)): E f of the pair's wavelengths
+    kLoadCalPair = 2,   // (c_{2t}[i], -c_{2t+1}[i]) from a dense w x n calibration
+    kLoadReal = 3,      // (u[i], 0)
+    kLoadCombine = 4,   // sum_t e_t[i] X_t[i]
+    kLoadConjE = 5,     // conj(e_t[i]) U[i]
+};
+// Store modes (pass B writes element k of the batch's sequence in natural order):
+enum Store : int {
+    kStoreComplex = 0,  // out[batch n + k]
+    kStoreReal = 1,     // ghat[k] = Re / n
+    kStoreRatio = 2,    // u[k] = g[k] / ghat[k], 0 where ghat <= 0
+    kStoreCrop = 3,     // z_s(x, y) = (Re, Im) / n for the pair's wavelengths
+    kStoreUpdate = 4,   // f_s(x, y) = f_s zeta_s / h_s, 0 where h_s = 0
+};
+
+struct Geo {
+    int a, alpha, gamma, xi, w;
+    long long ell;
+};
+
+struct Pass {
+    const float2 *in;          // complex input (modes complex, combine: X; conj-e: U)
+    float2 *out;               // complex output (pass A, complex store)
+    const float *fin;          // real input (embed: f; real: u; cal: c)
+    float *fout;               // real output (real, ratio: ghat / u; crop: z; update: f)
+    const float *g;            // ratio: the measured frame
+    const float2 *e;           // spectra e_t (combine, conj-e)
+    const float *h;            // column sums per wavelength (update)
+    const float2 *tw_stage;    // exp(-2 pi i j / L), j < L / 2
+    const float2 *tw_hi;       // exp(-2 pi i a / N1), a < N1   (pass A only)
+    const float2 *tw_lo;       // exp(-2 pi i b / N),  b < N2   (pass A only)
+    long long n;
+    int L, log_l, S;           // transform length, log2, sequences per workgroup
+    int n_seq;                 // sequences per batch (N2 for pass A, N1 for pass B)
+    int pass_a;                // 1: pass A (strided columns, twiddle, Y layout); 0: pass B
+    int N1, N2, log_n2;
+    int inverse;
+    int load, store;
+    int pairs;                 // number of wavelength pairs (combine sums over them)
+    Geo geo;
+};
+
+int seqs_per_group(int L, int n_seq);
+int launch_pass(const Pass &P, int batches, void *stream);
+
+}  // namespace fourier
+}  // namespace ctis

@@ -31,7 +31,8 @@ EXPORTED = ["ctis_plan_create", "ctis_plan_destroy", "ctis_plan_get_info",
             "ctis_last_error", "ctis_version", "ctis_batch_create", "ctis_batch_destroy",
             "ctis_batch_get_info", "ctis_batch_forward", "ctis_batch_adjoint", "ctis_batch_em_iterate",
             "ctis_em_vjp", "ctis_plan_set_values", "ctis_batch_em_vjp", "ctis_batch_set_values",
-            "ctis_batch_plan_entries"]
+            "ctis_batch_plan_entries", "ctis_fourier_create", "ctis_fourier_destroy", "ctis_fourier_get_info",
+            "ctis_fourier_forward", "ctis_fourier_adjoint", "ctis_fourier_em_iterate"]
 
 
 def CTIS_PLAN_BOX(b: int) -> int:
@@ -67,6 +68,12 @@ class _BatchInfo(ctypes.Structure):
                 ("waves_forward", ctypes.c_int32), ("waves_adjoint", ctypes.c_int32),
                 ("workspace_bytes", ctypes.c_size_t), ("n_plans", ctypes.c_int32),
                 ("n_entries", ctypes.c_int64), ("vjp_workspace_bytes", ctypes.c_size_t)]
+
+
+class _FourierInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("n1", ctypes.c_int32), ("n2", ctypes.c_int32),
+                ("pairs", ctypes.c_int32), ("spectra_bytes", ctypes.c_size_t),
+                ("workspace_bytes", ctypes.c_size_t)]
 
 
 @dataclasses.dataclass(frozen=True)
@@ -159,6 +166,17 @@ def load_library(path: str | None = None):
         L.ctis_batch_set_values.restype = st
         L.ctis_batch_plan_entries.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i64)]
         L.ctis_batch_plan_entries.restype = st
+        L.ctis_fourier_create.argtypes = [ctypes.POINTER(vp), vp]
+        L.ctis_fourier_create.restype = st
+        L.ctis_fourier_destroy.argtypes = [vp]
+        L.ctis_fourier_destroy.restype = None
+        L.ctis_fourier_get_info.argtypes = [vp, ctypes.POINTER(_FourierInfo)]
+        L.ctis_fourier_get_info.restype = st
+        for fn in (L.ctis_fourier_forward, L.ctis_fourier_adjoint):
+            fn.argtypes = [vp, vp, vp, vp, sz, vp]
+            fn.restype = st
+        L.ctis_fourier_em_iterate.argtypes = [vp, vp, vp, i32, vp, sz, vp]
+        L.ctis_fourier_em_iterate.restype = st
         L.ctis_status_str.argtypes = [st]
         L.ctis_status_str.restype = ctypes.c_char_p
         L.ctis_last_error.argtypes = []
@@ -558,3 +576,75 @@ class Batch:
                                        workspace.numel() * workspace.element_size(), _stream(torch, self.device))
         _check(self._L, st, "ctis_batch_em_vjp")
         return df_all
+
+
+class Fourier:
+    """The Fourier (WBH) projections of a plan: spectra of its calibration
+    and FFT-based forward, adjoint and EM (see include/ctis.h).  The plan must
+    outlive this object."""
+
+    def __init__(self, plan: Plan):
+        self._L = load_library()
+        self._handle = None
+        plan._need_device()
+        self.plan = plan
+        self.device = plan.device
+        h = ctypes.c_void_p()
+        _check(self._L, self._L.ctis_fourier_create(ctypes.byref(h), plan._handle), "ctis_fourier_create")
+        self._handle = h
+        inf = _FourierInfo()
+        _check(self._L, self._L.ctis_fourier_get_info(self._handle, ctypes.byref(inf)), "ctis_fourier_get_info")
+        self.info = {k: getattr(inf, k) for k, _ in _FourierInfo._fields_}
+
+    def close(self):
+        if self._handle:
+            _torch().cuda.synchronize(self.device)
+            self._L.ctis_fourier_destroy(self._handle)
+            self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace(self):
+        torch = _torch()
+        return torch.empty(max(self.info["workspace_bytes"] // 4, 64), dtype=torch.float32, device=self.device)
+
+    def forward(self, f, out=None, workspace=None):
+        torch = _torch()
+        f = self.plan._dev_tensor(f, self.plan.info.m, "f")
+        if out is None:
+            out = torch.empty(self.plan.shape_g, dtype=torch.float32, device=self.device)
+        ws = self.workspace() if workspace is None else workspace
+        st = self._L.ctis_fourier_forward(self._handle, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                          ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
+                                          _stream(torch, self.device))
+        _check(self._L, st, "ctis_fourier_forward")
+        return out
+
+    def adjoint(self, r, out=None, workspace=None):
+        torch = _torch()
+        r = self.plan._dev_tensor(r, self.plan.info.n, "r")
+        if out is None:
+            out = torch.empty(self.plan.shape_f, dtype=torch.float32, device=self.device)
+        ws = self.workspace() if workspace is None else workspace
+        st = self._L.ctis_fourier_adjoint(self._handle, ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                          ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
+                                          _stream(torch, self.device))
+        _check(self._L, st, "ctis_fourier_adjoint")
+        return out
+
+    def em(self, g, iters: int, f0=None, f=None, workspace=None):
+        torch = _torch()
+        g = self.plan._dev_tensor(g, self.plan.info.n, "g")
+        if f is None:
+            f = (torch.ones(self.plan.shape_f, dtype=torch.float32, device=self.device) if f0 is None
+                 else self.plan._dev_tensor(f0, self.plan.info.m, "f0").clone())
+        ws = self.workspace() if workspace is None else workspace
+        st = self._L.ctis_fourier_em_iterate(self._handle, ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(f.data_ptr()),
+                                             int(iters), ctypes.c_void_p(ws.data_ptr()),
+                                             ws.numel() * ws.element_size(), _stream(torch, self.device))
+        _check(self._L, st, "ctis_fourier_em_iterate")
+        return f
