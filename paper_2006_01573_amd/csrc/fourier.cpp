@@ -51,14 +51,12 @@ ctis_status run_fft(const ctis_fourier *F, Pass a, Pass b, int batches_a, int ba
     a.N2 = b.N2 = F->N2;
     a.log_n2 = b.log_n2 = F->log_n2;
     a.geo = b.geo = F->geo;
-    a.pairs = b.pairs = F->pairs;
     a.e = b.e = F->e;
     a.h = b.h = F->h;
     a.pass_a = 1;
     a.L = F->N1;
     a.log_l = F->log_n1;
     a.n_seq = F->N2;
-    a.S = seqs_per_group(a.L, a.n_seq);
     a.tw_stage = F->tw1;
     a.tw_hi = F->tw_hi;
     a.tw_lo = F->tw_lo;
@@ -66,7 +64,6 @@ ctis_status run_fft(const ctis_fourier *F, Pass a, Pass b, int batches_a, int ba
     b.L = F->N2;
     b.log_l = F->log_n2;
     b.n_seq = F->N1;
-    b.S = seqs_per_group(b.L, b.n_seq);
     b.tw_stage = F->tw2;
     b.load = kLoadComplex;
     ctis_status st = launched(launch_pass(a, batches_a, stream), "fft pass A");
@@ -87,17 +84,19 @@ ctis_status forward(const ctis_fourier *F, const float *f, const float *g, float
     b.store = kStoreComplex;
     ctis_status st = run_fft(F, a, b, F->pairs, F->pairs, stream);   // X_t = F(v_{2t} + i v_{2t+1})
     if (st != CTIS_OK) return st;
+    st = launched(launch_combine(F->e, B, A, F->pairs, F->n, stream), "spectral products");   // sum_t e_t X_t
+    if (st != CTIS_OK) return st;
     Pass c{}, d{};
-    c.in = B;
-    c.load = kLoadCombine;
-    c.out = A;
+    c.in = A;
+    c.load = kLoadComplex;
+    c.out = B;
     c.inverse = 1;
-    d.in = A;
+    d.in = B;
     d.inverse = 1;
     d.store = store;
     d.fout = out;
     d.g = g;
-    return run_fft(F, c, d, 1, 1, stream);                           // F^-1 sum_t e_t X_t
+    return run_fft(F, c, d, 1, 1, stream);                           // F^-1 of the sum
 }
 
 // z = H^T r (kStoreCrop into out) or f = f . H^T u / h (kStoreUpdate on out)
@@ -167,7 +166,7 @@ ctis_status ctis_fourier_create(ctis_fourier **out, const ctis_plan *p) {
     F->N1 = 1 << F->log_n1;
     F->N2 = 1 << F->log_n2;
     F->pairs = (p->w + 1) / 2;
-    F->geo = Geo{p->a, p->alpha, p->gamma, p->xi, p->w, (long long)p->ell};
+    F->geo = Geo{p->a, p->alpha, p->gamma, p->xi, p->w, (long long)p->ell, log2_exact(p->gamma)};
     F->device = dev;
     F->nonneg = p->ht.nonneg;
     const int64_t n = p->n;

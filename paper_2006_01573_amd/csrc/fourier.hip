@@ -15,14 +15,18 @@
 // strided sequences x[N2 n1 + n2], each output multiplied by w_N^(n2 k1),
 // written to Y[n2 + N2 k1]; pass B: N1 transforms of length N2 over the rows
 // of Y, written in natural order X[k1 + N1 k2].  A workgroup holds S
-// sequences (S L <= 8192 complex values, 64 KB of LDS) laid out [element][seq],
-// loads them so that consecutive lanes touch consecutive addresses, applies
-// log2 L radix-2 stages in place after a bit-reversed load, and stores the
-// same way.  Loads and stores carry the pipeline's own steps (embedding E f,
-// the spectral products, the ratio g / ghat, the crop E^T and the EM update)
-// so that no separate elementwise pass touches HBM.  Twiddles come from
-// tables computed in double on the host.
+// sequences (S L = 4096 complex values when many transforms run together, 4
+// sequences for a single transform) laid out [element][seq], loads them so
+// that consecutive lanes touch consecutive addresses, applies log2 L radix-2
+// stages in place after a bit-reversed load with the stage twiddles staged
+// in LDS, and stores the same way.  Loads and stores carry the pipeline's own
+// steps (embedding E f, the products conj(e_t) U, the ratio g / ghat, the
+// crop E^T and the EM update); the sum over pairs of the forward's spectral
+// products is one elementwise kernel.  Twiddles come from tables computed in
+// double on the host.
 #include <hip/hip_runtime.h>
+
+#include <mutex>
 
 #include "fourier_internal.h"
 
@@ -53,7 +57,7 @@ __device__ __forceinline__ C2 load_elem(const Pass &P, int bt, long long i) {
                 const float b = s1 < P.geo.w ? P.fin[(long long)s1 * P.n + i] : 0.0f;
                 return {a, -b};
             }
-            const int r = (int)(i % P.geo.gamma), c = (int)(i / P.geo.gamma);
+            const int r = (int)(i & (P.geo.gamma - 1)), c = (int)(i >> P.geo.log_gamma);
             if (r >= P.geo.a || c >= P.geo.alpha) return {0.0f, 0.0f};
             const long long j = r + (long long)P.geo.a * c;
             const float a = P.fin[(long long)s0 * P.geo.ell + j];
@@ -62,16 +66,6 @@ __device__ __forceinline__ C2 load_elem(const Pass &P, int bt, long long i) {
         }
         case kLoadReal:
             return {P.fin[i], 0.0f};
-        case kLoadCombine: {
-            C2 acc = {0.0f, 0.0f};
-            for (int t = 0; t < P.pairs; ++t) {
-                const float2 ev = P.e[(long long)t * P.n + i], xv = P.in[(long long)t * P.n + i];
-                const C2 p = cmul({ev.x, ev.y}, {xv.x, xv.y});
-                acc.x += p.x;
-                acc.y += p.y;
-            }
-            return acc;
-        }
         case kLoadConjE: {
             const float2 ev = P.e[(long long)bt * P.n + i], uv = P.in[i];
             return cmulc({ev.x, ev.y}, {uv.x, uv.y});
@@ -96,7 +90,7 @@ __device__ __forceinline__ void store_elem(const Pass &P, int bt, long long k, C
         }
         case kStoreCrop:
         case kStoreUpdate: {
-            const int r = (int)(k % P.geo.gamma), c = (int)(k / P.geo.gamma);
+            const int r = (int)(k & (P.geo.gamma - 1)), c = (int)(k >> P.geo.log_gamma);
             if (r >= P.geo.a || c >= P.geo.alpha) return;
             const long long j = r + (long long)P.geo.a * c;
             const int s0 = 2 * bt, s1 = 2 * bt + 1;
@@ -121,16 +115,26 @@ __device__ __forceinline__ void store_elem(const Pass &P, int bt, long long k, C
     }
 }
 
+// One pass over S sequences of length L = 2^LOGL.  LDS: the S L values
+// [element][sequence], then the L/2 stage twiddles.
+template <int LOGL, int S>
 __global__ void __launch_bounds__(256) k_fft_pass(const Pass P) {
-    extern __shared__ float2 buf[];   // [element][sequence], S L values
-    const int S = P.S, L = P.L;
+    constexpr int L = 1 << LOGL;
+    constexpr int TOTAL = S * L;
+    extern __shared__ float2 lds[];
+    float2 *buf = lds;
+    float2 *twl = lds + TOTAL;
     const int bt = blockIdx.y;
     const int seq0 = blockIdx.x * S;
-    const int total = S * L;
+    for (int j = threadIdx.x; j < L / 2; j += 256) {
+        const float2 t = P.tw_stage[j];
+        twl[j] = make_float2(t.x, P.inverse ? -t.y : t.y);
+    }
     // pass A: sequence = column n2 (addresses N2 n1 + n2: consecutive seqs
     // are consecutive); pass B: sequence = row k1 (addresses N2 k1 + n2:
     // consecutive elements are consecutive)
-    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+#pragma unroll 4
+    for (int idx = threadIdx.x; idx < TOTAL; idx += 256) {
         int s, j;
         if (P.pass_a) {
             s = idx % S;
@@ -149,19 +153,22 @@ __global__ void __launch_bounds__(256) k_fft_pass(const Pass P) {
                 v = {t.x, t.y};
             }
         }
-        const int jr = (int)(__builtin_bitreverse32((unsigned)j) >> (32 - P.log_l));
+        const int jr = (int)(__builtin_bitreverse32((unsigned)j) >> (32 - LOGL));
         buf[jr * S + s] = make_float2(v.x, v.y);
     }
     __syncthreads();
-    for (int half = 1; half < L; half <<= 1) {
+#pragma unroll
+    for (int lh = 0; lh < LOGL; ++lh) {
+        const int half = 1 << lh;
         const int step = L / (2 * half);
-        for (int b = threadIdx.x; b < (L / 2) * S; b += blockDim.x) {
+#pragma unroll 4
+        for (int b = threadIdx.x; b < (L / 2) * S; b += 256) {
             const int s = b % S, p = b / S;
             const int m = p & (half - 1);
             const int i0 = (p - m) * 2 + m, i1 = i0 + half;
-            const C2 w = tw(P.tw_stage, m * step, P.inverse);
+            const float2 wt = twl[m * step];
             const float2 a = buf[i0 * S + s], c = buf[i1 * S + s];
-            const C2 cw = cmul({c.x, c.y}, w);
+            const C2 cw = cmul({c.x, c.y}, {wt.x, wt.y});
             buf[i0 * S + s] = make_float2(a.x + cw.x, a.y + cw.y);
             buf[i1 * S + s] = make_float2(a.x - cw.x, a.y - cw.y);
         }
@@ -169,7 +176,8 @@ __global__ void __launch_bounds__(256) k_fft_pass(const Pass P) {
     }
     // pass A: Y[n2 + N2 k1] = X1[k1] w_N^(n2 k1) (consecutive seqs consecutive);
     // pass B: X[k1 + N1 k2] (consecutive seqs = rows k1 consecutive)
-    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+#pragma unroll 4
+    for (int idx = threadIdx.x; idx < TOTAL; idx += 256) {
         const int s = idx % S, k = idx / S;
         const int sq = seq0 + s;
         if (sq >= P.n_seq) continue;
@@ -187,19 +195,71 @@ __global__ void __launch_bounds__(256) k_fft_pass(const Pass P) {
     }
 }
 
-}  // namespace
-
-int seqs_per_group(int L, int n_seq) {
-    int S = 8192 / L;
-    if (S > 16) S = 16;
-    if (S > n_seq) S = n_seq;
-    return S < 1 ? 1 : S;
+// G[k] = sum_t e_t[k] X_t[k]: the spectral products of the forward
+// projection, summed over the wavelength pairs (fixed order).
+__global__ void __launch_bounds__(256) k_combine(const float2 *__restrict__ e, const float2 *__restrict__ X,
+                                                 float2 *__restrict__ G, int pairs, long long n) {
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    C2 acc = {0.0f, 0.0f};
+    for (int t = 0; t < pairs; ++t) {
+        const float2 ev = e[(long long)t * n + k], xv = X[(long long)t * n + k];
+        const C2 p = cmul({ev.x, ev.y}, {xv.x, xv.y});
+        acc.x += p.x;
+        acc.y += p.y;
+    }
+    G[k] = make_float2(acc.x, acc.y);
 }
 
+template <int LOGL, int S>
+int launch_ls(const Pass &P, int batches, hipStream_t st) {
+    constexpr int L = 1 << LOGL;
+    const size_t lds = ((size_t)S * L + L / 2) * sizeof(float2);
+    static std::once_flag once;
+    static hipError_t attr = hipSuccess;
+    std::call_once(once, [lds]() {
+        if (lds > 65536)
+            attr = hipFuncSetAttribute((const void *)k_fft_pass<LOGL, S>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    });
+    if (attr != hipSuccess) return (int)attr;
+    const int groups = (P.n_seq + S - 1) / S;
+    hipLaunchKernelGGL((k_fft_pass<LOGL, S>), dim3(groups, batches), dim3(256), lds, st, P);
+    return (int)hipGetLastError();
+}
+
+// Sequences per workgroup: S L = 4096 values (32 KB, four workgroups per
+// compute unit) for batched passes; 4 for a single transform, so that it
+// still spreads over the chip.
+template <int LOGL>
+int launch_l(const Pass &P, int batches, bool few, hipStream_t st) {
+    constexpr int SB = (4096 >> LOGL) > 16 ? 16 : ((4096 >> LOGL) < 1 ? 1 : (4096 >> LOGL));
+    constexpr int SS = SB < 4 ? SB : 4;
+    return few ? launch_ls<LOGL, SS>(P, batches, st) : launch_ls<LOGL, SB>(P, batches, st);
+}
+
+}  // namespace
+
 int launch_pass(const Pass &P, int batches, void *stream) {
-    const int groups = (P.n_seq + P.S - 1) / P.S;
-    const size_t lds = (size_t)P.S * P.L * sizeof(float2);
-    hipLaunchKernelGGL(k_fft_pass, dim3(groups, batches), dim3(256), lds, (hipStream_t)stream, P);
+    hipStream_t st = (hipStream_t)stream;
+    const bool few = (long long)P.n_seq * batches < 4096;
+    switch (P.log_l) {
+        case 2: return launch_l<2>(P, batches, few, st);
+        case 3: return launch_l<3>(P, batches, few, st);
+        case 4: return launch_l<4>(P, batches, few, st);
+        case 5: return launch_l<5>(P, batches, few, st);
+        case 6: return launch_l<6>(P, batches, few, st);
+        case 7: return launch_l<7>(P, batches, few, st);
+        case 8: return launch_l<8>(P, batches, few, st);
+        case 9: return launch_l<9>(P, batches, few, st);
+        case 10: return launch_l<10>(P, batches, few, st);
+    }
+    return (int)hipErrorInvalidValue;
+}
+
+int launch_combine(const float2 *e, const float2 *X, float2 *G, int pairs, long long n, void *stream) {
+    hipLaunchKernelGGL(k_combine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, e, X, G,
+                       pairs, n);
     return (int)hipGetLastError();
 }
 

@@ -14,8 +14,7 @@ enum Load : int {
     kLoadEmbedPair = 1, // (fE_{2t}(i), fE_{2t+1}(i)): E f of the pair's wavelengths
     kLoadCalPair = 2,   // (c_{2t}[i], -c_{2t+1}[i]) from a dense w x n calibration
     kLoadReal = 3,      // (u[i], 0)
-    kLoadCombine = 4,   // sum_t e_t[i] X_t[i]
-    kLoadConjE = 5,     // conj(e_t[i]) U[i]
+    kLoadConjE = 4,     // conj(e_t[i]) U[i]
 };
 // Store modes (pass B writes element k of the batch's sequence in natural order):
 enum Store : int {
@@ -29,32 +28,35 @@ enum Store : int {
 struct Geo {
     int a, alpha, gamma, xi, w;
     long long ell;
+    int log_gamma;             // n = gamma xi is a power of two, so gamma is one
 };
 
 struct Pass {
-    const float2 *in;          // complex input (modes complex, combine: X; conj-e: U)
+    const float2 *in;          // complex input (mode complex; conj-e: U)
     float2 *out;               // complex output (pass A, complex store)
     const float *fin;          // real input (embed: f; real: u; cal: c)
     float *fout;               // real output (real, ratio: ghat / u; crop: z; update: f)
     const float *g;            // ratio: the measured frame
-    const float2 *e;           // spectra e_t (combine, conj-e)
+    const float2 *e;           // spectra e_t (conj-e)
     const float *h;            // column sums per wavelength (update)
     const float2 *tw_stage;    // exp(-2 pi i j / L), j < L / 2
     const float2 *tw_hi;       // exp(-2 pi i a / N1), a < N1   (pass A only)
     const float2 *tw_lo;       // exp(-2 pi i b / N),  b < N2   (pass A only)
     long long n;
-    int L, log_l, S;           // transform length, log2, sequences per workgroup
+    int L, log_l;              // transform length and its log2
     int n_seq;                 // sequences per batch (N2 for pass A, N1 for pass B)
     int pass_a;                // 1: pass A (strided columns, twiddle, Y layout); 0: pass B
     int N1, N2, log_n2;
     int inverse;
     int load, store;
-    int pairs;                 // number of wavelength pairs (combine sums over them)
     Geo geo;
 };
 
-int seqs_per_group(int L, int n_seq);
+// One FFT pass (pass A or B per P.pass_a) over `batches` sequences of P.n_seq
+// transforms of length 2^P.log_l (2^2 .. 2^10).
 int launch_pass(const Pass &P, int batches, void *stream);
+// G = sum_t e_t . X_t over `pairs` spectra of length n.
+int launch_combine(const float2 *e, const float2 *X, float2 *G, int pairs, long long n, void *stream);
 
 }  // namespace fourier
 }  // namespace ctis
