@@ -94,6 +94,9 @@ def main(argv=None) -> int:
     ap.add_argument("--path", choices=["gather", "fourier"], default="gather",
                     help="gather: projections as gathers over the calibration nonzeros; fourier: the paper's "
                          "FFT form (configs 1-3)")
+    ap.add_argument("--blob-radius", type=int, default=0, metavar="R",
+                    help="with --path fourier: replace the configuration's calibration blobs by "
+                         "(2R+1)^2 blobs (denser calibrations: the gather/Fourier crossover)")
     ap.add_argument("--launch", choices=["graph", "stream"], default="graph",
                     help="graph: each step is one replay of a HIP graph holding the whole solve; "
                          "stream: the solve's kernels are launched one by one on the stream")
@@ -406,7 +409,15 @@ def bench_fourier(args, torch, ctis, W, dev) -> int:
     """The same single-frame EM solve through the Fourier (WBH) projections:
     per iteration w/2 + 1 forward and w/2 + 1 inverse complex FFTs of length
     n (two FFT passes each), with the gather path's rate beside it."""
-    case = W.make_case(args.config)
+    if args.blob_radius > 0:
+        base = W.CONFIGS[args.config]
+        R = args.blob_radius
+        cfg0 = W.Config(f"{base.name} with {2 * R + 1}x{2 * R + 1} blobs", base.geometry,
+                        W.KernelModel(base.kernel.orders, R, 0.4 * R + 0.4, base.kernel.dispersion),
+                        iters=base.iters, noise=base.noise, photons=base.photons)
+        case = W.make_case(args.config, cfg=cfg0)
+    else:
+        case = W.make_case(args.config)
     cfg, geo, K = case.cfg, case.geometry, case.cfg.iters
     progress(f"fourier {cfg.name}: plan and spectra")
     plan = ctis.Plan.from_case(case)
@@ -471,7 +482,7 @@ def bench_fourier(args, torch, ctis, W, dev) -> int:
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": cfg.name + " (Fourier projections)", "n": N, "fft": f"{F.info['n1']}x{F.info['n2']}",
-                   "pairs": P, "em_iters_per_step": K},
+                   "pairs": P, "em_iters_per_step": K, "nnz_per_wavelength": plan.info.nnz // geo.w},
         "voxel_updates_per_s": it_s * m,
         "gather_path_em_iters_per_s": gather_it_s,
         "fourier_vs_gather": it_s / gather_it_s,

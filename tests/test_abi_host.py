@@ -262,3 +262,16 @@ def test_keep_zeros_keeps_every_position_in_a_box(oracle_mod, lib, box):
                       for k in range(lam.size)]
             assert sum(inside) >= 1, (s, r, c)
     assert kept.info.vjp_workspace_bytes > kept.info.workspace_bytes > 0
+
+
+def test_fourier_rejects_host_only_plans(lib):
+    """The Fourier path needs a device plan: creating it from a host-only plan
+    fails with CTIS_E_ARG before any device work."""
+    import ctypes
+    geo = W.Geometry(5, 4, 2, 16, 16)
+    ptr, idx, val = W.random_kernels(geo, 5, np.random.default_rng(1))
+    p = host_plan(geo, ptr, idx, val)
+    h = ctypes.c_void_p()
+    st = lib.ctis_fourier_create(ctypes.byref(h), p._handle)
+    assert st == 1 and not h.value
+    assert b"host-only" in lib.ctis_last_error()
