@@ -110,43 +110,6 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
-// Sums of N values (N a power of two <= 64) over the 64 lanes, one sum per
-// lane group: while the partner distance m halves (32, 16, ...), each lane
-// keeps one half of its values -- the upper half if its lane bit m is set --
-// adds the partner's copy of that half and hands over the other half; the
-// lane bits below the last m are then summed plainly.  N - 1 + (6 - log2 N)
-// exchanges instead of 6 N.  Lane L ends with the total of value
-// scatter_index<N>(L); lanes that differ only in the low bits hold equal
-// (bitwise) totals.
-template <int N>
-__device__ __forceinline__ float reduce_scatter(float (&a)[N], int lane) {
-#pragma unroll
-    for (int h = N / 2, m = 32; h >= 1; h >>= 1, m >>= 1) {
-        const bool hi = (lane & m) != 0;
-#pragma unroll
-        for (int i = 0; i < h; ++i) {
-            const float keep = hi ? a[i + h] : a[i];
-            const float send = hi ? a[i] : a[i + h];
-            a[i] = keep + __shfl_xor(send, m, 64);
-        }
-    }
-    float v = a[0];
-#pragma unroll
-    for (int m = 64 / N / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-    return v;
-}
-
-template <int N>
-__device__ __forceinline__ int scatter_index(int lane) {
-    int idx = 0;
-#pragma unroll
-    for (int h = N / 2, m = 32; h >= 1; h >>= 1, m >>= 1)
-        if (lane & m) idx += h;
-    return idx;
-}
-
-constexpr int pow2_at_least(int x) { return x <= 1 ? 1 : 2 * pow2_at_least((x + 1) / 2); }
-
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const float *base, int nfloats) {
     return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, nfloats * 4, kRsrcWord3);
 }
@@ -695,13 +658,13 @@ __global__ void __launch_bounds__(64 * kVgWaves) k_value_grad(const int4 *__rest
             for (int t = 0; t < BB; ++t) acc[t] = 0.0f;
             correlate_values<B>(acc, Su, Se, bq, fq, lx, ly);
             wave_lds_sync();
-            constexpr int N = pow2_at_least(BB);
-            float red[N];
+            float mine = 0.0f;
 #pragma unroll
-            for (int t = 0; t < N; ++t) red[t] = t < BB ? acc[t] : 0.0f;
-            const float tot = reduce_scatter<N>(red, lane);
-            const int idx = scatter_index<N>(lane);
-            if ((lane & (64 / N - 1)) == 0 && idx < BB) part[((size_t)unit * stride + k) * BB + idx] = tot;
+            for (int t = 0; t < BB; ++t) {
+                const float tot = wave_sum(acc[t]);
+                if (lane == t) mine = tot;
+            }
+            if (lane < BB) part[((size_t)unit * stride + k) * BB + lane] = mine;
             k += nw;
             rec = nxt;
         }
