@@ -317,3 +317,47 @@ def test_vjp_in_a_hip_graph(torch, ctis, oracle_mod):
         torch.cuda.synchronize()
         assert torch.equal(df, ref_df) and torch.equal(dv, ref_dv), f"replay {rep} differs"
         del junk
+
+
+def test_unrolled_gradients_on_a_batch_of_distinct_plans(torch, ctis, oracle_mod):
+    """The autograd Function over a batch of three frames (two distinct plans,
+    one shared): gradients of f0 per frame and of each plan's values (summed
+    over the frames that share them) against the oracle; and the f0-only
+    path (no values given)."""
+    from paper_2006_01573_amd.autodiff import unrolled_em
+    geos = [W.Geometry(5, 4, 3, 23, 17), W.Geometry(9, 6, 2, 40, 30)]
+    rng = np.random.default_rng(61)
+    kern = [W.random_kernels(g, 10, rng, clustered=True) for g in geos]
+    plans = [ctis.Plan(g.a, g.alpha, g.w, g.gamma, g.xi, *k, box=3, keep_zeros=True) for g, k in zip(geos, kern)]
+    order = [0, 1, 0]
+    b = ctis.Batch([plans[k] for k in order])
+    orc = [oracle_mod.Oracle(geos[k].a, geos[k].alpha, geos[k].w, geos[k].gamma, geos[k].xi, kern[k][0],
+                             kern[k][1], kern[k][2].astype(np.float64)) for k in range(2)]
+    fo, go = b.f_offsets, b.g_offsets
+    K = 4
+    f0 = rng.uniform(0.5, 1.5, fo[-1]).astype(np.float32)
+    tgt = rng.uniform(0.2, 2.0, fo[-1])
+    g = np.concatenate([orc[order[k]].forward(rng.uniform(0.2, 2, geos[order[k]].m))
+                        for k in range(3)]).astype(np.float32)
+    vals = np.concatenate([kern[0][2], kern[1][2]]).astype(np.float32)
+    f0_t = torch.tensor(f0, device="cuda", requires_grad=True)
+    v_t = torch.tensor(vals, device="cuda", requires_grad=True)
+    fK = unrolled_em(b, torch.from_numpy(g).cuda(), f0_t, K, values=v_t)
+    ((fK - torch.tensor(tgt, dtype=torch.float32, device="cuda")) ** 2).sum().backward()
+    gf0, gv = f0_t.grad.cpu().numpy(), v_t.grad.cpu().numpy()
+    dv_ref = [np.zeros(kern[0][2].size), np.zeros(kern[1][2].size)]
+    for k in range(3):
+        sl = slice(fo[k], fo[k + 1])
+        t = tgt[sl]
+        _, df0, dv = orc[order[k]].unrolled_grad(g[go[k]:go[k + 1]], f0[sl].astype(np.float64), K,
+                                                 lambda x, t=t: 2.0 * (x - t))
+        assert rel_l2(gf0[sl], df0) <= GRAD_TOL
+        dv_ref[order[k]] += dv
+    n0 = kern[0][2].size
+    assert b.plan_entries(1) == (n0, kern[1][2].size)
+    assert rel_l2(gv[:n0], dv_ref[0]) <= GRAD_TOL
+    assert rel_l2(gv[n0:], dv_ref[1]) <= GRAD_TOL
+    f0_b = torch.tensor(f0, device="cuda", requires_grad=True)
+    fK2 = unrolled_em(b, torch.from_numpy(g).cuda(), f0_b, K)
+    ((fK2 - torch.tensor(tgt, dtype=torch.float32, device="cuda")) ** 2).sum().backward()
+    assert torch.allclose(f0_b.grad, f0_t.grad, rtol=1e-5, atol=1e-6 * f0_t.grad.abs().max().item())
