@@ -17,9 +17,10 @@
 // of Y, written in natural order X[k1 + N1 k2].  A workgroup holds S
 // sequences (S L = 4096 complex values when many transforms run together, 4
 // sequences for a single transform) laid out [element][seq], loads them so
-// that consecutive lanes touch consecutive addresses, applies log2 L radix-2
-// stages in place after a bit-reversed load with the stage twiddles staged
-// in LDS, and stores the same way.  Loads and stores carry the pipeline's own
+// that consecutive lanes touch consecutive addresses, applies the log2 L
+// radix-2 stages in place after a bit-reversed load -- two at a time, in
+// registers, with the stage twiddles staged in LDS -- and stores the same
+// way.  Loads and stores carry the pipeline's own
 // steps (embedding E f, the products conj(e_t) U, the ratio g / ghat, the
 // crop E^T and the EM update); the sum over pairs of the forward's spectral
 // products is one elementwise kernel.  Twiddles come from tables computed in
@@ -157,20 +158,41 @@ __global__ void __launch_bounds__(256) k_fft_pass(const Pass P) {
         buf[jr * S + s] = make_float2(v.x, v.y);
     }
     __syncthreads();
-#pragma unroll
-    for (int lh = 0; lh < LOGL; ++lh) {
-        const int half = 1 << lh;
-        const int step = L / (2 * half);
+    // an odd number of radix-2 stages starts with one plain radix-2 stage
+    if (LOGL & 1) {
 #pragma unroll 4
         for (int b = threadIdx.x; b < (L / 2) * S; b += 256) {
+            const int s = b % S, i0 = 2 * (b / S), i1 = i0 + 1;
+            const float2 a = buf[i0 * S + s], c = buf[i1 * S + s];
+            buf[i0 * S + s] = make_float2(a.x + c.x, a.y + c.y);
+            buf[i1 * S + s] = make_float2(a.x - c.x, a.y - c.y);
+        }
+        __syncthreads();
+    }
+    // then pairs of radix-2 stages (half h and 2h) fused: each thread takes
+    // i0 = 4h-block + m and i0 + h, i0 + 2h, i0 + 3h through both stages in
+    // registers (twiddles w_2h^m for the first, w_4h^m and w_4h^(m+h) for
+    // the second)
+#pragma unroll
+    for (int lh = LOGL & 1; lh + 1 < LOGL; lh += 2) {
+        const int half = 1 << lh;
+#pragma unroll 2
+        for (int b = threadIdx.x; b < (L / 4) * S; b += 256) {
             const int s = b % S, p = b / S;
             const int m = p & (half - 1);
-            const int i0 = (p - m) * 2 + m, i1 = i0 + half;
-            const float2 wt = twl[m * step];
-            const float2 a = buf[i0 * S + s], c = buf[i1 * S + s];
-            const C2 cw = cmul({c.x, c.y}, {wt.x, wt.y});
-            buf[i0 * S + s] = make_float2(a.x + cw.x, a.y + cw.y);
-            buf[i1 * S + s] = make_float2(a.x - cw.x, a.y - cw.y);
+            const int i0 = (p - m) * 4 + m, i1 = i0 + half, i2 = i1 + half, i3 = i2 + half;
+            const float2 w1 = twl[m * (L / (2 * half))];
+            const float2 w2 = twl[m * (L / (4 * half))];
+            const float2 w3 = twl[(m + half) * (L / (4 * half))];
+            const float2 a0 = buf[i0 * S + s], a1 = buf[i1 * S + s], a2 = buf[i2 * S + s], a3 = buf[i3 * S + s];
+            const C2 t1 = cmul({a1.x, a1.y}, {w1.x, w1.y}), t3 = cmul({a3.x, a3.y}, {w1.x, w1.y});
+            const C2 b0 = {a0.x + t1.x, a0.y + t1.y}, b1 = {a0.x - t1.x, a0.y - t1.y};
+            const C2 b2 = {a2.x + t3.x, a2.y + t3.y}, b3 = {a2.x - t3.x, a2.y - t3.y};
+            const C2 u2 = cmul(b2, {w2.x, w2.y}), u3 = cmul(b3, {w3.x, w3.y});
+            buf[i0 * S + s] = make_float2(b0.x + u2.x, b0.y + u2.y);
+            buf[i2 * S + s] = make_float2(b0.x - u2.x, b0.y - u2.y);
+            buf[i1 * S + s] = make_float2(b1.x + u3.x, b1.y + u3.y);
+            buf[i3 * S + s] = make_float2(b1.x - u3.x, b1.y - u3.y);
         }
         __syncthreads();
     }
