@@ -345,6 +345,21 @@ def bench_batched(args, torch, ctis, W, dev) -> int:
     e1.record()
     torch.cuda.synchronize()
     seq_fps = 64 * seq_steps / (e0.elapsed_time(e1) / 1e3)
+    # the same 64 solves, each frame's solve replayed from its own HIP graph
+    progress("c4: timing sequential single-frame solves from HIP graphs")
+    graphs = []
+    for p, gk, fk, wk in zip(plans, gs, fs, wss):
+        def one(p=p, gk=gk, fk=fk, wk=wk):
+            fk.fill_(1.0)
+            p.em(gk, K, f=fk, workspace=wk)
+        graphs.append(_graph_of(torch, one))
+    e0.record()
+    for _ in range(seq_steps):
+        for gr_k in graphs:
+            gr_k.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    seq_graph_fps = 64 * seq_steps / (e0.elapsed_time(e1) / 1e3)
     # per-kernel durations of the batched EM halves (back to back, events around)
     infos = [p.info for p in plans]
     m_all = sum(i.m for i in infos)
@@ -381,6 +396,8 @@ def bench_batched(args, torch, ctis, W, dev) -> int:
                              "candidates": len(tuned.table)}},
         "sequential_frames_per_s": seq_fps,
         "batched_vs_sequential": batched_fps / seq_fps,
+        "sequential_graph_frames_per_s": seq_graph_fps,
+        "batched_vs_sequential_graph": batched_fps / seq_graph_fps,
         "em_iteration_all_frames_us": it_ms * 1e3,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
