@@ -120,6 +120,24 @@ __device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, unsigned off) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
 }
 
+// The SY rows of one window column, from a buffer with row pitch P floats:
+// row yy sits at byte offset 4*(col + P*((y + yy) mod xi)), given
+// o0 = 4*(col + P*y) and wrap = 4*P*xi.  For xi >= SY the row index wraps at
+// most once over the window, so the offset is min(o, o - wrap) in unsigned
+// arithmetic with o = o0 + 4*P*yy the unwrapped one (below wrap, o - wrap
+// wraps round to more than o).  All offsets stay below 2^32: o0 < 4n, and
+// 4*P*SY <= 4n for P <= gamma, with n < 2^29.  A column whose o0 lies past
+// the buffer, with wrap = 0, reads 0 in every row.
+template <int B>
+__device__ __forceinline__ void column_rows(float (&v)[Win<B>::SY], __amdgpu_buffer_rsrc_t r, unsigned o0,
+                                            unsigned step, unsigned wrap) {
+#pragma unroll
+    for (int yy = 0; yy < Win<B>::SY; ++yy) {
+        const unsigned o = o0 + step * (unsigned)yy;
+        v[yy] = bload(r, min(o, o - wrap));
+    }
+}
+
 // Frame geometry of a work unit.
 struct Geo {
     int a, alpha, gamma, xi;
@@ -151,11 +169,18 @@ __device__ __forceinline__ void load_forward(Pending<B> &pd, const float *f, con
         y = step_mod(y, p.xi);
     }
     const bool vx = xm < p.a;
+    if (p.xi >= Wn::SY) {
+        // rows at or past alpha land at or past a*alpha floats and read 0;
+        // columns outside the field stop start past the buffer and never wrap
+        column_rows<B>(pd.v, fr, vx ? (unsigned)(xm + p.a * y) * 4u : kOutOfRange, 4u * (unsigned)p.a,
+                       vx ? 4u * (unsigned)(p.a * p.xi) : 0u);
+    } else {
 #pragma unroll
-    for (int yy = 0; yy < Wn::SY; ++yy) {
-        const bool ok = vx && (y < p.alpha);
-        pd.v[yy] = bload(fr, ok ? (unsigned)(xm + p.a * y) * 4u : kOutOfRange);
-        y = step_mod(y, p.xi);
+        for (int yy = 0; yy < Wn::SY; ++yy) {
+            const bool ok = vx && (y < p.alpha);
+            pd.v[yy] = bload(fr, ok ? (unsigned)(xm + p.a * y) * 4u : kOutOfRange);
+            y = step_mod(y, p.xi);
+        }
     }
 #pragma unroll
     for (int t = 0; t < Wn::NXT; ++t) {
@@ -195,10 +220,15 @@ __device__ __forceinline__ void load_adjoint(Pending<B> &pd, __amdgpu_buffer_rsr
         xm -= p.gamma;
         y = step_mod(y, p.xi);
     }
+    if (p.xi >= Wn::SY) {
+        column_rows<B>(pd.v, ur, (unsigned)(xm + p.gamma * y) * 4u, 4u * (unsigned)p.gamma,
+                       4u * (unsigned)(p.gamma * p.xi));
+    } else {
 #pragma unroll
-    for (int yy = 0; yy < Wn::SY; ++yy) {
-        pd.v[yy] = bload(ur, (unsigned)(xm + p.gamma * y) * 4u);
-        y = step_mod(y, p.xi);
+        for (int yy = 0; yy < Wn::SY; ++yy) {
+            pd.v[yy] = bload(ur, (unsigned)(xm + p.gamma * y) * 4u);
+            y = step_mod(y, p.xi);
+        }
     }
 #pragma unroll
     for (int t = 0; t < Wn::NXT; ++t) {
@@ -530,12 +560,25 @@ __device__ __forceinline__ void load_pair(Pending<B> &pu, Pending<B> &pe, __amdg
         xm -= p.gamma;
         y = step_mod(y, p.xi);
     }
+    if (p.xi >= Wn::SY) {
+        const bool vx = lane < xlim;
+        const unsigned o0 = vx ? (unsigned)(xm + p.gamma * y) * 4u : kOutOfRange;
+        const unsigned step = 4u * (unsigned)p.gamma, wrap = vx ? 4u * (unsigned)(p.gamma * p.xi) : 0u;
 #pragma unroll
-    for (int yy = 0; yy < Wn::SY; ++yy) {
-        const unsigned off = (lane < xlim && yy < ylim) ? (unsigned)(xm + p.gamma * y) * 4u : kOutOfRange;
-        pu.v[yy] = bload(ur, off);
-        pe.v[yy] = bload(er, off);
-        y = step_mod(y, p.xi);
+        for (int yy = 0; yy < Wn::SY; ++yy) {
+            const unsigned o = o0 + step * (unsigned)yy;
+            const unsigned off = yy < ylim ? min(o, o - wrap) : kOutOfRange;
+            pu.v[yy] = bload(ur, off);
+            pe.v[yy] = bload(er, off);
+        }
+    } else {
+#pragma unroll
+        for (int yy = 0; yy < Wn::SY; ++yy) {
+            const unsigned off = (lane < xlim && yy < ylim) ? (unsigned)(xm + p.gamma * y) * 4u : kOutOfRange;
+            pu.v[yy] = bload(ur, off);
+            pe.v[yy] = bload(er, off);
+            y = step_mod(y, p.xi);
+        }
     }
 #pragma unroll
     for (int t = 0; t < Wn::NXT; ++t) {
