@@ -79,6 +79,10 @@ def edge_cases():
     ptr, idx, val = W.random_kernels(geo, 12, np.random.default_rng(21), clustered=True)
     out.append(("ragged", geo, ptr, idx, val, 0))
     out.append(("split",) + split_case() + (0,))
+    for B in range(1, 9):                          # xi equal to the window height 16 + B - 1
+        geo = W.Geometry(7, 5 + B, 2, 11, 15 + B)
+        ptr, idx, val = W.random_kernels(geo, 3 + B, np.random.default_rng(40 + B), clustered=True)
+        out.append((f"rows-box{B}", geo, ptr, idx, val, B))
     return out
 
 

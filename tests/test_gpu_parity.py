@@ -103,6 +103,27 @@ def test_projection_parity_every_box_size(torch, ctis, oracle_mod, box):
     check_projections(torch, ctis, oracle_mod, geo, ptr, idx, val, seed=box, box=box)
 
 
+# A window spans 16 + B - 1 FPA rows.  Where xi is at least that many rows
+# the kernels take each row's offset by a wrap-once rule, below it row by
+# row: xi one below, at and one above the window height, on FPAs narrower
+# than a window (columns wrap onto the next row) and wider than one tile.
+ROWS = [(box, dxi, cols) for box in range(1, 9) for dxi in (-1, 0, 1) for cols in ((11, 7), (70, 66))]
+
+
+@pytest.mark.parametrize("box,dxi,cols", ROWS, ids=[f"B{b}-xi{15 + b + d}-g{c[0]}" for b, d, c in ROWS])
+def test_window_rows_near_window_height(torch, ctis, oracle_mod, box, dxi, cols):
+    gamma, a = cols
+    xi = 15 + box + dxi
+    geo = W.Geometry(a, min(xi, 5 + box), 2, gamma, xi)
+    rng = np.random.default_rng(1000 * box + 10 * xi + gamma)
+    ptr, idx, val = W.random_kernels(geo, 3 + box, rng, clustered=box % 2 == 0)
+    p, o = check_projections(torch, ctis, oracle_mod, geo, ptr, idx, val, seed=box, box=box, signed=True)
+    assert p.info.box == box
+    g = (o.forward(rng.uniform(0.2, 2.0, geo.m)) * rng.uniform(0.7, 1.3, geo.n)).astype(np.float32)
+    f = p.em(torch.from_numpy(g).cuda(), 2).cpu().numpy()
+    assert rel_l2(f, o.em(g, 2)) <= EM_TOL
+
+
 def test_empty_and_zero_wavelengths(torch, ctis, oracle_mod):
     geo = W.Geometry(8, 5, 3, 40, 30)
     # wavelength 1 has no entries, wavelength 2 only an explicit zero
