@@ -562,12 +562,12 @@ __device__ __forceinline__ void load_pair(Pending<B> &pu, Pending<B> &pe, __amdg
     }
     if (p.xi >= Wn::SY) {
         const bool vx = lane < xlim;
-        const unsigned o0 = vx ? (unsigned)(xm + p.gamma * y) * 4u : kOutOfRange;
-        const unsigned step = 4u * (unsigned)p.gamma, wrap = vx ? 4u * (unsigned)(p.gamma * p.xi) : 0u;
+        const unsigned o0 = (unsigned)(xm + p.gamma * y) * 4u;
+        const unsigned step = 4u * (unsigned)p.gamma, wrap = 4u * (unsigned)(p.gamma * p.xi);
 #pragma unroll
         for (int yy = 0; yy < Wn::SY; ++yy) {
             const unsigned o = o0 + step * (unsigned)yy;
-            const unsigned off = yy < ylim ? min(o, o - wrap) : kOutOfRange;
+            const unsigned off = (vx && yy < ylim) ? min(o, o - wrap) : kOutOfRange;
             pu.v[yy] = bload(ur, off);
             pe.v[yy] = bload(er, off);
         }
