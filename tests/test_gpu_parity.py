@@ -279,6 +279,45 @@ def test_c2_em_full_iterations(torch, c2):
     assert np.all(f_gpu >= 0)
 
 
+@pytest.fixture(scope="module")
+def largest_fpa(oracle_mod):
+    """An FPA just below the 2^29-pixel limit (23170 x 23170), so byte
+    offsets into g and u reach 2^31; a small datacube, spread-out nonzeros."""
+    geo = W.Geometry(32, 32, 4, 23170, 23170)
+    assert geo.n < 2 ** 29
+    rng = np.random.default_rng(29)
+    ptr, idx, val = W.random_kernels(geo, 6, rng)
+    log(f"largest FPA: building the oracle for n = {geo.n}")
+    o = oracle_for(oracle_mod, geo, ptr, idx, val)
+    return geo, ptr, idx, val, o
+
+
+@pytest.mark.parametrize("box", [0, 8])
+def test_largest_fpa(torch, ctis, largest_fpa, box):
+    geo, ptr, idx, val, o = largest_fpa
+    rng = np.random.default_rng(30 + box)
+    log(f"largest FPA box={box}: plan")
+    p = gpu_plan(ctis, geo, ptr, idx, val, box=box)
+    f = rng.random(geo.m).astype(np.float32)
+    g = p.forward(torch.from_numpy(f).cuda()).cpu().numpy().ravel()
+    g_ref = o.forward(f)
+    nz = np.flatnonzero(g_ref)
+    rows = np.concatenate([nz, rng.choice(geo.n, 4000, replace=False), np.arange(geo.n - geo.gamma, geo.n)])
+    log(f"  forward: {nz.size} nonzero rows")
+    assert rel_l2(g[rows], g_ref[rows]) <= PROJ_TOL
+    assert not np.any(g[g_ref == 0])                   # pixels no voxel reaches stay 0
+    del g
+    r = rng.random(geo.n, dtype=np.float32)
+    z = p.adjoint(torch.from_numpy(r).cuda()).cpu().numpy().ravel()
+    assert rel_l2(z, o.adjoint(r)) <= PROJ_TOL
+    del r
+    gm = (g_ref * rng.uniform(0.7, 1.3, geo.n)).astype(np.float32)
+    log("  EM, 2 iterations")
+    fe = p.em(torch.from_numpy(gm).cuda(), 2).cpu().numpy()
+    assert rel_l2(fe, o.em(gm, 2)) <= EM_TOL
+    p.close()
+
+
 def test_c3_sampled_projections(torch, ctis, oracle_mod):
     """Full-size c3 projections on the GPU, checked on sampled pixels and
     voxels that the oracle evaluates one by one from the definition."""
