@@ -355,6 +355,8 @@ ctis_status ctis_batch_plan_entries(const ctis_batch *batch, int32_t frame, int6
  * ctis_fourier_create computes the spectra e_t = F(c_{2t} - i c_{2t+1}) of the
  * plan's calibration on the current device (it synchronises the device before
  * returning) and keeps a pointer to the plan, which must outlive it.  The
+ * spectra and the sums h_s are those of the plan's values at creation: after
+ * ctis_plan_set_values, create the Fourier plan again.  The
  * spectra take info.spectra_bytes of device memory; the calls take a
  * workspace of info.workspace_bytes (256-byte aligned).  Layouts of f, g, r, z
  * as for the gather path.  Errors: CTIS_E_ARG (n not a power of two in range,
