@@ -18,7 +18,7 @@
 // sequences (S L = 8192 complex values when many transforms run together, 4
 // sequences for a single transform) laid out [element][seq], loads them so
 // that consecutive lanes touch consecutive addresses, applies the log2 L
-// radix-2 stages in place after a bit-reversed load -- two at a time, in
+// radix-2 stages in place after a bit-reversed load -- three at a time, in
 // registers, with the stage twiddles staged in LDS -- and stores the same
 // way.  Loads and stores carry the pipeline's own
 // steps (embedding E f, the products conj(e_t) U, the ratio g / ghat, the
@@ -43,6 +43,20 @@ struct C2 {
 
 __device__ __forceinline__ C2 cmul(C2 a, C2 b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
 __device__ __forceinline__ C2 cmulc(C2 a, C2 b) { return {a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x}; }  // conj(a) b
+
+// (a, b) <- (a + w b, a - w b): one radix-2 butterfly of the decimation in time
+__device__ __forceinline__ void bfly(C2 &a, C2 &b, C2 w) {
+    const C2 t = cmul(b, w);
+    b = {a.x - t.x, a.y - t.y};
+    a = {a.x + t.x, a.y + t.y};
+}
+
+__device__ __forceinline__ C2 ld(const float2 *buf, int i, int S, int s) {
+    const float2 v = buf[i * S + s];
+    return {v.x, v.y};
+}
+
+__device__ __forceinline__ void st(float2 *buf, int i, int S, int s, C2 v) { buf[i * S + s] = make_float2(v.x, v.y); }
 
 __device__ __forceinline__ C2 tw(const float2 *t, int j, int inverse) {
     const float2 v = t[j];
@@ -160,8 +174,11 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_pass(const Pass P) {
         buf[jr * S + s] = make_float2(v.x, v.y);
     }
     __syncthreads();
-    // an odd number of radix-2 stages starts with one plain radix-2 stage
-    if (LOGL & 1) {
+    // the log2 L radix-2 stages, three at a time (radix 8) after one radix-2
+    // or radix-4 step for the remainder of log2 L mod 3: LOGL = 9 takes three
+    // round trips through LDS, LOGL = 10 four
+    constexpr int REM = LOGL % 3;
+    if (REM == 1) {
 #pragma unroll 4
         for (int b = threadIdx.x; b < (L / 2) * S; b += kFftThreads) {
             const int s = b % S, i0 = 2 * (b / S), i1 = i0 + 1;
@@ -171,30 +188,57 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_pass(const Pass P) {
         }
         __syncthreads();
     }
-    // then pairs of radix-2 stages (half h and 2h) fused: each thread takes
-    // i0 = 4h-block + m and i0 + h, i0 + 2h, i0 + 3h through both stages in
-    // registers (twiddles w_2h^m for the first, w_4h^m and w_4h^(m+h) for
-    // the second)
-#pragma unroll
-    for (int lh = LOGL & 1; lh + 1 < LOGL; lh += 2) {
-        const int half = 1 << lh;
+    if (REM == 2) {
+        // stages of half 1 and 2: each thread takes a block of 4
 #pragma unroll 2
         for (int b = threadIdx.x; b < (L / 4) * S; b += kFftThreads) {
+            const int s = b % S, i0 = 4 * (b / S);
+            const float2 w3 = twl[L / 4];   // w_4^1
+            C2 a0 = ld(buf, i0, S, s), a1 = ld(buf, i0 + 1, S, s), a2 = ld(buf, i0 + 2, S, s),
+               a3 = ld(buf, i0 + 3, S, s);
+            bfly(a0, a1, {1.0f, 0.0f});
+            bfly(a2, a3, {1.0f, 0.0f});
+            bfly(a0, a2, {1.0f, 0.0f});
+            bfly(a1, a3, {w3.x, w3.y});
+            st(buf, i0, S, s, a0);
+            st(buf, i0 + 1, S, s, a1);
+            st(buf, i0 + 2, S, s, a2);
+            st(buf, i0 + 3, S, s, a3);
+        }
+        __syncthreads();
+    }
+    // stages of half h, 2h and 4h in registers: each thread takes
+    // i_k = 8h-block + m + k h (k < 8); twiddles w_2h^m, w_4h^(m + {0,h}),
+    // w_8h^(m + {0,h,2h,3h}), all powers of w_L from the staged table
+#pragma unroll
+    for (int lh = REM; lh + 2 < LOGL; lh += 3) {
+        const int h = 1 << lh;
+#pragma unroll 2
+        for (int b = threadIdx.x; b < (L / 8) * S; b += kFftThreads) {
             const int s = b % S, p = b / S;
-            const int m = p & (half - 1);
-            const int i0 = (p - m) * 4 + m, i1 = i0 + half, i2 = i1 + half, i3 = i2 + half;
-            const float2 w1 = twl[m * (L / (2 * half))];
-            const float2 w2 = twl[m * (L / (4 * half))];
-            const float2 w3 = twl[(m + half) * (L / (4 * half))];
-            const float2 a0 = buf[i0 * S + s], a1 = buf[i1 * S + s], a2 = buf[i2 * S + s], a3 = buf[i3 * S + s];
-            const C2 t1 = cmul({a1.x, a1.y}, {w1.x, w1.y}), t3 = cmul({a3.x, a3.y}, {w1.x, w1.y});
-            const C2 b0 = {a0.x + t1.x, a0.y + t1.y}, b1 = {a0.x - t1.x, a0.y - t1.y};
-            const C2 b2 = {a2.x + t3.x, a2.y + t3.y}, b3 = {a2.x - t3.x, a2.y - t3.y};
-            const C2 u2 = cmul(b2, {w2.x, w2.y}), u3 = cmul(b3, {w3.x, w3.y});
-            buf[i0 * S + s] = make_float2(b0.x + u2.x, b0.y + u2.y);
-            buf[i2 * S + s] = make_float2(b0.x - u2.x, b0.y - u2.y);
-            buf[i1 * S + s] = make_float2(b1.x + u3.x, b1.y + u3.y);
-            buf[i3 * S + s] = make_float2(b1.x - u3.x, b1.y - u3.y);
+            const int m = p & (h - 1);
+            const int i0 = (p - m) * 8 + m;
+            const int q1 = L / (2 * h), q2 = L / (4 * h), q3 = L / (8 * h);
+            C2 x[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) x[k] = ld(buf, i0 + k * h, S, s);
+            const float2 t1 = twl[m * q1];
+            const C2 w1 = {t1.x, t1.y};
+#pragma unroll
+            for (int k = 0; k < 8; k += 2) bfly(x[k], x[k + 1], w1);
+            const float2 t20 = twl[m * q2], t21 = twl[(m + h) * q2];
+            const C2 w20 = {t20.x, t20.y}, w21 = {t21.x, t21.y};
+            bfly(x[0], x[2], w20);
+            bfly(x[1], x[3], w21);
+            bfly(x[4], x[6], w20);
+            bfly(x[5], x[7], w21);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float2 t3 = twl[(m + k * h) * q3];
+                bfly(x[k], x[k + 4], {t3.x, t3.y});
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) st(buf, i0 + k * h, S, s, x[k]);
         }
         __syncthreads();
     }
