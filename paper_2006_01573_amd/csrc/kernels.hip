@@ -353,7 +353,7 @@ __global__ void __launch_bounds__(64 * Win<B>::MAXW) k_forward(const int4 *__res
         int k = wv;
         int4 rec0 = record(list, k, stride);
         int4 rec1 = record(list, k + nw, stride);
-                const int4 m0 = meta[3 * unit], m1 = meta[3 * unit + 1], m2 = meta[3 * unit + 2];
+        const int4 m0 = meta[3 * unit], m1 = meta[3 * unit + 1], m2 = meta[3 * unit + 2];
         const Geo geo{m1.x, m1.y, m1.z, m1.w};
         const int r0 = m0.x, c0 = m0.y;
         const int r = r0 + lane;
@@ -375,8 +375,9 @@ __global__ void __launch_bounds__(64 * Win<B>::MAXW) k_forward(const int4 *__res
 #pragma unroll
             for (int q = 0; q < 4; ++q) acc[a][q] = 0.0f;
 
-        // two windows in flight: pa holds item k, pb item k + nw; while item k
-        // is computed, item k + 2nw is fetched into the buffer item k came from
+        // one window in flight: once item k's window is in LDS, the window of
+        // the wave's next item (k + nw) is fetched into registers while item k
+        // is correlated; the work records run one item further ahead
         Pending<B> pa;
         if (rec0.w >= 0) load_forward<B>(pa, f, box_wf, geo, rec0, lane);
         while (rec0.w >= 0) {
