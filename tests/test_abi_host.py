@@ -275,3 +275,15 @@ def test_fourier_rejects_host_only_plans(lib):
     st = lib.ctis_fourier_create(ctypes.byref(h), p._handle)
     assert st == 1 and not h.value
     assert b"host-only" in lib.ctis_last_error()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The measurement covers one GPU; asking for more exits with a message
+    before anything touches a device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
+    assert r.stdout == ""
