@@ -51,6 +51,11 @@ EDGE = [
     ("clustered", W.Geometry(16, 8, 2, 64, 32), 12, True, True),
     ("signed", W.Geometry(7, 5, 5, 32, 32), 9, False, False),
     ("a=gamma", W.Geometry(16, 3, 2, 16, 16), 5, False, True),
+    # transform lengths 4, 8 and 512 x 256: the radix-4-only, single radix-8
+    # and radix-4 + two radix-8 stage schedules
+    ("n=16", W.Geometry(3, 2, 3, 4, 4), 5, False, True),
+    ("n=64", W.Geometry(5, 7, 2, 8, 8), 5, False, True),
+    ("n=2^17", W.Geometry(9, 6, 3, 512, 256), 5, True, True),
 ]
 
 
