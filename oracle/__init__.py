@@ -28,6 +28,9 @@ Each function cites the passage of the paper it follows:
   * ``unrolled_grad`` -- the same through K unrolled EM steps: the steps run
                         forward keeping every iterate, then their derivatives
                         are applied last to first.
+  * ``em_float32_probe`` -- NOT an oracle: the same EM steps in float storage
+                        and float accumulation, to estimate how much of a
+                        tolerance float rounding alone takes after K steps.
 """
 from __future__ import annotations
 
@@ -115,6 +118,9 @@ def _load():
         L.oracle_export_cal.restype = None
         L.oracle_em_vjp.argtypes = [P, f64p, f64p, f64p, f64p, ctypes.c_int64, P, P, P]
         L.oracle_em_vjp.restype = ci
+        f32p = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
+        L.oracle_em_f32.argtypes = [P, f32p, f32p, ci]
+        L.oracle_em_f32.restype = ci
         _lib = L
         return L
 
@@ -257,6 +263,21 @@ class Oracle:
         _check(st)
         if trace:
             return f, tr[: 2 * iters].reshape(iters, 2)
+        return f
+
+    def em_float32_probe(self, g, iters: int, f0=None) -> np.ndarray:
+        """The FP32 drift probe (not the oracle): ``iters`` EM iterations with
+        float storage and float accumulation in the explicit H's row / column
+        order.  Its distance from ``em`` estimates the float rounding floor."""
+        self._need_h()
+        g = np.ascontiguousarray(np.asarray(g, dtype=np.float32).reshape(-1))
+        if g.size != self.n:
+            raise OracleError("g must have n entries")
+        f = (np.ones(self.m, np.float32) if f0 is None
+             else np.array(np.asarray(f0, dtype=np.float32).reshape(-1), copy=True))
+        if f.size != self.m:
+            raise OracleError("f0 must have m entries")
+        _check(self._L.oracle_em_f32(self._h, g, f, int(iters)))
         return f
 
     def diagnostics(self, g, f):

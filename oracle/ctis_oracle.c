@@ -454,3 +454,55 @@ int oracle_em_vjp(const oracle_t *o, const double *g, const double *f, const dou
     free(ghat); free(u); free(Hb); free(e); free(zeta); free(b); free(hbar); free(Hte);
     return OR_OK;
 }
+
+/*
+ * O8, the FP32 drift probe -- NOT the oracle.  The same EM iteration as
+ * oracle_em (Sec. 2 eq. (em), in the order of the Sec. 3 algorithm) with
+ * float storage and float accumulation: the assembled H's values rounded to
+ * float, products summed in float along each row (forward) and each column
+ * (adjoint) of H.  Its distance from oracle_em shows how much of a tolerance
+ * float rounding alone uses after K iterations; a GPU sums the same terms in
+ * another order, so it is an estimate of the floor, not a bound.
+ * g[n] and f[m] are float; f is updated in place.
+ */
+int oracle_em_f32(const oracle_t *o, const float *g, float *f, int iters) {
+    if (!o->rowptr || iters < 0) return OR_E_ARG;
+    for (int64_t t = 0; t < o->cptr[o->w]; ++t)
+        if (o->cval[t] < 0.0) return OR_E_NEGATIVE;
+    const int64_t n = o->n, m = o->m, nnz = o->colptr[o->m];
+    float *rv = (float *)malloc(sizeof(float) * (size_t)(nnz > 0 ? nnz : 1));
+    float *cv = (float *)malloc(sizeof(float) * (size_t)(nnz > 0 ? nnz : 1));
+    float *h = (float *)malloc(sizeof(float) * (size_t)m);
+    float *ghat = (float *)malloc(sizeof(float) * (size_t)n);
+    float *u = (float *)malloc(sizeof(float) * (size_t)n);
+    float *zeta = (float *)malloc(sizeof(float) * (size_t)m);
+    if (!rv || !cv || !h || !ghat || !u || !zeta) {
+        free(rv); free(cv); free(h); free(ghat); free(u); free(zeta);
+        return OR_E_NOMEM;
+    }
+    int nt = set_threads(o);
+#pragma omp parallel for schedule(static) num_threads(nt)
+    for (int64_t k = 0; k < nnz; ++k) {
+        rv[k] = (float)o->rval[k];
+        cv[k] = (float)o->val[k];
+    }
+    for (int64_t j = 0; j < m; ++j) h[j] = (float)o->h[j];
+    for (int it = 0; it < iters; ++it) {
+#pragma omp parallel for schedule(static) num_threads(nt)
+        for (int64_t i = 0; i < n; ++i) {
+            float acc = 0.0f;
+            for (int64_t k = o->rowptr[i]; k < o->rowptr[i + 1]; ++k) acc += rv[k] * f[o->colidx[k]];
+            ghat[i] = acc;
+            u[i] = acc > 0.0f ? g[i] / acc : 0.0f;
+        }
+#pragma omp parallel for schedule(static) num_threads(nt)
+        for (int64_t j = 0; j < m; ++j) {
+            float acc = 0.0f;
+            for (int64_t k = o->colptr[j]; k < o->colptr[j + 1]; ++k) acc += cv[k] * u[o->rowidx[k]];
+            zeta[j] = acc;
+        }
+        for (int64_t j = 0; j < m; ++j) f[j] = h[j] != 0.0f ? (f[j] * zeta[j]) / h[j] : 0.0f;
+    }
+    free(rv); free(cv); free(h); free(ghat); free(u); free(zeta);
+    return OR_OK;
+}

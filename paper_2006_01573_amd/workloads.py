@@ -178,13 +178,13 @@ def make_ftrue(geo: Geometry, rng: np.random.Generator) -> np.ndarray:
     return spec * mask[None, :, :]
 
 
-def add_noise(clean: np.ndarray, mode: str, photons: float,
-              rng: np.random.Generator) -> np.ndarray:
-    """Poisson noise on a clean FPA image.
+def noise_counts(clean: np.ndarray, mode: str, photons: float,
+                 rng: np.random.Generator):
+    """Poisson photon counts on a clean FPA image and their scale.
 
-    mode "scale": g = Poisson(photons * clean) / photons.
-    mode "peak":  s = photons / max(clean); g = Poisson(s * clean) / s.
-    Returns float32.
+    mode "scale": counts = Poisson(photons * clean), s = photons.
+    mode "peak":  s = photons / max(clean); counts = Poisson(s * clean).
+    Returns (counts int64, s); the frame is ``frame_from_counts(counts, s)``.
     """
     clean = np.asarray(clean, dtype=np.float64)
     if np.any(clean < 0):
@@ -196,7 +196,20 @@ def add_noise(clean: np.ndarray, mode: str, photons: float,
         s = photons / peak if peak > 0 else 1.0
     else:
         raise ValueError(mode)
-    return (rng.poisson(s * clean) / s).astype(np.float32)
+    return rng.poisson(s * clean), s
+
+
+def frame_from_counts(counts: np.ndarray, s: float) -> np.ndarray:
+    """g = counts / s, float32."""
+    return (np.asarray(counts, dtype=np.float64) / s).astype(np.float32)
+
+
+def add_noise(clean: np.ndarray, mode: str, photons: float,
+              rng: np.random.Generator) -> np.ndarray:
+    """Poisson noise on a clean FPA image: g = Poisson(s * clean) / s (float32),
+    s as in ``noise_counts``."""
+    counts, s = noise_counts(clean, mode, photons, rng)
+    return frame_from_counts(counts, s)
 
 
 @dataclasses.dataclass

@@ -68,46 +68,52 @@ def test_uneven_batch_against_oracle(torch, ctis, oracle_mod):
 
 @pytest.fixture(scope="module")
 def c4(torch, ctis, oracle_mod):
+    """The 64 uneven frames of the batched workload, each with its frame made
+    from the oracle's H f_true and its expected EM result from the oracle
+    (one frame at a time, so that at most one explicit H is alive)."""
     cfgs = W.batched_configs(64)
     cases = [W.make_case(4, frame=k, cfg=c) for k, c in enumerate(cfgs)]
     plans = [ctis.Plan.from_case(c) for c in cases]
-    check = [0, 17, 63]
-    orc = {k: oracle_mod.Oracle.from_case(cases[k]) for k in check}
-    images = []
-    for k, (c, p) in enumerate(zip(cases, plans)):
-        if k in orc:
-            clean = orc[k].forward(c.f_true.ravel())
-        else:
-            clean = p.forward(torch.from_numpy(c.f_true.astype(np.float32)).cuda()).double().cpu().numpy()
-        images.append(c.noisy(clean))
-    return cfgs, cases, plans, orc, images
-
-
-def test_c4_batch_matches_single_frames_and_oracle(torch, ctis, c4):
-    cfgs, cases, plans, orc, images = c4
     K = cfgs[0].iters
-    log(f"c4: {len(plans)} frames, K={K}")
+    images, expected = [], []
+    for k, c in enumerate(cases):
+        o = oracle_mod.Oracle.from_case(c)
+        images.append(c.noisy(o.forward(c.f_true.astype(np.float32).ravel())))
+        expected.append(o.em(images[-1], K))
+        o.close()
+    log(f"c4: oracle results for {len(cases)} frames, K={K}")
+    return cfgs, cases, plans, images, expected
+
+
+def test_c4_batch_matches_oracle_every_frame(torch, ctis, c4):
+    """All 64 frames of the batched solve (one launch per kernel per
+    iteration, 50 iterations) against their own FP64 oracle solves, and
+    against the single-frame path."""
+    cfgs, cases, plans, images, expected = c4
+    K = cfgs[0].iters
     b = ctis.Batch(plans)
     g_all = b.pack_g(images)
     f_all = b.em(g_all, K).cpu().numpy()
+    assert np.all(f_all >= 0)
+    errs = []
+    for k in range(len(plans)):
+        e = rel_l2(f_all[b.f_offsets[k]:b.f_offsets[k + 1]], expected[k])
+        errs.append(e)
+        assert e <= EM_TOL, f"frame {k} ({cfgs[k].name}) rel-L2 {e:.3e}"
+    log(f"c4 vs oracle: worst rel-L2 {max(errs):.2e} (frame {int(np.argmax(errs))}), median {np.median(errs):.2e}")
     worst = 0.0
     for k, p in enumerate(plans):
         single = p.em(torch.from_numpy(images[k]).cuda(), K).cpu().numpy().ravel()
         worst = max(worst, rel_l2(f_all[b.f_offsets[k]:b.f_offsets[k + 1]], single))
     log(f"c4 batch vs single-frame worst rel-L2 {worst:.2e}")
     assert worst <= 1e-5
-    for k, o in orc.items():
-        e = rel_l2(f_all[b.f_offsets[k]:b.f_offsets[k + 1]], o.em(images[k], K))
-        log(f"c4 frame {k} vs oracle rel-L2 {e:.2e}")
-        assert e <= EM_TOL
-    assert np.all(f_all >= 0)
 
 
 def test_batch_em_in_a_hip_graph(torch, ctis, c4):
     """The batched EM loop captured in a HIP graph and replayed several times,
     with eager work and synchronisations in between, reproduces the eager
     result every time."""
-    cfgs, cases, plans, orc, images = c4
+    cfgs, cases, plans, images, _ = c4
     b = ctis.Batch(plans[:16])
     g_all = b.pack_g(images[:16])
     ws = b.workspace()

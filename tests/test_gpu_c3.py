@@ -1,0 +1,138 @@
+"""GPU parity at the large single-frame workload (a = alpha = 128, w = 64,
+1024 x 1024 FPA, 5 x 5 orders of 5 x 5 blobs; 200 EM iterations), the
+configuration the benchmark times, against expected values that the FP64
+oracle wrote (tests/golden/make_c3_expected.py: the explicit H has 655 M
+nonzeros, too large to assemble inside a test).
+
+Every vector is compared whole, element by element: the forward projection
+of f_true and the back projection of the frame at relative L2 <= 1e-5, the EM
+iterates after 100 and 200 iterations (Sec. 2 eq. (em), Sec. 3 algorithm)
+at <= 1e-4.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2006_01573_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLDEN = os.path.join(HERE, "golden", "c3_expected.npz")
+PROJ_TOL = 1e-5
+EM_TOL = 1e-4
+
+
+def rel_l2(x, ref):
+    x = np.asarray(x, np.float64).ravel()
+    ref = np.asarray(ref, np.float64).ravel()
+    return float(np.linalg.norm(x - ref) / np.linalg.norm(ref))
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU tests need a visible MI355X"
+    return _t
+
+
+@pytest.fixture(scope="module")
+def c3(torch):
+    sys.path.insert(0, os.path.join(HERE, "golden"))
+    from make_c3_expected import inputs_sha
+    from paper_2006_01573_amd import ctis
+    exp = dict(np.load(GOLDEN, allow_pickle=False))
+    case = W.make_case(3)
+    assert str(exp["inputs_sha"]) == inputs_sha(case), \
+        "the seeded generators changed: rerun tests/golden/make_c3_expected.py"
+    g = W.frame_from_counts(exp["counts"], float(exp["scale"]))
+    log(f"c3: plan ({case.cfg.name})")
+    plan = ctis.Plan.from_case(case)
+    return case, plan, exp, g
+
+
+def test_c3_full_projections(torch, c3):
+    case, plan, exp, g = c3
+    f = torch.from_numpy(case.f_true.astype(np.float32)).cuda()
+    hf = plan.forward(f).cpu().numpy().ravel()
+    e = rel_l2(hf, exp["hf"])
+    log(f"c3 forward rel-L2 {e:.3e}")
+    assert e <= PROJ_TOL
+    # pixels no voxel reaches are exactly zero on both sides
+    assert not np.any(hf[exp["hf"] == 0])
+    z = plan.adjoint(torch.from_numpy(g).cuda()).cpu().numpy().ravel()
+    e = rel_l2(z, exp["htg"])
+    log(f"c3 adjoint rel-L2 {e:.3e}")
+    assert e <= PROJ_TOL
+
+
+def test_c3_em_200_iterations(torch, c3):
+    """The whole solve from all ones, in the kernels and launch configuration
+    the benchmark times; the float32 drift probe's distance from the oracle
+    (float rounding alone) is logged beside the GPU's."""
+    case, plan, exp, g = c3
+    gd = torch.from_numpy(g).cuda()
+    f = torch.ones(plan.shape_f, device="cuda")
+    ws = plan.workspace()
+    plan.em(gd, 100, f=f, workspace=ws)
+    e100 = rel_l2(f.cpu().numpy(), exp["f100"])
+    plan.em(gd, 100, f=f, workspace=ws)
+    fk = f.cpu().numpy()
+    e200 = rel_l2(fk, exp["f200"])
+    log(f"c3 EM rel-L2 {e100:.3e} at K=100, {e200:.3e} at K=200 "
+        f"(float32 probe vs oracle: {float(exp['drift100']):.3e}, {float(exp['drift200']):.3e})")
+    assert np.all(np.isfinite(fk)) and np.all(fk >= 0)
+    assert e100 <= EM_TOL
+    assert e200 <= EM_TOL
+
+
+def test_c3_em_invariants(torch, c3):
+    """Properties of the solve at every iteration: nonnegative finite
+    iterates; the EM flux identity sum_j h_j f^(k+1)_j = sum of g over the
+    pixels where H f^(k) > 0; and a Poisson log-likelihood that does not
+    decrease (Shepp-Vardi EM, cited in Sec. 2); the final flux and
+    log-likelihood against the oracle's."""
+    case, plan, exp, g = c3
+    geo = case.geometry
+    K = case.cfg.iters
+    gd = torch.from_numpy(g).cuda()
+    g64 = gd.double().reshape(-1)
+    h = torch.from_numpy(np.repeat(plan.lambda_sums().astype(np.float64), geo.ell)).cuda()
+    f = torch.ones(plan.shape_f, device="cuda")
+    ws = plan.workspace()
+
+    def loglik(x):
+        ghat = plan.forward(x).double().reshape(-1)
+        pos = g64 > 0
+        if bool(((ghat <= 0) & pos).any()):
+            return -float("inf"), ghat
+        safe = torch.where(pos, ghat, torch.ones_like(ghat))
+        return float(torch.where(pos, g64 * torch.log(safe), 0.0).sum() - ghat.sum()), ghat
+
+    marks = {0, 1, 2, 5, 10, 25, 50, 100, 150, K - 1}
+    ll = []
+    for k in range(K):
+        if k in marks:
+            L, ghat = loglik(f)
+            ll.append(L)
+            if k == K - 1:
+                target = float(g64[ghat > 0].sum())
+        plan.em(gd, 1, f=f, workspace=ws)
+    L_end, _ = loglik(f)
+    ll.append(L_end)
+    flux = float((h * f.double().reshape(-1)).sum())
+    log(f"c3: flux {flux:.6e} vs {target:.6e} (oracle {float(exp['flux200']):.6e}); "
+        f"loglik {ll[0]:.6e} -> {ll[-1]:.6e} (oracle {float(exp['loglik200']):.6e})")
+    assert torch.isfinite(f).all() and bool((f >= 0).all())
+    assert abs(flux - target) <= 1e-5 * target
+    assert abs(flux - float(exp["flux200"])) <= 1e-5 * abs(float(exp["flux200"]))
+    assert abs(L_end - float(exp["loglik200"])) <= 1e-5 * abs(float(exp["loglik200"]))
+    for a, b in zip(ll, ll[1:]):
+        assert b >= a - 1e-9 * abs(a)

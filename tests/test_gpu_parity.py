@@ -6,6 +6,8 @@ the same float32 values on both sides; the oracle promotes them to double.
 """
 import sys
 
+import zlib
+
 import numpy as np
 import pytest
 
@@ -90,7 +92,7 @@ EDGE = [
 
 @pytest.mark.parametrize("name,geo,nnz,clustered", EDGE, ids=[e[0] for e in EDGE])
 def test_projection_parity_edge_cases(torch, ctis, oracle_mod, name, geo, nnz, clustered):
-    rng = np.random.default_rng(abs(hash(name)) % 99991)
+    rng = np.random.default_rng(zlib.crc32(name.encode()) % 99991)
     ptr, idx, val = W.random_kernels(geo, nnz, rng, clustered=clustered, nonneg=False)
     check_projections(torch, ctis, oracle_mod, geo, ptr, idx, val, seed=1, signed=True)
 
@@ -336,51 +338,6 @@ def test_c3_sampled_projections(torch, ctis, oracle_mod):
     z_gpu = p.adjoint(torch.from_numpy(r).cuda()).cpu().numpy().ravel()
     cols = rng.choice(geo.m, 3000, replace=False)
     assert rel_l2(z_gpu[cols], ok.adjoint_cols(r, cols)) <= PROJ_TOL
-
-
-def test_c3_full_em_properties(torch, ctis):
-    """The full c3 solve (a = alpha = 128, w = 64, FPA 1024^2, 200 iterations:
-    the benchmark's workload and kernels), checked through properties that
-    hold at any size: nonnegative finite iterates; the EM flux identity
-    sum_j h_j f^(K+1)_j = sum of g over the pixels where H f^(K) > 0; and a
-    Poisson log-likelihood that does not decrease along the iterations
-    (Shepp-Vardi EM, cited in Sec. 2)."""
-    case = W.make_case(3)
-    geo = case.geometry
-    K = case.cfg.iters
-    log(f"c3 full EM properties, K={K}")
-    p = ctis.Plan.from_case(case)
-    clean = p.forward(torch.from_numpy(case.f_true.astype(np.float32)).cuda()).double().cpu().numpy()
-    g = torch.from_numpy(case.noisy(clean)).cuda()
-    gd = g.double().reshape(-1)
-    h = torch.from_numpy(np.repeat(p.lambda_sums().astype(np.float64), geo.ell)).cuda()
-    f = torch.ones(p.shape_f, device="cuda")
-    ws = p.workspace()
-
-    def loglik(x):
-        ghat = p.forward(x).double().reshape(-1)
-        pos = gd > 0
-        if bool(((ghat <= 0) & pos).any()):
-            return -float("inf")
-        return float(torch.where(pos, gd * torch.log(torch.where(pos, ghat, torch.ones_like(ghat))), 0.0).sum()
-                     - ghat.sum())
-
-    marks = {0, 1, 2, 5, 10, 25, 50, 100, 150, K - 1}
-    ll = []
-    for k in range(K):
-        if k in marks:
-            ll.append(loglik(f))
-        if k == K - 1:
-            ghat_last = p.forward(f).double().reshape(-1)
-        p.em(g, 1, f=f, workspace=ws)
-    ll.append(loglik(f))
-    assert torch.isfinite(f).all() and bool((f >= 0).all())
-    flux = float((h * f.double().reshape(-1)).sum())
-    target = float(gd[ghat_last > 0].sum())
-    log(f"c3: flux {flux:.6e} vs {target:.6e}; loglik {ll[0]:.6e} -> {ll[-1]:.6e}")
-    assert abs(flux - target) <= 1e-5 * target
-    for a, b in zip(ll, ll[1:]):
-        assert b >= a - 1e-9 * abs(a)
 
 
 def test_em_halves_compose_to_em_iterate(torch, c1):
