@@ -10,7 +10,10 @@ the roofline position of the dominant kernel (its average duration over a HIP
 graph of back-to-back launches, HIP events around the replays), and the FP64
 oracle's rate on the host cores over a bounded sample of the same workload.
 
-    python bench.py [--steps K] [--warmup W] [--config 2]
+    python bench.py [--steps K] [--warmup W] [--config 3]
+
+The default workload is the largest single-frame configuration (a = alpha =
+128, w = 64, 1024 x 1024 FPA, 5 x 5 orders of 5 x 5 blobs, 200 iterations).
 """
 from __future__ import annotations
 
@@ -60,27 +63,53 @@ def measured_traffic(config_id: int, kernel: str):
     return float(e["bytes_per_launch"])
 
 
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(case, g_host: np.ndarray, iters_per_step: int, seconds: float):
-    """The FP64 oracle (explicit H, OpenMP) on the host cores: EM iterations
-    from all ones in chunks until `seconds` have passed.  Assembly excluded."""
+    """The FP64 oracle (explicit H, OpenMP) on the host: EM iterations from
+    all ones until `seconds` have passed, on all host cores and then on one
+    core.  Assembly of the explicit H is excluded (and timed separately)."""
     import oracle
     progress("cpu baseline: assembling the explicit H")
-    o = oracle.Oracle.from_case(case)
-    chunk = 10
-    done = 0
-    f = None
     t0 = time.perf_counter()
-    while True:
-        f = o.em(g_host, chunk, f0=f)
-        done += chunk
-        el = time.perf_counter() - t0
-        if el >= seconds or done >= 100_000:
-            break
+    o = oracle.Oracle.from_case(case)
+    t_asm = time.perf_counter() - t0
+
+    def sample(budget):
+        done, f = 0, None
+        t1 = time.perf_counter()
+        while True:
+            f = o.em(g_host, 1, f0=f)
+            done += 1
+            el = time.perf_counter() - t1
+            if el >= budget or done >= 100_000:
+                return done, el
+
+    all_threads = o.threads
+    progress(f"cpu baseline: oracle EM on {all_threads} threads")
+    done, el = sample(seconds)
     rate = done / el
-    return {"value": rate, "unit": "EM iterations/s", "cores": o.threads, "kind": "oracle",
+    o.set_threads(1)
+    progress("cpu baseline: oracle EM on 1 thread")
+    done1, el1 = sample(seconds)
+    o.close()
+    rate1 = done1 / el1
+    return {"value": rate, "unit": "EM iterations/s", "cores": all_threads, "kind": "oracle",
             "sample": f"{done} EM iterations of the same frame from all ones ({el:.1f} s, FP64 explicit "
-                      f"sparse H, assembly excluded); one step of {iters_per_step} iterations would take "
-                      f"{iters_per_step / rate:.3f} s"}
+                      f"sparse H, assembly of {t_asm:.1f} s excluded); one step of {iters_per_step} "
+                      f"iterations would take {iters_per_step / rate:.2f} s",
+            "host_cpu": host_cpu_model(),
+            "one_core": {"value": rate1, "unit": "EM iterations/s", "cores": 1,
+                         "sample": f"{done1} EM iterations ({el1:.1f} s)"}}
 
 
 def main(argv=None) -> int:
@@ -88,7 +117,7 @@ def main(argv=None) -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5],
+    ap.add_argument("--config", type=int, default=3, choices=[1, 2, 3, 4, 5],
                     help="1-3: one frame; 4: 64 uneven frames, batched vs sequential; "
                          "5: gradients of 10 unrolled EM iterations, 8 frames sharing one plan")
     ap.add_argument("--path", choices=["gather", "fourier"], default="gather",

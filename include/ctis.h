@@ -316,8 +316,12 @@ ctis_status ctis_em_vjp(const ctis_plan *plan, const float *g, const float *f, c
  * same positions, same box grouping): values DEVICE float[n_entries] in the
  * plan's input order, duplicates of a position summed (in double) as at
  * creation.  Rewrites the plan's box values and column sums h on `stream`;
- * later calls on the stream see them.  The sign check of EM keeps the sign of
- * the values given at creation: values made negative here are the caller's
+ * later calls on the stream see them.  The host-side readers of the values
+ * (ctis_plan_get_info, ctis_plan_lambda_sums, ctis_plan_export_boxes,
+ * ctis_batch_create, ctis_fourier_create) synchronise the device once after a
+ * set_values, re-read the values and the sign flag from the device, and then
+ * see the new values.  Until such a read, the sign check of EM keeps the sign
+ * of the values last read: negative values set here are the caller's
  * contract violation.  Errors: CTIS_E_ARG (also if the plan dropped an entry:
  * use CTIS_PLAN_KEEP_ZEROS), CTIS_E_HIP.  Batches hold their own copy of their
  * plans' values, taken at ctis_batch_create (see ctis_batch_set_values).
@@ -355,7 +359,8 @@ ctis_status ctis_batch_plan_entries(const ctis_batch *batch, int32_t frame, int6
  * ctis_fourier_create computes the spectra e_t = F(c_{2t} - i c_{2t+1}) of the
  * plan's calibration on the current device (it synchronises the device before
  * returning) and keeps a pointer to the plan, which must outlive it.  The
- * spectra and the sums h_s are those of the plan's values at creation: after
+ * spectra and the sums h_s are those of the plan's values at creation
+ * (including values set by ctis_plan_set_values before it): after a later
  * ctis_plan_set_values, create the Fourier plan again.  The
  * spectra take info.spectra_bytes of device memory; the calls take a
  * workspace of info.workspace_bytes (256-byte aligned).  Layouts of f, g, r, z

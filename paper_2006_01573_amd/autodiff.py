@@ -34,9 +34,9 @@ class _Op:
             self.n = int(op.g_offsets[-1])
             self.n_entries = int(op.info["n_entries"])
         else:
-            self.m = op.info.m
-            self.n = op.info.n
-            self.n_entries = op.info.n_entries
+            self.m = op.sizes.m
+            self.n = op.sizes.n
+            self.n_entries = op.sizes.n_entries
         self.device = op.device
 
     def workspace(self):

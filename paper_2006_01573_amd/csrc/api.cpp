@@ -1,5 +1,6 @@
 // C ABI of libctis: argument checking, plan lifetime and the stream-ordered
 // drivers.  The arithmetic is in kernels.hip.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -48,6 +49,29 @@ ctis_status launch_status(int err, const char *what) {
 }
 
 }  // namespace
+
+ctis_status refresh_host_tables(const ctis_plan *p) {
+    if (!p->host_stale) return CTIS_OK;
+    ctis_status st = check_device(p);
+    if (st != CTIS_OK) return st;
+    // set_values may have been queued on any stream: wait for all of them
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return fail(CTIS_E_HIP, std::string("hipDeviceSynchronize: ") + hipGetErrorString(e));
+    HostTables &T = const_cast<ctis_plan *>(p)->ht;
+    const struct {
+        std::vector<float> *host;
+        const float *dev;
+    } parts[] = {{&T.box_w, p->work.box_w}, {&T.box_wf, p->work.box_wf}, {&T.h, p->work.h}};
+    for (const auto &pt : parts) {
+        if (pt.host->empty()) continue;
+        e = hipMemcpy(pt.host->data(), pt.dev, pt.host->size() * sizeof(float), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return fail(CTIS_E_HIP, std::string("hipMemcpy of plan values: ") + hipGetErrorString(e));
+    }
+    T.nonneg = std::all_of(T.box_w.begin(), T.box_w.end(), [](float v) { return v >= 0.0f; });
+    p->host_stale = false;
+    return CTIS_OK;
+}
+
 }  // namespace ctis
 
 using namespace ctis;
@@ -174,6 +198,8 @@ void ctis_plan_destroy(ctis_plan *p) {
 
 ctis_status ctis_plan_get_info(const ctis_plan *p, ctis_plan_info *info) {
     if (!p || !info) return fail(CTIS_E_ARG, "plan or info is NULL");
+    ctis_status st = refresh_host_tables(p);
+    if (st != CTIS_OK) return st;
     std::memset(info, 0, sizeof(*info));
     info->a = p->a;
     info->alpha = p->alpha;
@@ -205,12 +231,16 @@ ctis_status ctis_plan_get_info(const ctis_plan *p, ctis_plan_info *info) {
 
 ctis_status ctis_plan_lambda_sums(const ctis_plan *p, float *h_out) {
     if (!p || !h_out) return fail(CTIS_E_ARG, "plan or h_out is NULL");
+    ctis_status st = refresh_host_tables(p);
+    if (st != CTIS_OK) return st;
     std::memcpy(h_out, p->ht.h.data(), sizeof(float) * p->ht.h.size());
     return CTIS_OK;
 }
 
 ctis_status ctis_plan_export_boxes(const ctis_plan *p, int32_t *box_lambda, int32_t *box_rc, float *box_values) {
     if (!p) return fail(CTIS_E_ARG, "plan is NULL");
+    ctis_status st = refresh_host_tables(p);
+    if (st != CTIS_OK) return st;
     const auto &T = p->ht;
     if (box_lambda) std::memcpy(box_lambda, T.box_lambda.data(), T.box_lambda.size() * 4);
     if (box_rc) std::memcpy(box_rc, T.box_rc.data(), T.box_rc.size() * 4);

@@ -53,6 +53,8 @@ ctis_status ctis_batch_create(ctis_batch **out, const ctis_plan *const *plans, i
         if (p->device < 0) return fail(CTIS_E_ARG, "plan " + std::to_string(k) + " is host-only");
         if (p->device != dev) return fail(CTIS_E_ARG, "plan " + std::to_string(k) + " lives on another device");
         if (p->ht.B != plans[0]->ht.B) return fail(CTIS_E_ARG, "all plans of a batch need the same box side B");
+        const ctis_status rs = refresh_host_tables(p);
+        if (rs != CTIS_OK) return rs;
         frames.push_back(FrameRef{p, fo, go, go});
         fo += p->m;
         go += p->n;

@@ -147,6 +147,10 @@ struct ctis_plan {
     int32_t device = -1;
     ctis::DevWork work;          // the plan as a batch of one frame
     size_t workspace_bytes = 0, vjp_workspace_bytes = 0;
+    // ctis_plan_set_values rewrites the device copies of the box values and
+    // column sums; the host copies in `ht` are re-read from the device by
+    // refresh_host_tables before the next host-side reader uses them
+    mutable bool host_stale = false;
 };
 
 struct ctis_batch {
@@ -165,6 +169,11 @@ namespace ctis {
 
 void set_error(const std::string &msg);
 ctis_status fail(ctis_status st, const std::string &msg);
+
+// Bring the host copies of a plan's box values, column sums and sign flag up
+// to date after ctis_plan_set_values (synchronises the device once; a no-op
+// otherwise).  api.cpp.
+ctis_status refresh_host_tables(const ctis_plan *p);
 
 // host plan builder (plan.cpp)
 ctis_status build_host_tables(ctis_plan *p, const int64_t *lambda_ptr, const int32_t *fpa_index,

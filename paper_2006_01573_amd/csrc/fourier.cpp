@@ -157,6 +157,8 @@ ctis_status ctis_fourier_create(ctis_fourier **out, const ctis_plan *p) {
     int dev = -1;
     hipError_t he = hipGetDevice(&dev);
     if (he != hipSuccess || dev != p->device) return fail(CTIS_E_ARG, "current HIP device differs from the plan's");
+    const ctis_status rs = refresh_host_tables(p);
+    if (rs != CTIS_OK) return rs;
     ctis_fourier *F = new (std::nothrow) ctis_fourier();
     if (!F) return fail(CTIS_E_NOMEM, "Fourier plan allocation");
     F->plan = p;

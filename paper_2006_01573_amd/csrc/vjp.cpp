@@ -127,7 +127,9 @@ ctis_status ctis_plan_set_values(ctis_plan *p, const float *values, void *stream
     if (p->ht.n_in > 0 && (!values || !aligned4(values))) return fail(CTIS_E_ARG, "values must be non-NULL and aligned");
     ctis_status st = on_device(p->device);
     if (st != CTIS_OK || p->w == 0) return st;
-    return launched(launch_set_values(p->work, values, 0, 0, p->w, stream), "set values launch");
+    st = launched(launch_set_values(p->work, values, 0, 0, p->w, stream), "set values launch");
+    if (st == CTIS_OK) p->host_stale = true;
+    return st;
 }
 
 ctis_status ctis_batch_set_values(ctis_batch *b, int32_t frame, const float *values, void *stream) {

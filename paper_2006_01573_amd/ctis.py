@@ -206,6 +206,40 @@ def _stream(torch, device) -> ctypes.c_void_p:
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
+def need_tensor(x, numel: int, name: str, device):
+    """Check a tensor the library will read or write through its pointer: a
+    torch tensor, float32, contiguous, on ``device``, with ``numel`` elements.
+    The C side cannot check sizes, so every tensor argument passes here before
+    any launch; raises ValueError otherwise."""
+    torch = _torch()
+    if not isinstance(x, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor, got {type(x).__name__}")
+    if x.dtype != torch.float32:
+        raise ValueError(f"{name} must be float32, got {x.dtype}")
+    if x.device != torch.device(device):
+        raise ValueError(f"{name} must be on {device}, got {x.device}")
+    if not x.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if x.numel() != int(numel):
+        raise ValueError(f"{name} must have {int(numel)} elements, got {x.numel()}")
+    return x
+
+
+def need_workspace(ws, nbytes: int, name: str, device):
+    """A workspace tensor: contiguous, on ``device``, at least ``nbytes`` bytes."""
+    torch = _torch()
+    if not isinstance(ws, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor, got {type(ws).__name__}")
+    if ws.device != torch.device(device):
+        raise ValueError(f"{name} must be on {device}, got {ws.device}")
+    if not ws.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    have = ws.numel() * ws.element_size()
+    if have < int(nbytes):
+        raise ValueError(f"{name} needs {int(nbytes)} bytes, got {have}")
+    return ctypes.c_void_p(ws.data_ptr()), have
+
+
 class Plan:
     """One geometry and one set of calibration images, on the current GPU.
 
@@ -239,9 +273,13 @@ class Plan:
                                       _ptr(ptr), _ptr(idx), _ptr(val), flags)
         _check(self._L, st, "ctis_plan_create")
         self._handle = h
-        self.info = self._info()
-        self.shape_f = (self.info.w, self.info.alpha, self.info.a)
-        self.shape_g = (self.info.xi, self.info.gamma)
+        self._info_cache = self._info()
+        self._info_stale = False
+        # sizes and layout never change after creation; `info` re-reads the
+        # sign flag after set_values (which synchronises the device)
+        self.sizes = self._info_cache
+        self.shape_f = (self.sizes.w, self.sizes.alpha, self.sizes.a)
+        self.shape_g = (self.sizes.xi, self.sizes.gamma)
 
     @classmethod
     def from_case(cls, case, **kw):
@@ -269,6 +307,15 @@ class Plan:
         self.close()
 
     # -- inspection -----------------------------------------------------------------
+    @property
+    def info(self) -> PlanInfo:
+        """Sizes and layout decisions (re-read after set_values, which can
+        change the sign flag)."""
+        if self._info_stale:
+            self._info_cache = self._info()
+            self._info_stale = False
+        return self._info_cache
+
     def _info(self) -> PlanInfo:
         inf = _Info()
         _check(self._L, self._L.ctis_plan_get_info(self._handle, ctypes.byref(inf)), "ctis_plan_get_info")
@@ -278,13 +325,13 @@ class Plan:
         return PlanInfo(**d)
 
     def lambda_sums(self) -> np.ndarray:
-        out = np.empty(self.info.w, np.float32)
+        out = np.empty(self.sizes.w, np.float32)
         _check(self._L, self._L.ctis_plan_lambda_sums(self._handle, _ptr(out)), "ctis_plan_lambda_sums")
         return out
 
     def boxes(self):
         """(box_lambda[nb], box_rc[nb, 2], box_values[nb, B, B] indexed [k, dc, dr])."""
-        nb, B = self.info.n_boxes, self.info.box
+        nb, B = self.sizes.n_boxes, self.sizes.box
         lam = np.empty(nb, np.int32)
         rc = np.empty(2 * nb, np.int32)
         vals = np.empty(nb * B * B, np.float32)
@@ -294,8 +341,8 @@ class Plan:
 
     def worklist(self):
         """(tile_ptr[n_tiles+1], item_box[n_items])."""
-        tp = np.empty(self.info.n_tiles + 1, np.int32)
-        ib = np.empty(self.info.n_items, np.int32)
+        tp = np.empty(self.sizes.n_tiles + 1, np.int32)
+        ib = np.empty(self.sizes.n_items, np.int32)
         _check(self._L, self._L.ctis_plan_export_worklist(self._handle, _ptr(tp), _ptr(ib)),
                "ctis_plan_export_worklist")
         return tp, ib
@@ -320,9 +367,10 @@ class Plan:
         """g = H f.  f: (w, alpha, a) float32 on the plan's GPU -> (xi, gamma)."""
         self._need_device()
         torch = _torch()
-        f = self._dev_tensor(f, self.info.m, "f")
+        f = self._dev_tensor(f, self.sizes.m, "f")
         if out is None:
             out = torch.empty(self.shape_g, dtype=torch.float32, device=self.device)
+        need_tensor(out, self.sizes.n, "out", self.device)
         st = self._L.ctis_forward(self._handle, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                   _stream(torch, self.device))
         _check(self._L, st, "ctis_forward")
@@ -332,9 +380,10 @@ class Plan:
         """z = H^T r.  r: (xi, gamma) float32 on the plan's GPU -> (w, alpha, a)."""
         self._need_device()
         torch = _torch()
-        r = self._dev_tensor(r, self.info.n, "r")
+        r = self._dev_tensor(r, self.sizes.n, "r")
         if out is None:
             out = torch.empty(self.shape_f, dtype=torch.float32, device=self.device)
+        need_tensor(out, self.sizes.m, "out", self.device)
         st = self._L.ctis_adjoint(self._handle, ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                   _stream(torch, self.device))
         _check(self._L, st, "ctis_adjoint")
@@ -342,27 +391,31 @@ class Plan:
 
     def workspace(self):
         torch = _torch()
-        nbytes = self.info.workspace_bytes
+        nbytes = self.sizes.workspace_bytes
         return torch.empty(max(nbytes // 4, 64), dtype=torch.float32, device=self.device)
 
-    @staticmethod
-    def _ws(workspace):
-        return ctypes.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size()
+    def _ws(self, workspace, nbytes=None):
+        return need_workspace(workspace, self.sizes.workspace_bytes if nbytes is None else nbytes, "workspace",
+                              self.device)
 
     def em_forward_ratio(self, f, g, workspace):
         """u = g / (H f) into the first n floats of the workspace (one EM half)."""
         self._need_device()
         torch = _torch()
+        need_tensor(f, self.sizes.m, "f", self.device)
+        need_tensor(g, self.sizes.n, "g", self.device)
         wp, wb = self._ws(workspace)
         st = self._L.ctis_em_forward_ratio(self._handle, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(g.data_ptr()),
                                            wp, wb, _stream(torch, self.device))
         _check(self._L, st, "ctis_em_forward_ratio")
-        return workspace[: self.info.n].view(self.shape_g)
+        return workspace[: self.sizes.n].view(self.shape_g)
 
     def em_adjoint_update(self, workspace, f_in, f_out):
         """f_out = f_in * (H^T u) / h with u from the workspace (the other EM half)."""
         self._need_device()
         torch = _torch()
+        need_tensor(f_in, self.sizes.m, "f_in", self.device)
+        need_tensor(f_out, self.sizes.m, "f_out", self.device)
         wp, wb = self._ws(workspace)
         st = self._L.ctis_em_adjoint_update(self._handle, wp, wb, ctypes.c_void_p(f_in.data_ptr()),
                                             ctypes.c_void_p(f_out.data_ptr()), _stream(torch, self.device))
@@ -376,23 +429,23 @@ class Plan:
         returned) and ``f0``/``start`` are ignored."""
         self._need_device()
         torch = _torch()
-        g = self._dev_tensor(g, self.info.n, "g")
+        g = self._dev_tensor(g, self.sizes.n, "g")
         if start not in ("ones", "adjoint"):
             raise ValueError("start must be 'ones' or 'adjoint'")
         if f is None:
             if f0 is not None:
-                f = self._dev_tensor(f0, self.info.m, "f0").clone()
+                f = self._dev_tensor(f0, self.sizes.m, "f0").clone()
             elif start == "adjoint":
                 f = self.adjoint(g)
             else:
                 f = torch.ones(self.shape_f, dtype=torch.float32, device=self.device)
-        elif not (f.is_contiguous() and f.dtype == torch.float32 and f.device == self.device):
-            raise ValueError("f must be a contiguous float32 tensor on the plan's device")
+        else:
+            need_tensor(f, self.sizes.m, "f", self.device)
         if workspace is None:
             workspace = self.workspace()
+        wp, wb = self._ws(workspace)
         st = self._L.ctis_em_iterate(self._handle, ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(f.data_ptr()),
-                                     int(iters), ctypes.c_void_p(workspace.data_ptr()),
-                                     workspace.numel() * workspace.element_size(), _stream(torch, self.device))
+                                     int(iters), wp, wb, _stream(torch, self.device))
         _check(self._L, st, "ctis_em_iterate")
         return f
 
@@ -400,17 +453,18 @@ class Plan:
     def vjp_workspace(self):
         """Workspace for em_vjp (also valid for em)."""
         torch = _torch()
-        return torch.empty(max(self.info.vjp_workspace_bytes // 4, 64), dtype=torch.float32, device=self.device)
+        return torch.empty(max(self.sizes.vjp_workspace_bytes // 4, 64), dtype=torch.float32, device=self.device)
 
     def set_values(self, values):
         """New calibration values (one per entry given at creation, device
         float32) on the same structure."""
         self._need_device()
         torch = _torch()
-        v = self._dev_tensor(values, self.info.n_entries, "values") if self.info.n_entries else None
+        v = self._dev_tensor(values, self.sizes.n_entries, "values") if self.sizes.n_entries else None
         st = self._L.ctis_plan_set_values(self._handle, ctypes.c_void_p(v.data_ptr()) if v is not None else None,
                                           _stream(torch, self.device))
         _check(self._L, st, "ctis_plan_set_values")
+        self._info_stale = True
 
     def em_vjp(self, g, f, y, df=None, dvalues=None, accumulate: bool = False, workspace=None):
         """Reverse-mode derivative of one EM iteration at input f for the
@@ -419,19 +473,18 @@ class Plan:
         ``accumulate``) dL/dv per calibration entry into it."""
         self._need_device()
         torch = _torch()
-        g = self._dev_tensor(g, self.info.n, "g")
-        f = self._dev_tensor(f, self.info.m, "f")
-        y = self._dev_tensor(y, self.info.m, "y")
+        g = self._dev_tensor(g, self.sizes.n, "g")
+        f = self._dev_tensor(f, self.sizes.m, "f")
+        y = self._dev_tensor(y, self.sizes.m, "y")
         if df is None:
             df = torch.empty(self.shape_f, dtype=torch.float32, device=self.device)
+        need_tensor(df, self.sizes.m, "df", self.device)
         if workspace is None:
             workspace = self.vjp_workspace()
-        wp, wb = self._ws(workspace)
+        wp, wb = self._ws(workspace, self.sizes.vjp_workspace_bytes)
         dvp = None
         if dvalues is not None:
-            if not (dvalues.is_contiguous() and dvalues.dtype == torch.float32
-                    and dvalues.numel() == self.info.n_entries):
-                raise ValueError("dvalues must be a contiguous float32 tensor with one element per entry")
+            need_tensor(dvalues, self.sizes.n_entries, "dvalues", self.device)
             dvp = ctypes.c_void_p(dvalues.data_ptr())
         st = self._L.ctis_em_vjp(self._handle, ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(f.data_ptr()),
                                  ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(df.data_ptr()), dvp,
@@ -464,8 +517,8 @@ class Batch:
         inf = _BatchInfo()
         _check(self._L, self._L.ctis_batch_get_info(self._handle, ctypes.byref(inf)), "ctis_batch_get_info")
         self.info = {k: getattr(inf, k) for k, _ in _BatchInfo._fields_}
-        m = np.array([p.info.m for p in self.plans], np.int64)
-        n = np.array([p.info.n for p in self.plans], np.int64)
+        m = np.array([p.sizes.m for p in self.plans], np.int64)
+        n = np.array([p.sizes.n for p in self.plans], np.int64)
         self.f_offsets = np.concatenate([[0], np.cumsum(m)])
         self.g_offsets = np.concatenate([[0], np.cumsum(n)])
 
@@ -495,10 +548,23 @@ class Batch:
         torch = _torch()
         return torch.empty(max(self.info["workspace_bytes"] // 4, 64), dtype=torch.float32, device=self.device)
 
+    @property
+    def m_total(self) -> int:
+        return int(self.f_offsets[-1])
+
+    @property
+    def n_total(self) -> int:
+        return int(self.g_offsets[-1])
+
+    def _ws(self, workspace, nbytes):
+        return need_workspace(workspace, nbytes, "workspace", self.device)
+
     def forward(self, f_all, out=None):
         torch = _torch()
+        need_tensor(f_all, self.m_total, "f_all", self.device)
         if out is None:
-            out = torch.empty(int(self.g_offsets[-1]), dtype=torch.float32, device=self.device)
+            out = torch.empty(self.n_total, dtype=torch.float32, device=self.device)
+        need_tensor(out, self.n_total, "out", self.device)
         st = self._L.ctis_batch_forward(self._handle, ctypes.c_void_p(f_all.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                         _stream(torch, self.device))
         _check(self._L, st, "ctis_batch_forward")
@@ -506,8 +572,10 @@ class Batch:
 
     def adjoint(self, r_all, out=None):
         torch = _torch()
+        need_tensor(r_all, self.n_total, "r_all", self.device)
         if out is None:
-            out = torch.empty(int(self.f_offsets[-1]), dtype=torch.float32, device=self.device)
+            out = torch.empty(self.m_total, dtype=torch.float32, device=self.device)
+        need_tensor(out, self.m_total, "out", self.device)
         st = self._L.ctis_batch_adjoint(self._handle, ctypes.c_void_p(r_all.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                         _stream(torch, self.device))
         _check(self._L, st, "ctis_batch_adjoint")
@@ -519,17 +587,19 @@ class Batch:
         torch = _torch()
         if start not in ("ones", "adjoint"):
             raise ValueError("start must be 'ones' or 'adjoint'")
+        need_tensor(g_all, self.n_total, "g_all", self.device)
         if f_all is None:
             if start == "adjoint":
                 f_all = self.adjoint(g_all)
             else:
-                f_all = torch.ones(int(self.f_offsets[-1]), dtype=torch.float32, device=self.device)
+                f_all = torch.ones(self.m_total, dtype=torch.float32, device=self.device)
+        need_tensor(f_all, self.m_total, "f_all", self.device)
         if workspace is None:
             workspace = self.workspace()
+        wp, wb = self._ws(workspace, self.info["workspace_bytes"])
         st = self._L.ctis_batch_em_iterate(self._handle, ctypes.c_void_p(g_all.data_ptr()),
-                                           ctypes.c_void_p(f_all.data_ptr()), int(iters),
-                                           ctypes.c_void_p(workspace.data_ptr()),
-                                           workspace.numel() * workspace.element_size(), _stream(torch, self.device))
+                                           ctypes.c_void_p(f_all.data_ptr()), int(iters), wp, wb,
+                                           _stream(torch, self.device))
         _check(self._L, st, "ctis_batch_em_iterate")
         return f_all
 
@@ -549,8 +619,7 @@ class Batch:
         """New values for the plan of frame k (and the frames sharing it)."""
         torch = _torch()
         v = torch.as_tensor(values, dtype=torch.float32, device=self.device).contiguous()
-        if v.numel() != self.plan_entries(k)[1]:
-            raise ValueError("values must have one element per entry of the frame's plan")
+        need_tensor(v, self.plan_entries(k)[1], "values", self.device)
         st = self._L.ctis_batch_set_values(self._handle, int(k), ctypes.c_void_p(v.data_ptr()) if v.numel() else None,
                                            _stream(torch, self.device))
         _check(self._L, st, "ctis_batch_set_values")
@@ -559,21 +628,23 @@ class Batch:
         """Batch form of Plan.em_vjp; dvalues holds the entries of the batch's
         distinct plans back to back (see plan_entries)."""
         torch = _torch()
+        need_tensor(g_all, self.n_total, "g_all", self.device)
+        need_tensor(f_all, self.m_total, "f_all", self.device)
+        need_tensor(y_all, self.m_total, "y_all", self.device)
         if df_all is None:
-            df_all = torch.empty(int(self.f_offsets[-1]), dtype=torch.float32, device=self.device)
+            df_all = torch.empty(self.m_total, dtype=torch.float32, device=self.device)
+        need_tensor(df_all, self.m_total, "df_all", self.device)
         if workspace is None:
             workspace = self.vjp_workspace()
+        wp, wb = self._ws(workspace, self.info["vjp_workspace_bytes"])
         dvp = None
         if dvalues is not None:
-            if not (dvalues.is_contiguous() and dvalues.dtype == torch.float32
-                    and dvalues.numel() == self.info["n_entries"]):
-                raise ValueError("dvalues must be a contiguous float32 tensor with n_entries elements")
+            need_tensor(dvalues, self.info["n_entries"], "dvalues", self.device)
             dvp = ctypes.c_void_p(dvalues.data_ptr())
         st = self._L.ctis_batch_em_vjp(self._handle, ctypes.c_void_p(g_all.data_ptr()),
                                        ctypes.c_void_p(f_all.data_ptr()), ctypes.c_void_p(y_all.data_ptr()),
                                        ctypes.c_void_p(df_all.data_ptr()), dvp, 1 if accumulate else 0,
-                                       ctypes.c_void_p(workspace.data_ptr()),
-                                       workspace.numel() * workspace.element_size(), _stream(torch, self.device))
+                                       wp, wb, _stream(torch, self.device))
         _check(self._L, st, "ctis_batch_em_vjp")
         return df_all
 
@@ -614,37 +685,40 @@ class Fourier:
 
     def forward(self, f, out=None, workspace=None):
         torch = _torch()
-        f = self.plan._dev_tensor(f, self.plan.info.m, "f")
+        f = self.plan._dev_tensor(f, self.plan.sizes.m, "f")
         if out is None:
             out = torch.empty(self.plan.shape_g, dtype=torch.float32, device=self.device)
+        need_tensor(out, self.plan.sizes.n, "out", self.device)
         ws = self.workspace() if workspace is None else workspace
+        wp, wb = need_workspace(ws, self.info["workspace_bytes"], "workspace", self.device)
         st = self._L.ctis_fourier_forward(self._handle, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(out.data_ptr()),
-                                          ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
-                                          _stream(torch, self.device))
+                                          wp, wb, _stream(torch, self.device))
         _check(self._L, st, "ctis_fourier_forward")
         return out
 
     def adjoint(self, r, out=None, workspace=None):
         torch = _torch()
-        r = self.plan._dev_tensor(r, self.plan.info.n, "r")
+        r = self.plan._dev_tensor(r, self.plan.sizes.n, "r")
         if out is None:
             out = torch.empty(self.plan.shape_f, dtype=torch.float32, device=self.device)
+        need_tensor(out, self.plan.sizes.m, "out", self.device)
         ws = self.workspace() if workspace is None else workspace
+        wp, wb = need_workspace(ws, self.info["workspace_bytes"], "workspace", self.device)
         st = self._L.ctis_fourier_adjoint(self._handle, ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(out.data_ptr()),
-                                          ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
-                                          _stream(torch, self.device))
+                                          wp, wb, _stream(torch, self.device))
         _check(self._L, st, "ctis_fourier_adjoint")
         return out
 
     def em(self, g, iters: int, f0=None, f=None, workspace=None):
         torch = _torch()
-        g = self.plan._dev_tensor(g, self.plan.info.n, "g")
+        g = self.plan._dev_tensor(g, self.plan.sizes.n, "g")
         if f is None:
             f = (torch.ones(self.plan.shape_f, dtype=torch.float32, device=self.device) if f0 is None
-                 else self.plan._dev_tensor(f0, self.plan.info.m, "f0").clone())
+                 else self.plan._dev_tensor(f0, self.plan.sizes.m, "f0").clone())
+        need_tensor(f, self.plan.sizes.m, "f", self.device)
         ws = self.workspace() if workspace is None else workspace
+        wp, wb = need_workspace(ws, self.info["workspace_bytes"], "workspace", self.device)
         st = self._L.ctis_fourier_em_iterate(self._handle, ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(f.data_ptr()),
-                                             int(iters), ctypes.c_void_p(ws.data_ptr()),
-                                             ws.numel() * ws.element_size(), _stream(torch, self.device))
+                                             int(iters), wp, wb, _stream(torch, self.device))
         _check(self._L, st, "ctis_fourier_em_iterate")
         return f

@@ -148,6 +148,74 @@ def test_set_values_matches_a_fresh_plan(torch, ctis):
     assert torch.equal(p1.em(g, 3), p2.em(g, 3))
 
 
+def test_set_values_reaches_every_host_reader(torch, ctis):
+    """After set_values, a batch and a Fourier plan built from the plan, its
+    column sums, its exported boxes and its sign flag equal those of a plan
+    created with the new values (the host copies are re-read from the
+    device)."""
+    c = W.make_case(1)
+    geo = c.geometry
+    rng = np.random.default_rng(5)
+    v2 = (c.value * rng.uniform(0.5, 1.5, c.value.size)).astype(np.float32)
+    p1 = ctis.Plan.from_case(c, keep_zeros=True)
+    p2 = ctis.Plan(geo.a, geo.alpha, geo.w, geo.gamma, geo.xi, c.lambda_ptr, c.fpa_index, v2, keep_zeros=True)
+    p1.set_values(torch.from_numpy(v2).cuda())
+    assert np.array_equal(p1.lambda_sums(), p2.lambda_sums())
+    for a, b in zip(p1.boxes(), p2.boxes()):
+        assert np.array_equal(a, b)
+    f = torch.rand(p1.shape_f, device="cuda")
+    g = p2.forward(f) + 0.01
+    b1, b2 = ctis.Batch([p1, p1]), ctis.Batch([p2, p2])
+    g2 = torch.cat([g.reshape(-1), g.reshape(-1)])
+    assert torch.equal(b1.em(g2, 3), b2.em(g2, 3))
+    F1, F2 = ctis.Fourier(p1), ctis.Fourier(p2)
+    assert torch.equal(F1.forward(f), F2.forward(f))
+    assert torch.equal(F1.em(g, 2), F2.em(g, 2))
+    # a negative value set on the device reaches the sign flag and the EM check
+    v3 = v2.copy()
+    v3[0] = -v3[0]
+    p1.set_values(torch.from_numpy(v3).cuda())
+    assert not p1.info.nonnegative
+    with pytest.raises(ctis.CtisError) as ei:
+        p1.em(g, 1)
+    assert ei.value.name == "CTIS_E_NEGATIVE"
+    p1.set_values(torch.from_numpy(v2).cuda())
+    assert p1.info.nonnegative
+    for x in (F1, F2, b1, b2, p1, p2):
+        x.close()
+
+
+def test_wrong_tensor_arguments_raise_before_any_launch(torch, ctis):
+    """Wrong element count, dtype, device or layout raises ValueError in the
+    binding; no kernel sees the pointer."""
+    c = W.make_case(1)
+    p = ctis.Plan.from_case(c)
+    b = ctis.Batch([p, p])
+    g = torch.rand(p.shape_g, device="cuda")
+    f = torch.ones(p.shape_f, device="cuda")
+    ws = p.workspace()
+    bad = [
+        lambda: p.em(g, 1, f=torch.ones(p.sizes.m - 1, device="cuda")),
+        lambda: p.em(g, 1, f=torch.ones(p.shape_f, device="cuda", dtype=torch.float64)),
+        lambda: p.em(g, 1, f=torch.ones(p.shape_f)),
+        lambda: p.em(g, 1, f=f, workspace=torch.empty(4, device="cuda")),
+        lambda: p.em_forward_ratio(f[:, :, :-1], g, ws),
+        lambda: p.em_adjoint_update(ws, f, torch.empty(p.sizes.m + 1, device="cuda")),
+        lambda: p.forward(f, out=torch.empty(p.sizes.n - 1, device="cuda")),
+        lambda: b.forward(torch.ones(p.sizes.m, device="cuda")),
+        lambda: b.em(torch.cat([g.reshape(-1), g.reshape(-1)])[:-1], 1),
+        lambda: b.em(torch.cat([g.reshape(-1), g.reshape(-1)]), 1,
+                     f_all=torch.ones(2 * p.sizes.m, device="cuda")[::2].contiguous()[:-1]),
+        lambda: b.adjoint(torch.ones(2 * p.sizes.n, device="cuda"), out=torch.empty(3, device="cuda")),
+    ]
+    for k, fn in enumerate(bad):
+        with pytest.raises(ValueError):
+            fn()
+    assert torch.equal(f, torch.ones_like(f))
+    b.close()
+    p.close()
+
+
 def test_value_derivatives_need_the_full_structure(torch, ctis):
     geo = W.Geometry(5, 7, 3, 13, 11)
     ptr, idx, val = W.random_kernels(geo, 9, np.random.default_rng(3))
