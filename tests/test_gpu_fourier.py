@@ -6,8 +6,8 @@ projection (n <= 2^20: < 1e-6 relative), so the projection bound (1e-5) and
 the EM bound after the configuration's iteration count (1e-4) are the same
 as for the gather path.
 """
+import ctypes
 import sys
-
 import zlib
 
 import numpy as np
@@ -133,9 +133,16 @@ def test_fourier_error_paths(torch, ctis):
     ptr, idx, val = W.random_kernels(geo, 5, np.random.default_rng(1))
     p = ctis.Plan(geo.a, geo.alpha, geo.w, geo.gamma, geo.xi, ptr, idx, val)
     F = ctis.Fourier(p)
-    with pytest.raises(ctis.CtisError) as ei:
-        F.forward(torch.ones(p.shape_f, device="cuda"), workspace=torch.empty(16, device="cuda"))
-    assert ei.value.name == "CTIS_E_WORKSPACE"
+    small = torch.empty(16, device="cuda")
+    f1 = torch.ones(p.shape_f, device="cuda")
+    out = torch.empty(p.shape_g, device="cuda")
+    with pytest.raises(ValueError):                   # the binding checks sizes first
+        F.forward(f1, workspace=small)
+    # the library's own check of the workspace size
+    st = F._L.ctis_fourier_forward(F._handle, ctypes.c_void_p(f1.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                   ctypes.c_void_p(small.data_ptr()), ctypes.c_size_t(64),
+                                   ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert ctis.STATUS_NAMES[st] == "CTIS_E_WORKSPACE"
     val2 = val.copy()
     val2[0] = -1.0
     F2 = ctis.Fourier(ctis.Plan(geo.a, geo.alpha, geo.w, geo.gamma, geo.xi, ptr, idx, val2))

@@ -4,8 +4,8 @@ Tolerances: relative L2 <= 1e-5 for one projection, <= 1e-4 after the full
 iteration count of a configuration, float32 arithmetic on the GPU.  Inputs are
 the same float32 values on both sides; the oracle promotes them to double.
 """
+import ctypes
 import sys
-
 import zlib
 
 import numpy as np
@@ -238,9 +238,14 @@ def test_gpu_error_paths(torch, ctis, c1):
     with pytest.raises(ValueError):
         p.forward(torch.zeros(5, device="cuda"))
     small = torch.empty(16, device="cuda")
-    with pytest.raises(ctis.CtisError) as ei:
+    with pytest.raises(ValueError):                   # the binding checks sizes first
         p.em(gd, 1, workspace=small)
-    assert ei.value.status == 8
+    # the library's own check of the workspace size
+    f1 = torch.ones(p.shape_f, device="cuda")
+    st = p._L.ctis_em_iterate(p._handle, ctypes.c_void_p(gd.data_ptr()), ctypes.c_void_p(f1.data_ptr()), 1,
+                              ctypes.c_void_p(small.data_ptr()), ctypes.c_size_t(64),
+                              ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert st == 8
     neg = ctis.Plan(4, 4, 1, 16, 16, np.array([0, 2], np.int64), np.array([0, 3], np.int32),
                     np.array([1.0, -1.0], np.float32))
     with pytest.raises(ctis.CtisError) as ei:
