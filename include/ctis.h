@@ -20,7 +20,7 @@
  * Conventions shared by every call
  * --------------------------------
  *  Sizes:   n = gamma * xi FPA pixels, ell = a * alpha field-stop pixels,
- *           m = ell * w voxels; n and ell below 2^29, m below 2^31.
+ *           m = ell * w voxels; n and m below 2^29.
  *  Layout:  the paper's column-major vectorisation (Sec. 2; Sec. 3 index map).
  *           Voxel (x, y, s), x < a, y < alpha, s < w, is f[x + a*y + ell*s]
  *           (a row-major (w, alpha, a) array).  FPA pixel (r, c), r < gamma,
@@ -78,6 +78,13 @@ typedef struct ctis_batch ctis_batch;
 #define CTIS_PLAN_BOX(b) (((uint32_t)(b) & 0xFu) << 8)
                                         /* force the calibration box side B in
                                            1..8 (0 = chosen by the plan)         */
+#define CTIS_PLAN_TILE_PATH 0x4u        /* EM on the tile path even where the
+                                           region path applies (comparisons) */
+#define CTIS_PLAN_REGION(k) (((uint32_t)(k) & 0x3u) << 12)
+                                        /* region shape of the region path
+                                           (pixels along gamma x xi): 1 = 8 x
+                                           32, 2 = 16 x 16, 3 = 32 x 8, 0 =
+                                           chosen by the plan                 */
 #define CTIS_PLAN_KEEP_ZEROS 0x2u       /* the structure is the set of given
                                            positions, whatever their values:
                                            entries that merge to an exact zero
@@ -110,6 +117,26 @@ typedef struct {
                                     enough for ctis_em_iterate)                 */
     int32_t dropped;         /* 1 if some entry merged to an exact zero and was
                                 dropped (never with CTIS_PLAN_KEEP_ZEROS)       */
+    /* The EM path's forward projection.  Region path: FPA regions of 256
+     * pixels (region_fast x region_slow), four boxes per wavefront at a time,
+     * windows read from a zero-bordered copy of f; taken when the FPA leaves
+     * region_fast + B - 2 pixels beside the field stop along gamma and
+     * region_slow + B - 2 along xi (and CTIS_PLAN_TILE_PATH is not set).
+     * Otherwise, and for ctis_forward, the tile path (tile_fast x tile_slow
+     * FPA tiles).                                                           */
+    int32_t region_fast, region_slow;   /* FPA region (pixels)                  */
+    int32_t n_regions, n_active_regions;
+    int64_t n_region_items;  /* (FPA region, box) pairs                         */
+    int32_t em_region_path;  /* 1 if ctis_em_iterate takes the region path      */
+    int32_t waves_region;    /* wavefronts per region-forward workgroup         */
+    /* Multiply-adds of one projection: the method's own (every calibration
+     * nonzero against every voxel of its wavelength, ell * nnz), and the ones
+     * the kernels execute (every slot of a B x B box against every output of a
+     * work item, overhang of the item past the box's image included).      */
+    int64_t method_madds;
+    int64_t tile_forward_madds;
+    int64_t region_forward_madds;
+    int64_t adjoint_madds;
 } ctis_plan_info;
 
 /*
@@ -164,6 +191,10 @@ ctis_status ctis_plan_export_boxes(const ctis_plan *plan, int32_t *box_lambda,
                                    int32_t *box_rc, float *box_values);
 ctis_status ctis_plan_export_worklist(const ctis_plan *plan, int32_t *tile_ptr,
                                       int32_t *item_box);
+/* The same for the region path's grid (region_fast x region_slow regions,
+ * fast index t % ceil(gamma/region_fast); sizes n_regions, n_region_items). */
+ctis_status ctis_plan_export_regions(const ctis_plan *plan, int32_t *region_ptr,
+                                     int32_t *item_box);
 
 /*
  * Forward projection g_out = H f (Sec. 2 eq. (linear); Sec. 3 eq. (vs_linear):
@@ -193,8 +224,10 @@ ctis_status ctis_adjoint(const ctis_plan *plan, const float *r, float *z_out, vo
  *   f          DEVICE float[m], in: start (the paper starts from all ones),
  *              out: f after `iters` updates; iters = 0 leaves f unchanged
  *   workspace  DEVICE, >= info.workspace_bytes, 256-byte aligned; its
- *              contents are scratch (u, and the partial tiles of FPA tiles
- *              whose boxes are split over several workgroups)
+ *              contents are scratch (u; the partial sums of FPA tiles or
+ *              regions whose boxes are split over several workgroups; on
+ *              the region path (info.em_region_path) a zero-bordered copy of
+ *              f, written at the start and kept current by the update)
  * Errors: CTIS_E_NEGATIVE if a calibration value is negative, CTIS_E_WORKSPACE,
  * CTIS_E_ARG, CTIS_E_HIP.
  */
@@ -202,24 +235,50 @@ ctis_status ctis_em_iterate(const ctis_plan *plan, const float *g, float *f, int
                             void *workspace, size_t workspace_bytes, void *stream);
 
 /*
- * The two fused kernels of one EM iteration, for callers that schedule the
+ * Diagnostics of an EM iterate (Sec. 2: the column sums h below eq. (em); the
+ * Poisson likelihood the EM iteration increases, after Shepp and Vardi), in
+ * double precision:
+ *   out[0] = sum_j h_j f_j               (flux; equals the sum of g over the
+ *                                         pixels with (H f_prev)_i > 0 after
+ *                                         an EM update)
+ *   out[1] = sum_i g_i
+ *   out[2] = sum_i (g_i log (H f)_i - (H f)_i), a g_i = 0 term contributing
+ *            -(H f)_i; -HUGE_VAL if some g_i > 0 has (H f)_i <= 0
+ *   out[3] = the number of such pixels
+ *   g          DEVICE float[n];  f  DEVICE float[m]
+ *   out        DEVICE double[4], 8-byte aligned, written
+ *   workspace  DEVICE, >= info.workspace_bytes, 256-byte aligned (scratch:
+ *              H f and the per-workgroup partial sums)
+ * Two reduction passes in a fixed order: the result does not depend on
+ * timing.  Errors: CTIS_E_ARG, CTIS_E_WORKSPACE, CTIS_E_HIP.
+ */
+ctis_status ctis_em_diagnostics(const ctis_plan *plan, const float *g, const float *f, double *out,
+                                void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * The two halves of one EM iteration, for callers that schedule the
  * iteration themselves.  ctis_em_iterate is `iters` pairs of these two calls
- * on one workspace (>= info.workspace_bytes, 256-byte aligned).
+ * on one workspace (>= info.workspace_bytes, 256-byte aligned), apart from
+ * writing the padded copy of f once instead of in every forward half.
  *
  *   ctis_em_forward_ratio:  u_i = g_i / (H f)_i, or 0 where (H f)_i <= 0, into
  *       the first n floats of the workspace, for every pixel of an FPA tile
- *       that meets the image of some calibration nonzero (the back projection
- *       reads no other pixel).  f DEVICE float[m], g DEVICE float[n].
+ *       or region that meets the image of some calibration nonzero (the back
+ *       projection reads no other pixel).  f DEVICE float[m], g DEVICE
+ *       float[n].  On the region path this is two kernels: the zero-bordered
+ *       copy of f into the workspace, then the projection.
  *   ctis_em_adjoint_update: f_out_j = f_in_j * (H^T u)_j / h_j, or 0 where
- *       h_j == 0, with u as left in the workspace by ctis_em_forward_ratio.
- *       f_out may equal f_in (in place) but must not overlap it otherwise.
+ *       h_j == 0, with u as left in the workspace by ctis_em_forward_ratio;
+ *       on the region path it also writes f_out into the workspace's padded
+ *       copy.  f_out may equal f_in (in place) but must not overlap it
+ *       otherwise.
  * Errors: CTIS_E_NEGATIVE if a calibration value is negative, CTIS_E_WORKSPACE,
  * CTIS_E_ARG, CTIS_E_HIP.  Calls sharing one workspace must be ordered on one
  * stream.
  */
 ctis_status ctis_em_forward_ratio(const ctis_plan *plan, const float *f, const float *g, void *workspace,
                                   size_t workspace_bytes, void *stream);
-ctis_status ctis_em_adjoint_update(const ctis_plan *plan, const void *workspace, size_t workspace_bytes,
+ctis_status ctis_em_adjoint_update(const ctis_plan *plan, void *workspace, size_t workspace_bytes,
                                    const float *f_in, float *f_out, void *stream);
 
 
@@ -244,6 +303,8 @@ ctis_status ctis_em_adjoint_update(const ctis_plan *plan, const void *workspace,
 #define CTIS_BATCH_PERSISTENT 0x400u   /* launch only as many workgroups as fit on the chip
                                           at once, each walking the work list; default:
                                           one workgroup per work unit                    */
+#define CTIS_BATCH_WAVES_REGION(n) (((uint32_t)(n) & 0xFu) << 11)  /* region forward, 0 = chosen */
+#define CTIS_BATCH_TILE_PATH 0x8000u   /* EM on the tile path even where the region path applies */
 
 typedef struct {
     int32_t n_frames;
@@ -255,13 +316,19 @@ typedef struct {
     int32_t n_plans;               /* distinct plans (frames may share one)      */
     int64_t n_entries;             /* calibration entries of the distinct plans  */
     size_t vjp_workspace_bytes;    /* workspace of ctis_batch_em_vjp             */
+    int32_t em_region_path;        /* 1 if EM takes the region path (every plan
+                                      allows it, CTIS_BATCH_TILE_PATH not set)  */
+    int32_t waves_region;
+    int64_t region_units;
 } ctis_batch_info;
 
-/* Create a batch over n_frames >= 1 frames.  flags: CTIS_BATCH_WAVES_* (wave
- * counts per workgroup of the two kernels, 4..16, or 0 for the built-in
- * choice), CTIS_BATCH_PERSISTENT.  Errors: CTIS_E_ARG (different B, host-only or other-device plan,
- * bad flags), CTIS_E_TOO_LARGE (buffers beyond 2^31 floats), CTIS_E_NOMEM,
- * CTIS_E_HIP. */
+/* Create a batch over n_frames >= 1 frames.  flags: CTIS_BATCH_WAVES_FORWARD /
+ * _ADJOINT (waves per workgroup of the tile kernels, 4..16 for B <= 5 and
+ * 4..8 above, or 0 for the built-in choice), CTIS_BATCH_WAVES_REGION (region
+ * forward, 1..8 or 0), CTIS_BATCH_PERSISTENT, CTIS_BATCH_TILE_PATH.  Errors:
+ * CTIS_E_ARG (different B, host-only or other-device plan, bad flags),
+ * CTIS_E_TOO_LARGE (f_all of 2^29 floats or more, g_all of 2^31 or more),
+ * CTIS_E_NOMEM, CTIS_E_HIP. */
 ctis_status ctis_batch_create(ctis_batch **out, const ctis_plan *const *plans, int32_t n_frames, uint32_t flags);
 void ctis_batch_destroy(ctis_batch *batch);
 ctis_status ctis_batch_get_info(const ctis_batch *batch, ctis_batch_info *info);

@@ -62,6 +62,45 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+# Host-code sanitizer build (AddressSanitizer + UndefinedBehaviorSanitizer)
+# for CPU runs of the plan builder and argument checks: the C++ sources are
+# compiled by g++ with the sanitizers, the HIP sources as in build() without
+# them, linked into _build/libctis_san.so.  Run the host tests against it with
+#   CTIS_LIBRARY=_build/libctis_san.so LD_PRELOAD=$(g++ -print-file-name=libasan.so) \
+#   ASAN_OPTIONS=detect_leaks=0 UBSAN_OPTIONS=halt_on_error=1:print_stacktrace=1 \
+#   python -m pytest tests/test_abi_host.py
+HOST_SOURCES = [s for s in SOURCES if s.endswith(".cpp")]
+SAN_LIB = os.path.join(BUILD, "libctis_san.so")
+SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer"]
+
+
+def build_sanitized(verbose: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    objs = []
+    for src in HOST_SOURCES:
+        obj = os.path.join(BUILD, src + ".san.o")
+        cmd = ["g++", "-O1", "-g", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", *SAN_FLAGS,
+               "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", f"-I{INCLUDE}", f"-I{CSRC}", "-c",
+               os.path.join(CSRC, src), "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+        objs.append(obj)
+    with cf.ThreadPoolExecutor(max_workers=2) as ex:
+        objs += list(ex.map(_compile, [s for s in SOURCES if s.endswith(".hip")]))
+    cmd = ["g++", "-shared", *SAN_FLAGS, *objs, "-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib",
+           "-o", SAN_LIB]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    if verbose:
+        print(f"built {SAN_LIB}")
+    return SAN_LIB
+
+
 if __name__ == "__main__":
-    build(verbose=True)
+    if "--sanitize" in sys.argv[1:]:
+        build_sanitized(verbose=True)
+    else:
+        build(verbose=True)
     sys.exit(0)

@@ -50,6 +50,41 @@ ctis_status launch_status(int err, const char *what) {
 
 }  // namespace
 
+// The first half of an EM iteration, u = g / (H f) into the workspace: on the
+// region path the zero-bordered copy of f is written first.
+ctis_status em_forward_half(const DevWork &w, const float *f, const float *g, void *workspace, void *stream) {
+    if (w.pad_ok) {
+        ctis_status st = launch_status(launch_pad(w, f, workspace, stream), "pad launch");
+        if (st != CTIS_OK) return st;
+        return launch_status(launch_forward_pad(w, g, nullptr, (float *)workspace, kFwdRatio, workspace, stream),
+                             "forward+ratio launch");
+    }
+    return launch_status(launch_forward(w, f, g, nullptr, (float *)workspace, kFwdRatio, workspace, stream),
+                         "forward+ratio launch");
+}
+
+// iters EM iterations in place.  Region path: the padded copy of f is
+// written once, then kept current by the update epilogue.
+ctis_status em_loop(const DevWork &w, const float *g, float *f, int32_t iters, void *workspace, void *stream) {
+    float *u = (float *)workspace;
+    ctis_status st = CTIS_OK;
+    if (w.pad_ok && iters > 0) {
+        st = launch_status(launch_pad(w, f, workspace, stream), "pad launch");
+        if (st != CTIS_OK) return st;
+    }
+    for (int32_t k = 0; k < iters; ++k) {
+        if (w.pad_ok)
+            st = launch_status(launch_forward_pad(w, g, nullptr, u, kFwdRatio, workspace, stream), "forward+ratio launch");
+        else
+            st = launch_status(launch_forward(w, f, g, nullptr, u, kFwdRatio, workspace, stream), "forward+ratio launch");
+        if (st != CTIS_OK) return st;
+        st = launch_status(launch_adjoint(w, u, f, nullptr, f, nullptr, nullptr, kAdjUpdate, stream, workspace),
+                           "adjoint+update launch");
+        if (st != CTIS_OK) return st;
+    }
+    return CTIS_OK;
+}
+
 ctis_status refresh_host_tables(const ctis_plan *p) {
     if (!p->host_stale) return CTIS_OK;
     ctis_status st = check_device(p);
@@ -103,7 +138,8 @@ ctis_status ctis_plan_create(ctis_plan **out, int32_t a, int32_t alpha, int32_t 
     g_last_error.clear();
     if (!out) return fail(CTIS_E_ARG, "out is NULL");
     *out = nullptr;
-    const uint32_t known = CTIS_PLAN_HOST_ONLY | CTIS_PLAN_KEEP_ZEROS | CTIS_PLAN_BOX(0xF);
+    const uint32_t known =
+        CTIS_PLAN_HOST_ONLY | CTIS_PLAN_KEEP_ZEROS | CTIS_PLAN_TILE_PATH | CTIS_PLAN_BOX(0xF) | CTIS_PLAN_REGION(3);
     if (flags & ~known) return fail(CTIS_E_ARG, "unknown flag bits");
     const int forced_box = (int)((flags >> 8) & 0xFu);
     if (forced_box > kMaxBox) return fail(CTIS_E_ARG, "forced box side must be in 1..8");
@@ -111,8 +147,8 @@ ctis_status ctis_plan_create(ctis_plan **out, int32_t a, int32_t alpha, int32_t 
         return fail(CTIS_E_ARG, "a, alpha, w, gamma, xi must all be >= 1");
     if (a > gamma || alpha > xi) return fail(CTIS_E_ARG, "the field stop must fit on the FPA (a <= gamma, alpha <= xi)");
     const int64_t n = (int64_t)gamma * xi, ell = (int64_t)a * alpha, m = ell * w;
-    if (n > kMaxPixels || ell > kMaxPixels || m > INT32_MAX - 4096)
-        return fail(CTIS_E_TOO_LARGE, "n = gamma*xi and a*alpha must be below 2^29, m = a*alpha*w below 2^31");
+    if (n > kMaxPixels || m > kMaxPixels)
+        return fail(CTIS_E_TOO_LARGE, "n = gamma*xi and m = a*alpha*w must be below 2^29");
     if (!lambda_ptr) return fail(CTIS_E_ARG, "lambda_ptr is NULL");
     if (lambda_ptr[0] != 0) return fail(CTIS_E_ARG, "lambda_ptr[0] must be 0");
     for (int32_t s = 0; s < w; ++s)
@@ -139,7 +175,9 @@ ctis_status ctis_plan_create(ctis_plan **out, int32_t a, int32_t alpha, int32_t 
     p->m = m;
     ctis_status st;
     try {
-        st = build_host_tables(p, lambda_ptr, fpa_index, value, forced_box, (flags & CTIS_PLAN_KEEP_ZEROS) != 0);
+        const int shape = (int)((flags >> 12) & 0x3u);   // CTIS_PLAN_REGION: 1 -> 8 x 32, 2 -> 16 x 16, 3 -> 32 x 8
+        st = build_host_tables(p, lambda_ptr, fpa_index, value, forced_box, (flags & CTIS_PLAN_KEEP_ZEROS) != 0,
+                               shape ? 1 << shape : 0);
     } catch (const std::bad_alloc &) {
         st = fail(CTIS_E_NOMEM, "host allocation while building the plan");
     }
@@ -147,6 +185,7 @@ ctis_status ctis_plan_create(ctis_plan **out, int32_t a, int32_t alpha, int32_t 
         delete p;
         return st;
     }
+    if (flags & CTIS_PLAN_TILE_PATH) p->ht.pad_ok = false;
     if (!(flags & CTIS_PLAN_HOST_ONLY)) {
         int dev = -1;
         hipError_t e = hipGetDevice(&dev);
@@ -184,6 +223,7 @@ ctis_status ctis_plan_create(ctis_plan **out, int32_t a, int32_t alpha, int32_t 
         p->workspace_bytes = L.em_bytes;
         p->vjp_workspace_bytes = L.vjp_bytes;
         p->work.fwd_em.waves = hw.fwd_em.waves;
+        p->work.fwd_pad.waves = hw.fwd_pad.waves;
         p->work.adj.waves = hw.adj.waves;
     }
     *out = p;
@@ -213,11 +253,27 @@ ctis_status ctis_plan_get_info(const ctis_plan *p, ctis_plan_info *info) {
     info->n_support = p->ht.n_support;
     info->box = p->ht.B;
     info->n_boxes = (int32_t)p->ht.box_lambda.size();
+    const HostTables &T = p->ht;
     info->tile_fast = kTileFast;
     info->tile_slow = kTileSlow;
-    info->n_tiles = p->ht.n_tiles;
-    info->n_active_tiles = p->ht.n_active;
-    info->n_items = (int64_t)p->ht.item_box.size();
+    info->n_tiles = T.tiles.n_cells;
+    info->n_active_tiles = T.tiles.n_active;
+    info->n_items = (int64_t)T.tiles.item_box.size();
+    info->region_fast = T.regions.tf;
+    info->region_slow = T.regions.ts;
+    info->n_regions = T.regions.n_cells;
+    info->n_active_regions = T.regions.n_active;
+    info->n_region_items = (int64_t)T.regions.item_box.size();
+    info->em_region_path = (p->device >= 0 ? p->work.pad_ok : T.pad_ok) ? 1 : 0;
+    info->waves_region = p->work.fwd_pad.waves;
+    // multiply-adds: the method's (every calibration nonzero against every
+    // voxel of its wavelength), and the ones the kernels execute (every slot
+    // of a B x B box against every output of a work item)
+    const int64_t BB = (int64_t)T.B * T.B;
+    info->method_madds = p->ell * T.nnz;
+    info->tile_forward_madds = (int64_t)T.tiles.item_box.size() * kTileFast * kTileSlow * BB;
+    info->region_forward_madds = (int64_t)T.regions.item_box.size() * kRegionPixels * BB;
+    info->adjoint_madds = (int64_t)T.nbx * T.nby * kTileFast * kTileSlow * (int64_t)T.box_lambda.size() * BB;
     info->workspace_bytes = p->workspace_bytes;
     info->nonnegative = p->ht.nonneg ? 1 : 0;
     info->device = p->device;
@@ -250,9 +306,17 @@ ctis_status ctis_plan_export_boxes(const ctis_plan *p, int32_t *box_lambda, int3
 
 ctis_status ctis_plan_export_worklist(const ctis_plan *p, int32_t *tile_ptr, int32_t *item_box) {
     if (!p) return fail(CTIS_E_ARG, "plan is NULL");
-    const auto &T = p->ht;
-    if (tile_ptr) std::memcpy(tile_ptr, T.tile_item_ptr.data(), T.tile_item_ptr.size() * 4);
-    if (item_box) std::memcpy(item_box, T.item_box.data(), T.item_box.size() * 4);
+    const auto &G = p->ht.tiles;
+    if (tile_ptr) std::memcpy(tile_ptr, G.item_ptr.data(), G.item_ptr.size() * 4);
+    if (item_box) std::memcpy(item_box, G.item_box.data(), G.item_box.size() * 4);
+    return CTIS_OK;
+}
+
+ctis_status ctis_plan_export_regions(const ctis_plan *p, int32_t *region_ptr, int32_t *item_box) {
+    if (!p) return fail(CTIS_E_ARG, "plan is NULL");
+    const auto &G = p->ht.regions;
+    if (region_ptr) std::memcpy(region_ptr, G.item_ptr.data(), G.item_ptr.size() * 4);
+    if (item_box) std::memcpy(item_box, G.item_box.data(), G.item_box.size() * 4);
     return CTIS_OK;
 }
 
@@ -305,14 +369,7 @@ ctis_status ctis_em_iterate(const ctis_plan *p, const float *g, float *f, int32_
                             size_t workspace_bytes, void *stream) {
     ctis_status st = em_check(p, g, f, iters, workspace, workspace_bytes);
     if (st != CTIS_OK || iters == 0) return st;
-    float *u = (float *)workspace;
-    for (int32_t k = 0; k < iters; ++k) {
-        st = launch_status(launch_forward(p->work, f, g, nullptr, u, kFwdRatio, workspace, stream), "forward+ratio launch");
-        if (st != CTIS_OK) return st;
-        st = launch_status(launch_adjoint(p->work, u, f, nullptr, f, nullptr, nullptr, kAdjUpdate, stream), "adjoint+update launch");
-        if (st != CTIS_OK) return st;
-    }
-    return CTIS_OK;
+    return em_loop(p->work, g, f, iters, workspace, stream);
 }
 
 ctis_status ctis_em_forward_ratio(const ctis_plan *p, const float *f, const float *g, void *workspace,
@@ -328,11 +385,10 @@ ctis_status ctis_em_forward_ratio(const ctis_plan *p, const float *f, const floa
         return fail(CTIS_E_ARG, "the workspace must not overlap f or g");
     st = check_device(p);
     if (st != CTIS_OK) return st;
-    return launch_status(launch_forward(p->work, f, g, nullptr, (float *)workspace, kFwdRatio, workspace, stream),
-                         "forward+ratio launch");
+    return em_forward_half(p->work, f, g, workspace, stream);
 }
 
-ctis_status ctis_em_adjoint_update(const ctis_plan *p, const void *workspace, size_t workspace_bytes,
+ctis_status ctis_em_adjoint_update(const ctis_plan *p, void *workspace, size_t workspace_bytes,
                                    const float *f_in, float *f_out, void *stream) {
     if (!p) return fail(CTIS_E_ARG, "plan is NULL");
     if (!f_in || !f_out) return fail(CTIS_E_ARG, "f_in or f_out is NULL");
@@ -346,8 +402,32 @@ ctis_status ctis_em_adjoint_update(const ctis_plan *p, const void *workspace, si
         return fail(CTIS_E_ARG, "the workspace and f_out overlap");
     st = check_device(p);
     if (st != CTIS_OK) return st;
-    return launch_status(launch_adjoint(p->work, (const float *)workspace, f_in, nullptr, f_out, nullptr, nullptr, kAdjUpdate, stream),
+    return launch_status(launch_adjoint(p->work, (const float *)workspace, f_in, nullptr, f_out, nullptr, nullptr,
+                                        kAdjUpdate, stream, workspace),
                          "adjoint+update launch");
+}
+
+ctis_status ctis_em_diagnostics(const ctis_plan *p, const float *g, const float *f, double *out, void *workspace,
+                                size_t workspace_bytes, void *stream) {
+    if (!p) return fail(CTIS_E_ARG, "plan is NULL");
+    if (!g || !f || !out) return fail(CTIS_E_ARG, "g, f or out is NULL");
+    if (!aligned4(g) || !aligned4(f) || ((uintptr_t)out & 7u) != 0)
+        return fail(CTIS_E_ARG, "g and f must be 4-byte aligned, out 8-byte aligned");
+    ctis_status st = workspace_check(p, workspace, workspace_bytes);
+    if (st != CTIS_OK) return st;
+    if (overlaps(workspace, p->workspace_bytes, f, (size_t)p->m * 4) ||
+        overlaps(workspace, p->workspace_bytes, g, (size_t)p->n * 4) ||
+        overlaps(workspace, p->workspace_bytes, out, 4 * sizeof(double)))
+        return fail(CTIS_E_ARG, "the workspace must not overlap g, f or out");
+    st = check_device(p);
+    if (st != CTIS_OK) return st;
+    float *ghat = (float *)workspace;
+    st = launch_status(launch_forward(p->work, f, nullptr, nullptr, ghat, kFwdPlain, nullptr, stream),
+                       "diagnostics forward launch");
+    if (st != CTIS_OK) return st;
+    return launch_status(launch_diagnostics(g, ghat, f, p->work.h, p->n, p->m, p->ell,
+                                            (double *)((char *)workspace + p->work.diag_off), out, stream),
+                         "diagnostics launch");
 }
 
 }  // extern "C"

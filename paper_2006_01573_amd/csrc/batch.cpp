@@ -39,7 +39,8 @@ ctis_status ctis_batch_create(ctis_batch **out, const ctis_plan *const *plans, i
     if (!out) return fail(CTIS_E_ARG, "out is NULL");
     *out = nullptr;
     if (!plans || n_frames < 1) return fail(CTIS_E_ARG, "need at least one plan");
-    if (flags & ~(0x3FFu | CTIS_BATCH_PERSISTENT)) return fail(CTIS_E_ARG, "unknown flag bits");
+    if (flags & ~(0x3FFu | CTIS_BATCH_PERSISTENT | CTIS_BATCH_WAVES_REGION(0xF) | CTIS_BATCH_TILE_PATH))
+        return fail(CTIS_E_ARG, "unknown flag bits");
     const int wf = (int)(flags & 0x1Fu), wa = (int)((flags >> 5) & 0x1Fu);
     int dev = -1;
     hipError_t e = hipGetDevice(&dev);
@@ -59,13 +60,17 @@ ctis_status ctis_batch_create(ctis_batch **out, const ctis_plan *const *plans, i
         fo += p->m;
         go += p->n;
         nonneg = nonneg && p->ht.nonneg;
-        if (fo > INT32_MAX || go > INT32_MAX) return fail(CTIS_E_TOO_LARGE, "batch buffers beyond 2^31 floats");
+        if (fo > kMaxPixels || go > INT32_MAX)
+            return fail(CTIS_E_TOO_LARGE, "batch buffers of 2^29 (f_all) or 2^31 (g_all) floats or more");
     }
     const int B = plans[0]->ht.B;
     for (int nw : {wf, wa})
         if (nw != 0 && (nw < min_waves() || nw > max_waves(B)))
             return fail(CTIS_E_ARG, "waves per workgroup must be 0 or in " + std::to_string(min_waves()) + ".." +
                                         std::to_string(max_waves(B)));
+    const int wr = (int)((flags >> 11) & 0xFu);
+    if (wr > kFwdMaxWaves)
+        return fail(CTIS_E_ARG, "region waves per workgroup must be 0 or in 1.." + std::to_string(kFwdMaxWaves));
     ctis_batch *b = new (std::nothrow) ctis_batch();
     if (!b) return fail(CTIS_E_NOMEM, "batch allocation");
     ctis_status st;
@@ -78,6 +83,8 @@ ctis_status ctis_batch_create(ctis_batch **out, const ctis_plan *const *plans, i
     if (st == CTIS_OK) {
         if (wf) hw.fwd_em.waves = hw.fwd_full.waves = wf;
         if (wa) hw.adj.waves = wa;
+        if (wr) hw.fwd_pad.waves = wr;
+        if (flags & CTIS_BATCH_TILE_PATH) hw.pad_ok = false;
         st = upload_work(hw, b->work);
         b->work.persistent = (flags & CTIS_BATCH_PERSISTENT) != 0;
     }
@@ -121,6 +128,9 @@ ctis_status ctis_batch_get_info(const ctis_batch *b, ctis_batch_info *info) {
     info->adjoint_units = b->work.adj.n_units;
     info->waves_forward = b->work.fwd_em.waves;
     info->waves_adjoint = b->work.adj.waves;
+    info->em_region_path = b->work.pad_ok ? 1 : 0;
+    info->waves_region = b->work.fwd_pad.waves;
+    info->region_units = b->work.fwd_pad.n_units;
     info->workspace_bytes = b->work.workspace_bytes;
     info->n_plans = (int32_t)b->plan_entry0.size();
     info->n_entries = b->work.n_entries;
@@ -165,14 +175,7 @@ ctis_status ctis_batch_em_iterate(const ctis_batch *b, const float *g_all, float
         return fail(CTIS_E_ARG, "g_all, f_all and the workspace must not overlap");
     ctis_status st = batch_device(b);
     if (st != CTIS_OK) return st;
-    float *u = (float *)workspace;
-    for (int32_t k = 0; k < iters; ++k) {
-        st = launched(launch_forward(b->work, f_all, g_all, nullptr, u, kFwdRatio, workspace, stream), "batch forward+ratio launch");
-        if (st != CTIS_OK) return st;
-        st = launched(launch_adjoint(b->work, u, f_all, nullptr, f_all, nullptr, nullptr, kAdjUpdate, stream), "batch adjoint+update launch");
-        if (st != CTIS_OK) return st;
-    }
-    return CTIS_OK;
+    return em_loop(b->work, g_all, f_all, iters, workspace, stream);
 }
 
 }  // extern "C"

@@ -16,12 +16,27 @@
 
 namespace ctis {
 
-// Tile shape of both kernels: a wavefront covers 64 x 16 outputs (fast x slow
-// axis) with a 4 x 4 register micro-tile per lane (16 lanes x 4 lanes).
+// Tile shape of the back projection and of the tile forward projection: a
+// wavefront covers 64 x 16 outputs (fast x slow axis) with a 4 x 4 register
+// micro-tile per lane (16 lanes x 4 lanes).
 constexpr int kTileFast = 64;
 constexpr int kTileSlow = 16;
+// Regions of the region forward projection (the EM path): a group of 16
+// lanes covers 256 FPA pixels, gx x (16 / gx) lanes with a 4 x 4 micro-tile
+// each, i.e. (4 gx) x (64 / gx) pixels along gamma x xi; four groups per
+// wavefront, each on another box.  gx is 2, 4 or 8 (8 x 32, 16 x 16, 32 x 8).
+constexpr int kRegionPixels = 256;
+constexpr int kFwdMaxWaves = 8;
 constexpr int kMaxBox = 8;
-// 32-bit buffer offsets (in bytes) address the FPA and one wavelength block
+constexpr int region_fast(int gx) { return 4 * gx; }
+constexpr int region_slow(int gx) { return 64 / gx; }
+// Zero border of the padded copy of f the region forward reads, per axis: a
+// window of a region (region + B - 1 slots per side) that meets the field
+// stop lies inside [-hx, a + hx) x [-hy, alpha + hy).
+constexpr int halo_fast(int gx, int B) { return region_fast(gx) + B - 2; }
+constexpr int halo_slow(int gx, int B) { return region_slow(gx) + B - 2; }
+// 32-bit buffer offsets (in bytes) address the FPA, a wavelength block and
+// the whole f buffer (and its padded copy) of a plan or batch
 constexpr int64_t kMaxPixels = (int64_t(1) << 29) - 1;
 
 // ---------------------------------------------------------------------------
@@ -71,13 +86,27 @@ struct DevList {
 struct DevWork {
     int32_t B = 1;
     DevList fwd_full;            // plain projection: every FPA tile once
-    DevList fwd_em;              // EM: tiles with boxes, heavy tiles split
+    DevList fwd_em;              // tile forward for EM: tiles with boxes, heavy tiles split
     const int4 *split_meta = nullptr;
     int32_t n_split = 0;
+    // region forward of the EM path (when pad_ok): regions with boxes, heavy
+    // regions split; reads the padded copy of f in the workspace
+    bool pad_ok = false;
+    int32_t region_gx = 4;       // region shape (lanes of a group along gamma)
+    int32_t halo_x = 0, halo_y = 0;   // zero border of the padded copy
+    DevList fwd_pad;
+    const int4 *rsplit_meta = nullptr;
+    int32_t n_rsplit = 0;
+    const int4 *pad_blocks = nullptr;   // per (frame, wavelength): (f_off, fp_off, a, alpha)
+    int32_t n_pad_blocks = 0, pad_rows = 0;   // max alpha + 2 halo_y over the blocks
+    int32_t f_floats = 0, fp_floats = 0, n_wf = 0;   // extents of f, of its padded copy, of box_wf
     DevList adj;                 // adjoint units; items indexed by global wavelength
     float *box_w = nullptr, *box_wf = nullptr, *h = nullptr;
     size_t partials_off = 0;     // byte offset of the partial tiles in the EM workspace
-    size_t workspace_bytes = 0;  // u region + partial tiles
+    size_t rpartials_off = 0;    // byte offset of the partial regions
+    size_t fp_off = 0;           // byte offset of the padded copy of f
+    size_t diag_off = 0;         // byte offset of the diagnostics partials
+    size_t workspace_bytes = 0;  // u region + partial tiles + partial regions + padded f + diagnostics
     bool persistent = false;     // grid-stride workgroups instead of one per unit
     // value gradients and value updates
     const int32_t *entry_slot = nullptr, *box_lam = nullptr, *lam_box0 = nullptr;
@@ -98,9 +127,13 @@ struct HostList {
 
 struct HostWork {
     int32_t B = 1;
-    HostList fwd_full, fwd_em, adj;
-    std::vector<int32_t> split_meta;
-    int32_t n_split = 0, partial_slots = 0;
+    HostList fwd_full, fwd_em, fwd_pad, adj;
+    std::vector<int32_t> split_meta, rsplit_meta, pad_blocks;
+    int32_t n_split = 0, partial_slots = 0, n_rsplit = 0, rpartial_slots = 0;
+    bool pad_ok = false;
+    int32_t region_gx = 4, halo_x = 0, halo_y = 0;
+    int64_t fp_floats = 0;       // padded copy of f (all frames)
+    int32_t pad_rows = 0;
     std::vector<float> box_w, box_wf, h;
     int64_t u_floats = 0;        // u region of the EM workspace
     int64_t f_floats = 0;        // extent of the f buffer
@@ -115,7 +148,18 @@ struct HostWork {
 
 // Workspace layout of a work description (byte offsets, 256-byte aligned).
 struct Layout {
-    size_t partials_off, em_bytes, e_off, zeta_off, b_off, hpart_off, vg_off, vjp_bytes;
+    size_t partials_off, rpartials_off, fp_off, diag_off, em_bytes, e_off, zeta_off, b_off, hpart_off, vg_off,
+        vjp_bytes;
+};
+
+// Forward work list over a grid of FPA cells (tf x ts pixels): for every
+// cell the boxes whose shifted, dilated field-stop image meets it.
+struct WorkGrid {
+    int32_t tf = 0, ts = 0;      // cell size along gamma and xi
+    int32_t ntr = 0, ntc = 0, n_cells = 0, n_active = 0, max_items = 0;
+    int32_t chunk = 64;          // max boxes per forward unit in EM
+    std::vector<int32_t> order;  // cells, heaviest first (stable)
+    std::vector<int32_t> item_ptr, item_box;   // boxes of cell t: item_box[item_ptr[t] .. item_ptr[t+1])
 };
 Layout layout_for(const HostWork &hw);
 
@@ -124,12 +168,15 @@ struct HostTables {
     int32_t B = 1;
     std::vector<int32_t> box_rc, box_lambda, lambda_box_ptr;
     std::vector<float> box_w, box_wf, h;
-    std::vector<int32_t> tile_order, tile_item_ptr, item_box;
-    int32_t ntr = 0, ntc = 0, n_tiles = 0, n_active = 0;
+    WorkGrid tiles;              // 64 x 16 FPA tiles (plain projection, tile EM path)
+    WorkGrid regions;            // FPA regions of the region EM path
+    int32_t region_gx = 4;       // their shape: region_fast(gx) x region_slow(gx)
+    // the region path reads f through a zero-bordered copy; exact when the
+    // FPA leaves halo_fast / halo_slow pixels beside the field stop
+    bool pad_ok = false;
     int32_t nbx = 0, nby = 0;
     int64_t nnz = 0, n_support = 0;
-    int32_t max_items = 0, max_boxes = 0;
-    int32_t chunk = 64;          // max boxes per forward unit in EM
+    int32_t max_boxes = 0;
     bool nonneg = true;
     // calibration entries as given: count, slot of each (global box of the
     // plan * B*B + position in the box; -1 if dropped), any dropped
@@ -177,7 +224,7 @@ ctis_status refresh_host_tables(const ctis_plan *p);
 
 // host plan builder (plan.cpp)
 ctis_status build_host_tables(ctis_plan *p, const int64_t *lambda_ptr, const int32_t *fpa_index,
-                              const float *value, int forced_box, bool keep_zeros);
+                              const float *value, int forced_box, bool keep_zeros, int region_gx);
 
 // One frame of a work description: its plan and buffer offsets (floats).
 struct FrameRef {
@@ -188,8 +235,12 @@ ctis_status build_work(const std::vector<FrameRef> &frames, bool with_full, Host
 ctis_status upload_work(const HostWork &hw, DevWork &dw);
 void free_work(DevWork &dw);
 
+// stream-ordered EM drivers shared by plans and batches (api.cpp)
+ctis_status em_forward_half(const DevWork &w, const float *f, const float *g, void *workspace, void *stream);
+ctis_status em_loop(const DevWork &w, const float *g, float *f, int32_t iters, void *workspace, void *stream);
+
 // kernel launchers (kernels.hip); return hipError_t as int
-int max_waves(int box);
+int max_waves(int box);         // tile kernels: waves per workgroup
 int min_waves();
 
 // Epilogues of the forward projection v = (H x)_i:
@@ -208,14 +259,26 @@ enum AdjMode : int {
 };
 int launch_forward(const DevWork &w, const float *x, const float *g, const float *u, float *out, int mode,
                    void *workspace, void *stream);
+// Region path (w.pad_ok): launch_pad writes the zero-bordered copy of x into
+// the workspace; launch_forward_pad projects that copy (modes as above).
+int launch_pad(const DevWork &w, const float *x, void *workspace, void *stream);
+int launch_forward_pad(const DevWork &w, const float *g, const float *u, float *out, int mode, void *workspace,
+                       void *stream);
+// `fpad`: with kAdjUpdate, also write the updated f into the padded copy at
+// that workspace (nullptr: not)
 int launch_adjoint(const DevWork &w, const float *r, const float *in1, const float *in2, float *out, float *out2,
-                   float *flux, int mode, void *stream);
+                   float *flux, int mode, void *stream, void *fpad = nullptr);
 // per-(adjoint unit, box) partial derivatives of the calibration values, then
 // their sums per entry into dv (accumulated if `accumulate`)
 int launch_value_grad(const DevWork &w, const float *u, const float *e, const float *b, const float *f,
                       float *partial, void *stream);
 int launch_value_finish(const DevWork &w, const float *partial, const float *flux, float *dv, int64_t entry0,
                         int64_t n_entries, bool accumulate, void *stream);
+// EM diagnostics of one frame into out[4] = (flux, sum g, log-likelihood,
+// pixels with g > 0 and ghat <= 0); `part` holds kDiagParts * 4 doubles
+constexpr int kDiagParts = 256;
+int launch_diagnostics(const float *g, const float *ghat, const float *f, const float *hsum, int64_t n, int64_t m,
+                       int64_t ell, double *part, double *out, void *stream);
 // box values and column sums of the global wavelengths [lam0, lam1) from
 // the entry values `values` (entry `entry0` first)
 int launch_set_values(const DevWork &w, const float *values, int64_t entry0, int32_t lam0, int32_t lam1,

@@ -264,17 +264,18 @@ __device__ __forceinline__ void store_window(float *S, const Pending<B> &pd, int
     if (kValues && lane < B * B) S[Wn::REG + lane] = pd.wt;
 }
 
-// acc[k][q] += sum_{i,j < B} W[j*B + i] * S[(4ly + k + j) * SXP + 4lx + q + i]
-template <int B>
+// acc[k][q] += sum_{i,j < B} W[j*B + i] * S[(4ly + k + j) * SXP + 4lx + q + i],
+// W = S + WOFF: a window of row pitch SXP with the box values after it
+template <int B, int SXP, int WOFF>
 __device__ __forceinline__ void correlate(float (&acc)[4][4], const float *S, int lx, int ly) {
-    using Wn = Win<B>;
-    const float *W = S + Wn::REG;
+    constexpr int NR = 4 + B - 1, NV = (NR + 3) / 4;
+    const float *W = S + WOFF;
 #pragma unroll
-    for (int row = 0; row < Wn::NR; ++row) {
-        float seg[4 * Wn::NV];
-        const float4 *src = reinterpret_cast<const float4 *>(S + (4 * ly + row) * Wn::SXP + 4 * lx);
+    for (int row = 0; row < NR; ++row) {
+        float seg[4 * NV];
+        const float4 *src = reinterpret_cast<const float4 *>(S + (4 * ly + row) * SXP + 4 * lx);
 #pragma unroll
-        for (int v = 0; v < Wn::NV; ++v) {
+        for (int v = 0; v < NV; ++v) {
             const float4 t = src[v];
             seg[4 * v + 0] = t.x;
             seg[4 * v + 1] = t.y;
@@ -386,7 +387,7 @@ __global__ void __launch_bounds__(64 * Win<B>::MAXW) k_forward(const int4 *__res
             k += nw;
             const int4 rec3 = record(list, k + nw, stride);
             if (rec1.w >= 0) load_forward<B>(pa, f, box_wf, geo, rec1, lane);
-            correlate<B>(acc, S, lx, ly);
+            correlate<B, Win<B>::SXP, Win<B>::REG>(acc, S, lx, ly);
             wave_lds_sync();
             rec0 = rec1;
             rec1 = rec3;
@@ -430,6 +431,268 @@ __global__ void __launch_bounds__(256) k_finish_split(const int4 *__restrict__ s
     }
 }
 
+// ---------------------------------------------------------------------------
+// Region forward projection (the EM path).  A wavefront is four groups of 16
+// lanes.  A group owns an FPA region of 256 pixels, (4 GX) x (4 GY) with
+// GX * GY = 16 (GX x GY lanes with a 4 x 4 register micro-tile each), and
+// takes one box of the region's work list at a time, so the four groups of a
+// wave correlate four different boxes with the same region at once, and the
+// waves of a workgroup split the region's boxes.  At the end the groups are
+// summed with a fixed butterfly and the waves in LDS in a fixed order
+// (deterministic results).  The small region keeps the outputs computed per
+// box close to the box's shifted field-stop image: a larger output tile
+// spends its multiply-adds on the overhang, where the window holds zeros.
+//
+// The windows come from a zero-bordered copy of f (per wavelength a block of
+// (a + 2 Hx) x (alpha + 2 Hy) floats, Hx = 4 GX + B - 2, Hy = 4 GY + B - 2,
+// written by k_pad and by the back projection's EM update): the host writes
+// each window origin as a position of that block, so a window is a plain
+// 2-D rectangle of it, read in 16-byte pieces with no field-stop test and no
+// wrap arithmetic (exact when the FPA leaves Hx and Hy pixels beside the
+// field stop; the tile kernel serves other plans).
+constexpr int kRegion = 256;
+constexpr int kGroups = 4;
+constexpr int kGroupLanes = 64 / kGroups;
+
+template <int B, int GX>
+struct RWin {
+    static constexpr int GY = kGroupLanes / GX;
+    static constexpr int RX = 4 * GX, RY = 4 * GY;  // region (fast x slow)
+    static constexpr int SX = RX + B - 1;          // window extent, fast axis
+    static constexpr int SX4 = (SX + 3) / 4;       // 16-byte pieces per window row
+    static constexpr int SXP = 4 * SX4;            // LDS row pitch
+    static constexpr int SY = RY + B - 1;          // window extent, slow axis
+    static constexpr int REG = SXP * SY;           // window floats per group
+    static constexpr int BB = B * B;
+    static constexpr int GREG = REG + ((BB + 3) & ~3);   // window + box values
+    static constexpr int WAVE = kGroups * GREG;    // LDS floats per wavefront
+    static constexpr int NSLOT = SX4 * SY;         // 16-byte pieces per window
+    static constexpr int NT = (NSLOT + kGroupLanes - 1) / kGroupLanes;
+    static constexpr int NWT = (BB + kGroupLanes - 1) / kGroupLanes;
+    static constexpr int MAXW = kFwdMaxWaves;
+    static_assert(RX * RY == kRegion && kGroupLanes % GX == 0, "a group covers 256 pixels");
+    static_assert(WAVE >= kRegion, "the reduction parks 256 floats per wave");
+    static_assert(REG % 4 == 0 && GREG % 4 == 0, "16-byte aligned group regions");
+    static_assert(4 * (GX - 1) + 4 * ((4 + B - 1 + 3) / 4) <= SXP, "segment reads stay inside the row");
+    static_assert(halo_fast(GX, B) >= SX - 1 && halo_slow(GX, B) >= SY - 1,
+                  "a window meeting the field stop stays inside the padded block");
+};
+
+// One window in flight per group lane, in registers: its 16-byte pieces of
+// the window and its share of the box's values.
+template <int B, int GX>
+struct RPend {
+    float4 v[RWin<B, GX>::NT];
+    float wt[RWin<B, GX>::NWT];
+};
+
+// raw 128-bit buffer load at byte offset `off` (4-byte aligned)
+__device__ __forceinline__ float4 bload4(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+
+// Window of one (region, box) item, rec = (origin, 0, 0, box): piece t of
+// this lane at byte offset 4*origin + poff[t] of the padded copy (poff: the
+// piece's column and row within the window; 0 for a lane without a piece t,
+// whose load is then not stored); box < 0 (an empty slot) reads zeros (the
+// out-of-range offset).  A piece may run up to three floats past the
+// window's last column (LDS pitch padding, never used).
+template <int B, int GX>
+__device__ __forceinline__ void load_region(RPend<B, GX> &pd, __amdgpu_buffer_rsrc_t fr, __amdgpu_buffer_rsrc_t wr,
+                                            int4 rec, int gl, const unsigned (&poff)[RWin<B, GX>::NT]) {
+    using Wn = RWin<B, GX>;
+    const bool ok = rec.w >= 0;
+    const unsigned base = ok ? 4u * (unsigned)rec.x : kOutOfRange;
+#pragma unroll
+    for (int t = 0; t < Wn::NT; ++t) pd.v[t] = bload4(fr, base + poff[t]);
+#pragma unroll
+    for (int t = 0; t < Wn::NWT; ++t) {
+        const int k = gl + kGroupLanes * t;
+        pd.wt[t] = bload(wr, (ok && k < Wn::BB) ? 4u * (unsigned)(rec.w * Wn::BB + k) : kOutOfRange);
+    }
+}
+
+// Window into S[0, REG), box values into S[REG, REG + B*B).
+template <int B, int GX>
+__device__ __forceinline__ void store_region(float *S, const RPend<B, GX> &pd, int gl) {
+    using Wn = RWin<B, GX>;
+#pragma unroll
+    for (int t = 0; t < Wn::NT; ++t) {
+        const int k = gl + kGroupLanes * t;
+        if (t + 1 < Wn::NT || k < Wn::NSLOT)
+            *reinterpret_cast<float4 *>(S + (k / Wn::SX4) * Wn::SXP + 4 * (k % Wn::SX4)) = pd.v[t];
+    }
+#pragma unroll
+    for (int t = 0; t < Wn::NWT; ++t) {
+        const int k = gl + kGroupLanes * t;
+        if (k < Wn::BB) S[Wn::REG + k] = pd.wt[t];
+    }
+}
+
+// Region forward.  Workgroups walk the unit list (grid stride); a unit is a
+// chunk of the boxes meeting one FPA region of one frame (meta as the tile
+// list's, with the padded block's row pitch P in the third record).  A region
+// split into several units writes one partial region per unit to
+// `partials`; k_finish_regions sums them (next launch on the stream).
+template <int B, int GX>
+__global__ void __launch_bounds__(64 * kFwdMaxWaves) k_forward_region(
+    const int4 *__restrict__ meta, const int4 *__restrict__ items, const int stride, const int n_units,
+    const float *__restrict__ box_wf, const int n_wf, const float *__restrict__ fp, const int fp_floats,
+    const float *__restrict__ g, const float *__restrict__ uaux, float *__restrict__ out,
+    float *__restrict__ partials, const int mode) {
+    using Wn = RWin<B, GX>;
+    constexpr int RX = Wn::RX;
+    extern __shared__ float4 lds4[];
+    float *lds = reinterpret_cast<float *>(lds4);
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nw = blockDim.x >> 6;
+    const int gi = lane >> 4, gl = lane & 15, lx = gl % GX, ly = gl / GX;
+    float *S = lds + wv * Wn::WAVE + gi * Wn::GREG;
+    const __amdgpu_buffer_rsrc_t fr = rsrc(fp, fp_floats);
+    const __amdgpu_buffer_rsrc_t wr = rsrc(box_wf, n_wf);
+    const int tid = threadIdx.x, nt = blockDim.x;
+    constexpr int kOut = kRegion / 64;   // outputs per thread at one wave per workgroup
+
+    for (int unit = blockIdx.x; unit < n_units; unit += gridDim.x) {
+        const int4 *list = items + (size_t)unit * stride;
+        const int4 m0 = meta[3 * unit], m1 = meta[3 * unit + 1], m2 = meta[3 * unit + 2];
+        const int gamma = m1.z, xi = m1.w;
+        const int r0 = m0.x, c0 = m0.y;
+        const bool whole = m0.z == 1;
+        // byte offsets of this lane's window pieces from the window origin
+        unsigned poff[Wn::NT];
+#pragma unroll
+        for (int t = 0; t < Wn::NT; ++t) {
+            const int k = gl + kGroupLanes * t;
+            poff[t] = k < Wn::NSLOT ? 16u * (unsigned)(k % Wn::SX4) + 4u * (unsigned)m2.z * (unsigned)(k / Wn::SX4)
+                                    : 0u;
+        }
+        const int step = kGroups * nw;
+        int k = kGroups * wv + gi;
+        int4 rec0 = record(list, k, stride);
+        int4 rec1 = record(list, k + step, stride);
+
+        // operands of the epilogue (output o = tid + nt*j of the region), fetched up front
+        float gpre[kOut], upre[kOut];
+#pragma unroll
+        for (int j = 0; j < kOut; ++j) {
+            const int o = tid + nt * j;
+            const int r = r0 + o % RX, c = c0 + o / RX;
+            const bool in = o < kRegion && mode != kFwdPlain && whole && r < gamma && c < xi;
+            const size_t i = (size_t)r + (size_t)gamma * c;
+            gpre[j] = in ? g[(size_t)m2.x + i] : 0.0f;
+            upre[j] = (in && mode == kFwdVjp) ? uaux[(size_t)m2.y + i] : 0.0f;
+        }
+
+        float acc[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[a][q] = 0.0f;
+
+        // one window in flight per group: while the groups correlate their
+        // items, the windows of the wave's next four items are fetched (an
+        // empty record reads zeros); the work records run one pass further
+        // ahead.  Lists are padded with empty records, so a wave is done once
+        // its first group has none.
+        RPend<B, GX> pa;
+        load_region<B, GX>(pa, fr, wr, rec0, gl, poff);
+        if (__builtin_amdgcn_readfirstlane(rec0.w) >= 0) {
+            do {
+                store_region<B, GX>(S, pa, gl);
+                wave_lds_sync();
+                k += step;
+                const int4 rec3 = record(list, k + step, stride);
+                load_region<B, GX>(pa, fr, wr, rec1, gl, poff);
+                correlate<B, Wn::SXP, Wn::REG>(acc, S, lx, ly);
+                wave_lds_sync();
+                rec0 = rec1;
+                rec1 = rec3;
+            } while (__builtin_amdgcn_readfirstlane(rec0.w) >= 0);
+        }
+
+        // sum of the four groups (lanes l, l^16, l^32 and l^48 hold the same
+        // outputs): every group gets ((g0 + g1) + (g2 + g3))
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                float v = acc[a][q];
+                v += __shfl_xor(v, 16, 64);
+                v += __shfl_xor(v, 32, 64);
+                acc[a][q] = v;
+            }
+        // park the wave's region in LDS (group gi stores row gi of its
+        // lanes' micro-tiles), then sum the waves in order
+        __syncthreads();   // every wave is done with its windows
+        {
+            float4 row = make_float4(acc[0][0], acc[0][1], acc[0][2], acc[0][3]);
+#pragma unroll
+            for (int a = 1; a < 4; ++a)
+                if (gi == a) row = make_float4(acc[a][0], acc[a][1], acc[a][2], acc[a][3]);
+            *reinterpret_cast<float4 *>(lds + wv * Wn::WAVE + (4 * ly + gi) * RX + 4 * lx) = row;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kOut; ++j) {
+            const int o = tid + nt * j;
+            if (o >= kRegion) continue;
+            float v = 0.0f;
+            for (int w2 = 0; w2 < nw; ++w2) v += lds[w2 * Wn::WAVE + o];
+            if (!whole) {
+                partials[(size_t)m0.w * kRegion + o] = v;
+            } else {
+                const int r = r0 + o % RX, c = c0 + o / RX;
+                if (r < gamma && c < xi)
+                    out[(size_t)m2.y + (size_t)r + (size_t)gamma * c] = fwd_epilogue(mode, v, gpre[j], upre[j]);
+            }
+        }
+        __syncthreads();   // the next unit reuses the LDS regions
+    }
+}
+
+// Sum the partial regions (rx pixels wide) of every split FPA region in
+// chunk order and apply the forward epilogue.  One workgroup (a thread per
+// output) per split region.
+__global__ void __launch_bounds__(kRegion) k_finish_regions(const int4 *__restrict__ split_meta,
+                                                            const float *__restrict__ partials,
+                                                            const float *__restrict__ g,
+                                                            const float *__restrict__ uaux, float *__restrict__ out,
+                                                            int mode, int rx) {
+    const int o = threadIdx.x;
+    const int4 s0 = split_meta[2 * blockIdx.x], s1 = split_meta[2 * blockIdx.x + 1];
+    const int r = s0.x + o % rx, c = s0.y + o / rx;
+    if (r >= s1.x || c >= s1.y) return;
+    const size_t i = (size_t)r + (size_t)s1.x * c;
+    const float gv = mode != kFwdPlain ? g[(size_t)s1.z + i] : 0.0f;
+    const float uv = mode == kFwdVjp ? uaux[(size_t)s1.w + i] : 0.0f;
+    float v = 0.0f;
+    for (int ch = 0; ch < s0.z; ++ch) v += partials[((size_t)s0.w + ch) * kRegion + o];
+    out[(size_t)s1.w + i] = fwd_epilogue(mode, v, gv, uv);
+}
+
+// Zero-bordered copy of x for the region forward.  Block b = (x offset,
+// padded offset, a, alpha) of one (frame, wavelength); workgroup (row, b)
+// writes padded row `row` (rows 0 .. alpha + 2 hy - 1, pitch a + 2 hx):
+// element (X, Y) of the block, X in [-hx, a + hx), Y in [-hy, alpha + hy),
+// holds x_s(X, Y) inside the field stop and 0 outside.
+__global__ void __launch_bounds__(256) k_pad(const int4 *__restrict__ blocks, const float *__restrict__ x,
+                                             float *__restrict__ fp, const int hx, const int hy) {
+    const int4 bl = blocks[blockIdx.y];
+    const int a = bl.z, alpha = bl.w, P = a + 2 * hx;
+    const int row = blockIdx.x;
+    if (row >= alpha + 2 * hy) return;
+    const int Y = row - hy;
+    const bool yin = Y >= 0 && Y < alpha;
+    float *dst = fp + (size_t)bl.y + (size_t)P * row;
+    const float *src = x + (size_t)bl.x + (size_t)a * (yin ? Y : 0);
+    for (int e = threadIdx.x; e < P; e += blockDim.x) {
+        const int X = e - hx;
+        dst[e] = (yin && X >= 0 && X < a) ? src[X] : 0.0f;
+    }
+}
+
 // Back projection (+ EM update).  Units: (frame, wavelength, field-stop tile).
 template <int B>
 __global__ void __launch_bounds__(64 * Win<B>::MAXW) k_adjoint(const int4 *__restrict__ meta,
@@ -439,7 +702,8 @@ __global__ void __launch_bounds__(64 * Win<B>::MAXW) k_adjoint(const int4 *__res
                                                                const float *__restrict__ u, const float *in1,
                                                                const float *__restrict__ in2, float *out,
                                                                float *__restrict__ out2, float *__restrict__ flux,
-                                                               const int mode) {
+                                                               const int mode, float *__restrict__ fpad,
+                                                               const int hx, const int hy) {
     using Wn = Win<B>;
     extern __shared__ float4 lds4[];
     float *lds = reinterpret_cast<float *>(lds4);
@@ -486,7 +750,7 @@ __global__ void __launch_bounds__(64 * Win<B>::MAXW) k_adjoint(const int4 *__res
             k += nw;
             const int4 rec3 = record(list, k + nw, stride);
             if (rec1.w >= 0) load_adjoint<B>(pa, ur, box_w, geo, rec1.x + x0, rec1.y + y0, rec1.w, lane);
-            correlate<B>(acc, S, lx, ly);
+            correlate<B, Win<B>::SXP, Win<B>::REG>(acc, S, lx, ly);
             wave_lds_sync();
             rec0 = rec1;
             rec1 = rec3;
@@ -502,7 +766,11 @@ __global__ void __launch_bounds__(64 * Win<B>::MAXW) k_adjoint(const int4 *__res
                 if (mode == kAdjPlain) {
                     out[o] = v;
                 } else if (mode == kAdjUpdate) {
-                    out[o] = hs != 0.0f ? (p1[j] * v) / hs : 0.0f;
+                    const float nf = hs != 0.0f ? (p1[j] * v) / hs : 0.0f;
+                    out[o] = nf;
+                    // the padded copy of f the region forward reads (block offset
+                    // m2.y, row pitch m2.z)
+                    if (fpad) fpad[(size_t)m2.y + (size_t)(x + hx) + (size_t)m2.z * (size_t)(y + hy)] = nf;
                 } else if (mode == kAdjVjpPre) {
                     const float bj = hs != 0.0f ? (p1[j] * p2[j]) / hs : 0.0f;
                     out[o] = v;
@@ -781,6 +1049,75 @@ __global__ void __launch_bounds__(256) k_set_values(const float *__restrict__ va
     if (threadIdx.x == 0) hsum[gl] = (float)red[0];
 }
 
+// ---------------------------------------------------------------------------
+// EM diagnostics of one frame (Sec. 2: the column sums h below eq. (em) and
+// the Poisson likelihood EM increases, Shepp and Vardi): flux sum_j h_j f_j,
+// sum_i g_i, log-likelihood sum_i (g_i log ghat_i - ghat_i) with a g_i = 0
+// term contributing -ghat_i, and the count of pixels with g_i > 0 but
+// ghat_i <= 0 (the likelihood is then -inf).  Accumulated in double;
+// atomic-free and deterministic: every workgroup of k_diag_partial reduces a
+// fixed slice (thread-strided, then a fixed tree) into diag partial b, and
+// k_diag_final sums the partials in order.
+constexpr int kDiagBlocks = kDiagParts;
+
+__device__ __forceinline__ void block_sum4(double (&v)[4], double *red) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) red[4 * threadIdx.x + k] = v[k];
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) red[4 * threadIdx.x + k] += red[4 * (threadIdx.x + o) + k];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = red[k];
+}
+
+__global__ void __launch_bounds__(256) k_diag_partial(const float *__restrict__ g, const float *__restrict__ ghat,
+                                                      const float *__restrict__ f, const float *__restrict__ hsum,
+                                                      const long long n, const long long m, const long long ell,
+                                                      double *__restrict__ part) {
+    __shared__ double red[4 * 256];
+    const long long b = blockIdx.x, nb = gridDim.x;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};   // flux, sum g, log-likelihood, bad pixels
+    const long long p0 = n * b / nb, p1 = n * (b + 1) / nb;
+    for (long long i = p0 + threadIdx.x; i < p1; i += blockDim.x) {
+        const double gi = g[i], gh = ghat[i];
+        v[1] += gi;
+        if (gi > 0.0) {
+            if (gh > 0.0)
+                v[2] += gi * log(gh) - gh;
+            else
+                v[3] += 1.0;
+        } else {
+            v[2] -= gh;
+        }
+    }
+    const long long j0 = m * b / nb, j1 = m * (b + 1) / nb;
+    for (long long j = j0 + threadIdx.x; j < j1; j += blockDim.x) v[0] += (double)hsum[j / ell] * (double)f[j];
+    block_sum4(v, red);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) part[4 * b + k] = v[k];
+}
+
+__global__ void __launch_bounds__(256) k_diag_final(const double *__restrict__ part, const int nparts,
+                                                    double *__restrict__ out) {
+    __shared__ double red[4 * 256];
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int p = threadIdx.x; p < nparts; p += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] += part[4 * p + k];
+    block_sum4(v, red);
+    if (threadIdx.x == 0) {
+        out[0] = v[0];
+        out[1] = v[1];
+        out[2] = v[3] > 0.0 ? -HUGE_VAL : v[2];
+        out[3] = v[3];
+    }
+}
+
 template <int B>
 int enable_large_lds() {
     static std::once_flag once;
@@ -842,9 +1179,50 @@ int forward_B(const DevWork &w, const float *x, const float *g, const float *u, 
     return (int)hipGetLastError();
 }
 
+template <int B, int GX>
+int forward_region_B(const DevWork &w, const float *g, const float *u, float *out, int mode, void *workspace,
+                     hipStream_t st) {
+    const DevList &L = w.fwd_pad;
+    if (L.n_units == 0) return 0;
+    const size_t lds = (size_t)L.waves * RWin<B, GX>::WAVE * sizeof(float);
+    if (lds > 65536) {
+        static std::once_flag once;
+        static hipError_t err = hipSuccess;
+        std::call_once(once, []() {
+            err = hipFuncSetAttribute((const void *)k_forward_region<B, GX>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      RWin<B, GX>::MAXW * RWin<B, GX>::WAVE * (int)sizeof(float));
+        });
+        if (err != hipSuccess) return (int)err;
+    }
+    const float *fp = (const float *)((const char *)workspace + w.fp_off);
+    float *partials = w.n_rsplit > 0 ? (float *)((char *)workspace + w.rpartials_off) : nullptr;
+    hipLaunchKernelGGL((k_forward_region<B, GX>), dim3(grid_for(L.n_units, lds, L.waves, w.persistent)),
+                       dim3(64 * L.waves), lds, st, L.meta, L.items, L.stride, L.n_units, w.box_wf, w.n_wf, fp,
+                       w.fp_floats, g, u, out, partials, mode);
+    if (partials) {
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return (int)e;
+        hipLaunchKernelGGL(k_finish_regions, dim3(w.n_rsplit), dim3(kRegion), 0, st, w.rsplit_meta,
+                           (const float *)partials, g, u, out, mode, RWin<B, GX>::RX);
+    }
+    return (int)hipGetLastError();
+}
+
+template <int B>
+int forward_region_gx(const DevWork &w, const float *g, const float *u, float *out, int mode, void *workspace,
+                      hipStream_t st) {
+    switch (w.region_gx) {
+        case 2: return forward_region_B<B, 2>(w, g, u, out, mode, workspace, st);
+        case 4: return forward_region_B<B, 4>(w, g, u, out, mode, workspace, st);
+        case 8: return forward_region_B<B, 8>(w, g, u, out, mode, workspace, st);
+    }
+    return (int)hipErrorInvalidValue;
+}
+
 template <int B>
 int adjoint_B(const DevWork &w, const float *r, const float *in1, const float *in2, float *out, float *out2,
-              float *flux, int mode, hipStream_t st) {
+              float *flux, int mode, hipStream_t st, float *fpad) {
     const DevList &L = w.adj;
     if (L.n_units == 0) return 0;
     const size_t lds = (size_t)L.waves * Win<B>::WREG * sizeof(float);
@@ -853,7 +1231,8 @@ int adjoint_B(const DevWork &w, const float *r, const float *in1, const float *i
         if (e) return e;
     }
     hipLaunchKernelGGL(k_adjoint<B>, dim3(grid_for(L.n_units, lds, L.waves, w.persistent)), dim3(64 * L.waves), lds, st,
-                       L.meta, L.items, L.stride, L.n_units, w.box_w, w.h, r, in1, in2, out, out2, flux, mode);
+                       L.meta, L.items, L.stride, L.n_units, w.box_w, w.h, r, in1, in2, out, out2, flux, mode, fpad,
+                       w.halo_x, w.halo_y);
     return (int)hipGetLastError();
 }
 
@@ -891,17 +1270,43 @@ int launch_forward(const DevWork &w, const float *x, const float *g, const float
 }
 
 int launch_adjoint(const DevWork &w, const float *r, const float *in1, const float *in2, float *out, float *out2,
-                   float *flux, int mode, void *stream) {
+                   float *flux, int mode, void *stream, void *fpad_ws) {
+    hipStream_t st = (hipStream_t)stream;
+    float *fpad = (fpad_ws && mode == kAdjUpdate && w.pad_ok) ? (float *)((char *)fpad_ws + w.fp_off) : nullptr;
+    switch (w.B) {
+        case 1: return adjoint_B<1>(w, r, in1, in2, out, out2, flux, mode, st, fpad);
+        case 2: return adjoint_B<2>(w, r, in1, in2, out, out2, flux, mode, st, fpad);
+        case 3: return adjoint_B<3>(w, r, in1, in2, out, out2, flux, mode, st, fpad);
+        case 4: return adjoint_B<4>(w, r, in1, in2, out, out2, flux, mode, st, fpad);
+        case 5: return adjoint_B<5>(w, r, in1, in2, out, out2, flux, mode, st, fpad);
+        case 6: return adjoint_B<6>(w, r, in1, in2, out, out2, flux, mode, st, fpad);
+        case 7: return adjoint_B<7>(w, r, in1, in2, out, out2, flux, mode, st, fpad);
+        case 8: return adjoint_B<8>(w, r, in1, in2, out, out2, flux, mode, st, fpad);
+    }
+    return (int)hipErrorInvalidValue;
+}
+
+int launch_pad(const DevWork &w, const float *x, void *workspace, void *stream) {
+    if (!w.pad_ok || w.n_pad_blocks == 0) return (int)hipErrorInvalidValue;
+    float *fp = (float *)((char *)workspace + w.fp_off);
+    hipLaunchKernelGGL(k_pad, dim3((unsigned)w.pad_rows, (unsigned)w.n_pad_blocks), dim3(256), 0,
+                       (hipStream_t)stream, w.pad_blocks, x, fp, w.halo_x, w.halo_y);
+    return (int)hipGetLastError();
+}
+
+int launch_forward_pad(const DevWork &w, const float *g, const float *u, float *out, int mode, void *workspace,
+                       void *stream) {
+    if (!w.pad_ok) return (int)hipErrorInvalidValue;
     hipStream_t st = (hipStream_t)stream;
     switch (w.B) {
-        case 1: return adjoint_B<1>(w, r, in1, in2, out, out2, flux, mode, st);
-        case 2: return adjoint_B<2>(w, r, in1, in2, out, out2, flux, mode, st);
-        case 3: return adjoint_B<3>(w, r, in1, in2, out, out2, flux, mode, st);
-        case 4: return adjoint_B<4>(w, r, in1, in2, out, out2, flux, mode, st);
-        case 5: return adjoint_B<5>(w, r, in1, in2, out, out2, flux, mode, st);
-        case 6: return adjoint_B<6>(w, r, in1, in2, out, out2, flux, mode, st);
-        case 7: return adjoint_B<7>(w, r, in1, in2, out, out2, flux, mode, st);
-        case 8: return adjoint_B<8>(w, r, in1, in2, out, out2, flux, mode, st);
+        case 1: return forward_region_gx<1>(w, g, u, out, mode, workspace, st);
+        case 2: return forward_region_gx<2>(w, g, u, out, mode, workspace, st);
+        case 3: return forward_region_gx<3>(w, g, u, out, mode, workspace, st);
+        case 4: return forward_region_gx<4>(w, g, u, out, mode, workspace, st);
+        case 5: return forward_region_gx<5>(w, g, u, out, mode, workspace, st);
+        case 6: return forward_region_gx<6>(w, g, u, out, mode, workspace, st);
+        case 7: return forward_region_gx<7>(w, g, u, out, mode, workspace, st);
+        case 8: return forward_region_gx<8>(w, g, u, out, mode, workspace, st);
     }
     return (int)hipErrorInvalidValue;
 }
@@ -929,6 +1334,17 @@ int launch_value_finish(const DevWork &w, const float *part, const float *flux, 
     hipLaunchKernelGGL(k_value_finish, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, w.entry_slot,
                        w.box_lam, w.lam_box0, w.lam_units_ptr, w.lam_units, w.adj.stride, w.B * w.B, part, flux,
                        (const float *)w.h, dv, (long long)entry0, (long long)n_entries, accumulate ? 1 : 0);
+    return (int)hipGetLastError();
+}
+
+int launch_diagnostics(const float *g, const float *ghat, const float *f, const float *hsum, int64_t n, int64_t m,
+                       int64_t ell, double *part, double *out, void *stream) {
+    hipLaunchKernelGGL(k_diag_partial, dim3(kDiagBlocks), dim3(256), 0, (hipStream_t)stream, g, ghat, f, hsum,
+                       (long long)n, (long long)m, (long long)ell, part);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return (int)e;
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, (hipStream_t)stream, (const double *)part, kDiagBlocks,
+                       out);
     return (int)hipGetLastError();
 }
 

@@ -104,6 +104,11 @@ std::vector<std::pair<int32_t, int32_t>> cells(const Component &cp, const std::v
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+int64_t floor_mod(int64_t a, int64_t b) {
+    const int64_t r = a % b;
+    return r < 0 ? r + b : r;
+}
+
 // count of set entries of the circular sliding OR along a sequence
 // get(k), k in [0, len), window `win` ending at k (k - win + 1 .. k, mod len)
 template <class Get, class Set>
@@ -120,8 +125,75 @@ void circular_window_or(int64_t len, int64_t win, Get get, Set set) {
 
 }  // namespace
 
+// Forward work list on a grid of tf x ts FPA cells: the cells met by the
+// dilated image of every box, i.e. the pixels (A + X + gamma*Y) mod n for X <
+// a + B - 1, Y < alpha + B - 1 (the exact 1-D shift, including runs that
+// continue in the next FPA column or wrap round the FPA).
+ctis_status build_grid(HostTables &T, const ctis_plan *p, int32_t tf, int32_t ts, WorkGrid &G) {
+    const int64_t gamma = p->gamma, xi = p->xi;
+    const int B = T.B;
+    G = WorkGrid{};
+    G.tf = tf;
+    G.ts = ts;
+    const int64_t ntr = ceil_div(gamma, tf), ntc = ceil_div(xi, ts);
+    if (ntr * ntc > INT32_MAX) return fail(CTIS_E_TOO_LARGE, "too many FPA cells");
+    G.ntr = (int32_t)ntr;
+    G.ntc = (int32_t)ntc;
+    G.n_cells = (int32_t)(ntr * ntc);
+    const int32_t nb = (int32_t)T.box_lambda.size();
+    std::vector<int32_t> stamp((size_t)G.n_cells, -1);
+    std::vector<std::pair<int32_t, int32_t>> pairs;   // (cell, box)
+    const int64_t L0 = (int64_t)p->a + B - 1, rows = (int64_t)p->alpha + B - 1;
+    for (int32_t b = 0; b < nb; ++b) {
+        const int32_t rA = T.box_rc[2 * (size_t)b], cA = T.box_rc[2 * (size_t)b + 1];
+        for (int64_t Y = 0; Y < rows; ++Y) {
+            // pixels (A + X + gamma*Y) mod n, X in [0, L0): a run along the fast
+            // axis starting at (rA, cA + Y), continuing in the next FPA column
+            int64_t r = rA, c = (cA + Y) % xi, L = L0;
+            while (L > 0) {
+                const int64_t seg = std::min<int64_t>(L, gamma - r);
+                const int64_t tc = c / ts;
+                for (int64_t tr = r / tf; tr <= (r + seg - 1) / tf; ++tr) {
+                    const int32_t cell = (int32_t)(tr + ntr * tc);
+                    if (stamp[(size_t)cell] != b) {
+                        stamp[(size_t)cell] = b;
+                        pairs.emplace_back(cell, b);
+                    }
+                }
+                L -= seg;
+                r = 0;
+                c = (c + 1) % xi;
+            }
+        }
+    }
+    if ((int64_t)pairs.size() > INT32_MAX) return fail(CTIS_E_TOO_LARGE, "forward work list too long");
+    std::sort(pairs.begin(), pairs.end());
+    G.item_ptr.assign((size_t)G.n_cells + 1, 0);
+    G.item_box.resize(pairs.size());
+    for (size_t k = 0; k < pairs.size(); ++k) {
+        G.item_ptr[(size_t)pairs[k].first + 1]++;
+        G.item_box[k] = pairs[k].second;
+    }
+    for (int32_t t = 0; t < G.n_cells; ++t) G.item_ptr[(size_t)t + 1] += G.item_ptr[(size_t)t];
+    G.order.resize((size_t)G.n_cells);
+    std::iota(G.order.begin(), G.order.end(), 0);
+    auto count = [&](int32_t t) { return G.item_ptr[(size_t)t + 1] - G.item_ptr[(size_t)t]; };
+    std::stable_sort(G.order.begin(), G.order.end(), [&](int32_t x, int32_t y) { return count(x) > count(y); });
+    int64_t active_items = 0;
+    for (int32_t t = 0; t < G.n_cells; ++t) {
+        G.n_active += count(t) > 0;
+        G.max_items = std::max(G.max_items, count(t));
+        active_items += count(t);
+    }
+    // EM chunk: a cell is split over several workgroups only when it holds
+    // more than 64 boxes and more than twice the boxes an average compute
+    // unit gets (256 CUs); otherwise splitting only adds the partial pass
+    G.chunk = (int32_t)std::max<int64_t>(64, 2 * ((active_items + 255) / 256));
+    return CTIS_OK;
+}
+
 ctis_status build_host_tables(ctis_plan *p, const int64_t *lambda_ptr, const int32_t *fpa_index,
-                              const float *value, int forced_box, bool keep_zeros) {
+                              const float *value, int forced_box, bool keep_zeros, int region_gx) {
     HostTables &T = p->ht;
     const int32_t w = p->w, gamma = p->gamma, xi = p->xi, a = p->a, alpha = p->alpha;
     const int64_t n = p->n;
@@ -235,7 +307,6 @@ ctis_status build_host_tables(ctis_plan *p, const int64_t *lambda_ptr, const int
         for (int64_t t = lambda_ptr[s]; t < lambda_ptr[s + 1]; ++t)
             if (in_merged[(size_t)t] >= 0) T.entry_slot[(size_t)t] = (int32_t)merged_slot[(size_t)in_merged[(size_t)t]];
     }
-    const int32_t nb = (int32_t)T.box_lambda.size();
 
     // -- 4. column sums per wavelength (sum of c_s, in double) ------------------
     T.h.assign((size_t)w, 0.0f);
@@ -262,74 +333,24 @@ ctis_status build_host_tables(ctis_plan *p, const int64_t *lambda_ptr, const int
         T.n_support = cnt;
     }
 
-    // -- 6. forward work list: FPA tiles met by each box's dilated image --------
-    const int64_t ntr = ceil_div(gamma, kTileFast), ntc = ceil_div(xi, kTileSlow);
-    if (ntr * ntc > INT32_MAX) return fail(CTIS_E_TOO_LARGE, "too many FPA tiles");
-    T.ntr = (int32_t)ntr;
-    T.ntc = (int32_t)ntc;
-    T.n_tiles = (int32_t)(ntr * ntc);
-    std::vector<int32_t> stamp((size_t)T.n_tiles, -1);
-    std::vector<std::pair<int32_t, int32_t>> pairs;   // (tile, box)
-    const int64_t L0 = (int64_t)a + B - 1, rows = (int64_t)alpha + B - 1;
-    for (int32_t b = 0; b < nb; ++b) {
-        const int32_t rA = T.box_rc[2 * (size_t)b], cA = T.box_rc[2 * (size_t)b + 1];
-        for (int64_t Y = 0; Y < rows; ++Y) {
-            // pixels (A + X + gamma*Y) mod n, X in [0, L0): a run along the fast
-            // axis starting at (rA, cA + Y), continuing in the next FPA column
-            int64_t r = rA, c = (cA + Y) % xi, L = L0;
-            while (L > 0) {
-                const int64_t seg = std::min<int64_t>(L, gamma - r);
-                const int64_t tc = c / kTileSlow;
-                for (int64_t tr = r / kTileFast; tr <= (r + seg - 1) / kTileFast; ++tr) {
-                    const int32_t tile = (int32_t)(tr + ntr * tc);
-                    if (stamp[(size_t)tile] != b) {
-                        stamp[(size_t)tile] = b;
-                        pairs.emplace_back(tile, b);
-                    }
-                }
-                L -= seg;
-                r = 0;
-                c = (c + 1) % xi;
-            }
-        }
-    }
-    if ((int64_t)pairs.size() > INT32_MAX) return fail(CTIS_E_TOO_LARGE, "forward work list too long");
-    std::sort(pairs.begin(), pairs.end());
-    T.tile_item_ptr.assign((size_t)T.n_tiles + 1, 0);
-    T.item_box.resize(pairs.size());
-    for (size_t k = 0; k < pairs.size(); ++k) {
-        T.tile_item_ptr[(size_t)pairs[k].first + 1]++;
-        T.item_box[k] = pairs[k].second;
-    }
-    for (int32_t t = 0; t < T.n_tiles; ++t) T.tile_item_ptr[(size_t)t + 1] += T.tile_item_ptr[(size_t)t];
-    T.tile_order.resize((size_t)T.n_tiles);
-    std::iota(T.tile_order.begin(), T.tile_order.end(), 0);
-    auto count = [&](int32_t t) { return T.tile_item_ptr[(size_t)t + 1] - T.tile_item_ptr[(size_t)t]; };
-    std::stable_sort(T.tile_order.begin(), T.tile_order.end(),
-                     [&](int32_t x, int32_t y) { return count(x) > count(y); });
-    T.n_active = 0;
-    for (int32_t t = 0; t < T.n_tiles; ++t) T.n_active += count(t) > 0;
+    // -- 6. forward work lists: FPA tiles and regions met by each box's dilated
+    //       image, and whether the region path's padded copy of f is exact --
+    ctis_status st = build_grid(T, p, kTileFast, kTileSlow, T.tiles);
+    if (st != CTIS_OK) return st;
+    T.region_gx = region_gx ? region_gx : 4;
+    st = build_grid(T, p, region_fast(T.region_gx), region_slow(T.region_gx), T.regions);
+    if (st != CTIS_OK) return st;
+    T.pad_ok = (int64_t)gamma - a >= halo_fast(T.region_gx, B) && (int64_t)xi - alpha >= halo_slow(T.region_gx, B);
 
     // -- 7. field-stop tiling of the back projection ----------------------------
     T.nbx = (int32_t)ceil_div(a, kTileFast);
     T.nby = (int32_t)ceil_div(alpha, kTileSlow);
     if ((int64_t)T.nbx * T.nby * w > INT32_MAX) return fail(CTIS_E_TOO_LARGE, "too many field-stop tiles");
 
-    int32_t max_boxes = 0, max_items = 0;
-    int64_t active_items = 0;
+    int32_t max_boxes = 0;
     for (int32_t s = 0; s < w; ++s)
         max_boxes = std::max(max_boxes, T.lambda_box_ptr[(size_t)s + 1] - T.lambda_box_ptr[(size_t)s]);
-    for (int32_t t = 0; t < T.n_tiles; ++t) {
-        max_items = std::max(max_items, count(t));
-        active_items += count(t);
-    }
-    T.max_items = max_items;
     T.max_boxes = max_boxes;
-    // EM chunk: a tile is split over several workgroups only when it holds
-    // more than 64 boxes (4 per wave) and more than twice the boxes an
-    // average compute unit gets (256 CUs); otherwise splitting only adds the
-    // partial-tile pass
-    T.chunk = (int32_t)std::max<int64_t>(64, 2 * ((active_items + 255) / 256));
     return CTIS_OK;
 }
 
@@ -365,6 +386,17 @@ int32_t forward_waves(int64_t units, int64_t items, int32_t max_items, int B) {
     if (units <= kChipCUs) return waves_for(max_items, B);
     const int64_t avg = units > 0 ? (items + units / 2) / units : 0;
     return std::max(min_waves(), std::min<int32_t>(max_waves(B), (int32_t)((avg + 2) / 4)));
+}
+
+// Region forward: a wave takes four boxes of its region at a time (one per
+// lane group), so a workgroup of W waves takes 4W per pass.  About one wave
+// per five boxes of the average unit, 1 to 4: more waves per workgroup leave
+// fewer workgroups resident per compute unit (measured on the 512^2 and
+// 1024^2 frames with 15 and 46 boxes per region: 3 and 4 waves best, 5 or
+// more a third slower).
+int32_t region_waves(int64_t units, int64_t items) {
+    const int64_t avg = units > 0 ? (items + units - 1) / units : 0;
+    return (int32_t)std::max<int64_t>(1, std::min<int64_t>(4, (avg + 4) / 5));
 }
 
 void push4(std::vector<int32_t> &v, int32_t a, int32_t b, int32_t c, int32_t d) {
@@ -466,8 +498,6 @@ ctis_status build_work(const std::vector<FrameRef> &frames, bool with_full, Host
             hw.h.insert(hw.h.end(), T.h.begin(), T.h.end());
             hw.dropped = hw.dropped || T.dropped;
         }
-        max_chunk_items = std::max(max_chunk_items, std::min(T.max_items, T.chunk));
-        max_full_items = std::max(max_full_items, T.max_items);
         max_boxes = std::max(max_boxes, T.max_boxes);
         hw.u_floats = std::max<int64_t>(hw.u_floats, frames[k].u_base + pl->n);
         hw.f_floats = std::max<int64_t>(hw.f_floats, frames[k].f_base + pl->m);
@@ -478,23 +508,47 @@ ctis_status build_work(const std::vector<FrameRef> &frames, bool with_full, Host
         flam[k] = hw.plan_lam0[(size_t)hw.frame_plan[k]];
     }
 
-    // forward lists: units of every frame, heaviest first (a stable order)
-    auto build_fwd = [&](HostList &L, bool em, int32_t stride) -> ctis_status {
+    // padded copy of f for the region path: per frame and wavelength a block
+    // of (a + 2 Hx) x (alpha + 2 Hy) floats, frames back to back.  The path
+    // needs every frame to allow it, with one region shape.
+    const int gx = frames[0].plan->ht.region_gx;
+    const int Hx = halo_fast(gx, B), Hy = halo_slow(gx, B);
+    hw.region_gx = gx;
+    hw.halo_x = Hx;
+    hw.halo_y = Hy;
+    std::vector<int64_t> fp_base(frames.size(), 0);
+    hw.pad_ok = true;
+    for (size_t k = 0; k < frames.size(); ++k) {
+        const ctis_plan *pl = frames[k].plan;
+        hw.pad_ok = hw.pad_ok && pl->ht.pad_ok && pl->ht.region_gx == gx;
+        fp_base[k] = hw.fp_floats;
+        hw.fp_floats += (int64_t)pl->w * (pl->a + 2 * Hx) * (pl->alpha + 2 * Hy);
+        hw.pad_rows = std::max(hw.pad_rows, pl->alpha + 2 * Hy);
+    }
+    if (hw.fp_floats > kMaxPixels) hw.pad_ok = false;
+
+    // forward lists: units of every frame, heaviest first (a stable order).
+    // Tile records (tile path): (window origin Xs, Ys, f offset of the box's
+    // wavelength block, global box).  Region records (region path): (float
+    // offset of the window origin in the padded copy, 0, 0, global box).
+    auto build_fwd = [&](HostList &L, bool region, bool em, int32_t stride, std::vector<int32_t> &smeta,
+                         int32_t &n_split, int32_t &slots) -> ctis_status {
         std::vector<UnitRef> units;
         for (size_t k = 0; k < frames.size(); ++k) {
             const HostTables &T = frames[k].plan->ht;
-            const int32_t ntl = em ? T.n_active : T.n_tiles;
+            const WorkGrid &G = region ? T.regions : T.tiles;
+            const int32_t ntl = em ? G.n_active : G.n_cells;
             for (int32_t u = 0; u < ntl; ++u) {
-                const int32_t tile = T.tile_order[(size_t)u];
-                const int32_t cnt = T.tile_item_ptr[(size_t)tile + 1] - T.tile_item_ptr[(size_t)tile];
+                const int32_t tile = G.order[(size_t)u];
+                const int32_t cnt = G.item_ptr[(size_t)tile + 1] - G.item_ptr[(size_t)tile];
                 const int32_t nch = em ? std::max(1, (cnt + stride - 1) / stride) : 1;
-                const int32_t slot0 = nch > 1 ? hw.partial_slots : -1;
+                const int32_t slot0 = nch > 1 ? slots : -1;
                 if (nch > 1) {
-                    push4(hw.split_meta, (tile % T.ntr) * kTileFast, (tile / T.ntr) * kTileSlow, nch, slot0);
-                    push4(hw.split_meta, frames[k].plan->gamma, frames[k].plan->xi, (int32_t)frames[k].g_base,
+                    push4(smeta, (tile % G.ntr) * G.tf, (tile / G.ntr) * G.ts, nch, slot0);
+                    push4(smeta, frames[k].plan->gamma, frames[k].plan->xi, (int32_t)frames[k].g_base,
                           (int32_t)frames[k].u_base);
-                    hw.partial_slots += nch;
-                    hw.n_split++;
+                    slots += nch;
+                    n_split++;
                 }
                 for (int32_t c = 0; c < nch; ++c)
                     units.push_back(UnitRef{(int32_t)k, tile, c, nch, nch > 1 ? slot0 + c : -1,
@@ -511,30 +565,67 @@ ctis_status build_work(const std::vector<FrameRef> &frames, bool with_full, Host
             const FrameRef &fr = frames[(size_t)ur.frame];
             const ctis_plan *pl = fr.plan;
             const HostTables &T = pl->ht;
-            const int32_t r0 = (ur.tile % T.ntr) * kTileFast, c0 = (ur.tile / T.ntr) * kTileSlow;
+            const WorkGrid &G = region ? T.regions : T.tiles;
+            const int32_t r0 = (ur.tile % G.ntr) * G.tf, c0 = (ur.tile / G.ntr) * G.ts;
+            const int64_t P = (int64_t)pl->a + 2 * Hx, PB = P * ((int64_t)pl->alpha + 2 * Hy);
             push4(L.meta, r0, c0, ur.n_chunks, ur.slot);
             push4(L.meta, pl->a, pl->alpha, pl->gamma, pl->xi);
-            push4(L.meta, (int32_t)fr.g_base, em ? (int32_t)fr.u_base : (int32_t)fr.g_base, 0, 0);
-            const int32_t b0 = T.tile_item_ptr[(size_t)ur.tile];
-            const int32_t cnt = T.tile_item_ptr[(size_t)ur.tile + 1] - b0;
+            push4(L.meta, (int32_t)fr.g_base, em ? (int32_t)fr.u_base : (int32_t)fr.g_base, region ? (int32_t)P : 0, 0);
+            const int32_t b0 = G.item_ptr[(size_t)ur.tile];
+            const int32_t cnt = G.item_ptr[(size_t)ur.tile + 1] - b0;
             for (int32_t k = 0; k < L.stride; ++k) {
                 const int32_t idx = ur.chunk * L.stride + k;
-                if (k < ur.work && idx < cnt) {
-                    const int32_t b = T.item_box[(size_t)(b0 + idx)];
-                    const int32_t s = T.box_lambda[(size_t)b];
-                    push4(L.items, r0 - (B - 1) - T.box_rc[2 * (size_t)b], c0 - (B - 1) - T.box_rc[2 * (size_t)b + 1],
-                          (int32_t)(fr.f_base + (int64_t)s * pl->ell), fbox[(size_t)ur.frame] + b);
-                } else {
+                if (!(k < ur.work && idx < cnt)) {
                     push4(L.items, 0, 0, 0, -1);
+                    continue;
                 }
+                const int32_t b = G.item_box[(size_t)(b0 + idx)];
+                const int32_t s = T.box_lambda[(size_t)b];
+                const int64_t Xs = (int64_t)r0 - (B - 1) - T.box_rc[2 * (size_t)b];
+                const int64_t Ys = (int64_t)c0 - (B - 1) - T.box_rc[2 * (size_t)b + 1];
+                if (!region) {
+                    push4(L.items, (int32_t)Xs, (int32_t)Ys, (int32_t)(fr.f_base + (int64_t)s * pl->ell),
+                          fbox[(size_t)ur.frame] + b);
+                    continue;
+                }
+                // The window's slot (xx, yy) holds fE((Xs + xx) + gamma*(Ys + yy) mod n).
+                // Write its origin as X + gamma*Y with X in [-Hx, a) and Y in [-Hy,
+                // alpha): the window then lies inside the padded block, whose value
+                // at (X', Y') is fE(X' + gamma*Y' mod n) because the FPA leaves Hx
+                // and Hy pixels beside the field stop.  From the canonical origin
+                // (qf, qs): X = qf, or qf - gamma with qs + 1 if the window starts
+                // within Hx of the FPA's last row; likewise Y = qs or qs - xi.  (A
+                // window meeting the image of its box holds a voxel of the field
+                // stop, so one of the two fits.)
+                const int64_t q = floor_mod(Xs + (int64_t)pl->gamma * Ys, pl->n);
+                int64_t X = q % pl->gamma, Y = q / pl->gamma;
+                if (X >= pl->a) {
+                    if (X < (int64_t)pl->gamma - Hx) return fail(CTIS_E_ARG, "region window outside the field stop");
+                    X -= pl->gamma;
+                    Y = (Y + 1) % pl->xi;
+                }
+                if (Y >= pl->alpha) {
+                    if (Y < (int64_t)pl->xi - Hy) return fail(CTIS_E_ARG, "region window outside the field stop");
+                    Y -= pl->xi;
+                }
+                const int64_t poff = fp_base[(size_t)ur.frame] + (int64_t)s * PB + (X + Hx) + P * (Y + Hy);
+                push4(L.items, (int32_t)poff, 0, 0, fbox[(size_t)ur.frame] + b);
             }
             if (L.items.size() > (size_t)INT32_MAX) return fail(CTIS_E_TOO_LARGE, "forward work list too large");
         }
         L.n_units = (int32_t)(L.meta.size() / 12);
         return CTIS_OK;
     };
-    int32_t chunk = 1 << 30;
-    for (const FrameRef &fr : frames) chunk = std::min(chunk, fr.plan->ht.chunk);
+    int32_t chunk = 1 << 30, rchunk = 1 << 30;
+    for (const FrameRef &fr : frames) {
+        chunk = std::min(chunk, fr.plan->ht.tiles.chunk);
+        rchunk = std::min(rchunk, fr.plan->ht.regions.chunk);
+    }
+    for (const FrameRef &fr : frames) {
+        const HostTables &T = fr.plan->ht;
+        max_chunk_items = std::max(max_chunk_items, std::min(T.tiles.max_items, chunk));
+        max_full_items = std::max(max_full_items, T.tiles.max_items);
+    }
     auto count_items = [](const HostList &L) {
         int64_t n = 0;
         for (size_t k = 3; k < L.items.size(); k += 4) n += L.items[k] >= 0;
@@ -542,16 +633,27 @@ ctis_status build_work(const std::vector<FrameRef> &frames, bool with_full, Host
     };
     ctis_status st = CTIS_OK;
     if (with_full) {
-        const int32_t saved_slots = hw.partial_slots, saved_split = hw.n_split;
-        st = build_fwd(hw.fwd_full, false, std::max(1, max_full_items));
+        std::vector<int32_t> no_split;
+        int32_t n0 = 0, s0 = 0;
+        st = build_fwd(hw.fwd_full, false, false, std::max(1, max_full_items), no_split, n0, s0);
         if (st != CTIS_OK) return st;
-        hw.partial_slots = saved_slots;
-        hw.n_split = saved_split;
         hw.fwd_full.waves = forward_waves(hw.fwd_full.n_units, count_items(hw.fwd_full), max_full_items, B);
     }
-    st = build_fwd(hw.fwd_em, true, chunk);
+    st = build_fwd(hw.fwd_em, false, true, chunk, hw.split_meta, hw.n_split, hw.partial_slots);
     if (st != CTIS_OK) return st;
     hw.fwd_em.waves = forward_waves(hw.fwd_em.n_units, count_items(hw.fwd_em), max_chunk_items, B);
+    if (hw.pad_ok) {
+        st = build_fwd(hw.fwd_pad, true, true, rchunk, hw.rsplit_meta, hw.n_rsplit, hw.rpartial_slots);
+        if (st != CTIS_OK) return st;
+        hw.fwd_pad.waves = region_waves(hw.fwd_pad.n_units, count_items(hw.fwd_pad));
+        for (size_t k = 0; k < frames.size(); ++k) {
+            const ctis_plan *pl = frames[k].plan;
+            const int64_t PB = (int64_t)(pl->a + 2 * Hx) * (pl->alpha + 2 * Hy);
+            for (int32_t s = 0; s < pl->w; ++s)
+                push4(hw.pad_blocks, (int32_t)(frames[k].f_base + (int64_t)s * pl->ell),
+                      (int32_t)(fp_base[k] + (int64_t)s * PB), pl->a, pl->alpha);
+        }
+    }
 
     // adjoint: units (frame, wavelength, field-stop tile); records per global wavelength
     HostList &A = hw.adj;
@@ -601,7 +703,9 @@ ctis_status build_work(const std::vector<FrameRef> &frames, bool with_full, Host
         push4(A.meta, (au.vt % T.nbx) * kTileFast, (au.vt / T.nbx) * kTileSlow, gs,
               (int32_t)(fr.f_base + (int64_t)au.s * pl->ell));
         push4(A.meta, pl->a, pl->alpha, pl->gamma, pl->xi);
-        push4(A.meta, (int32_t)fr.u_base, 0, 0, 0);
+        const int64_t P = (int64_t)pl->a + 2 * Hx, PB = P * ((int64_t)pl->alpha + 2 * Hy);
+        push4(A.meta, (int32_t)fr.u_base, hw.pad_ok ? (int32_t)(fp_base[(size_t)au.frame] + (int64_t)au.s * PB) : 0,
+              hw.pad_ok ? (int32_t)P : 0, 0);
     }
     A.n_units = (int32_t)(A.meta.size() / 12);
     A.waves = adjoint_waves(A.n_units, max_boxes, B);
@@ -641,7 +745,10 @@ Layout layout_for(const HostWork &hw) {
     auto up256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
     Layout L{};
     L.partials_off = up256((size_t)hw.u_floats * sizeof(float));
-    L.em_bytes = L.partials_off + (size_t)hw.partial_slots * kTileFast * kTileSlow * sizeof(float);
+    L.rpartials_off = L.partials_off + up256((size_t)hw.partial_slots * kTileFast * kTileSlow * sizeof(float));
+    L.fp_off = L.rpartials_off + up256((size_t)hw.rpartial_slots * kRegionPixels * sizeof(float));
+    L.diag_off = L.fp_off + up256(hw.pad_ok ? (size_t)hw.fp_floats * sizeof(float) : 0);
+    L.em_bytes = L.diag_off + (size_t)kDiagParts * 4 * sizeof(double);
     L.e_off = up256(L.em_bytes);
     L.zeta_off = L.e_off + up256((size_t)hw.u_floats * sizeof(float));
     L.b_off = L.zeta_off + up256((size_t)hw.f_floats * sizeof(float));
@@ -675,6 +782,10 @@ ctis_status upload_work(const HostWork &hw, DevWork &dw) {
         {hw.lam_units.data(), hw.lam_units.size() * 4, 0},
         {hw.slot_entries_ptr.data(), hw.slot_entries_ptr.size() * 4, 0},
         {hw.slot_entries.data(), hw.slot_entries.size() * 4, 0},
+        {hw.fwd_pad.meta.data(), hw.fwd_pad.meta.size() * 4, 0},
+        {hw.fwd_pad.items.data(), hw.fwd_pad.items.size() * 4, 0},
+        {hw.rsplit_meta.data(), hw.rsplit_meta.size() * 4, 0},
+        {hw.pad_blocks.data(), hw.pad_blocks.size() * 4, 0},
     };
     size_t total = 0;
     for (auto &pt : parts) {
@@ -721,11 +832,29 @@ ctis_status upload_work(const HostWork &hw, DevWork &dw) {
     dw.lam_units = (const int32_t *)at(14);
     dw.slot_entries_ptr = (const int32_t *)at(15);
     dw.slot_entries = (const int32_t *)at(16);
+    dw.pad_ok = hw.pad_ok;
+    dw.region_gx = hw.region_gx;
+    dw.halo_x = hw.halo_x;
+    dw.halo_y = hw.halo_y;
+    if (hw.pad_ok) {
+        list(dw.fwd_pad, hw.fwd_pad, 17);
+        dw.rsplit_meta = (const int4 *)at(19);
+        dw.n_rsplit = hw.n_rsplit;
+        dw.pad_blocks = (const int4 *)at(20);
+        dw.n_pad_blocks = (int32_t)(hw.pad_blocks.size() / 4);
+        dw.pad_rows = hw.pad_rows;
+        dw.fp_floats = (int32_t)hw.fp_floats;
+    }
+    dw.f_floats = (int32_t)hw.f_floats;
+    dw.n_wf = (int32_t)hw.box_wf.size();
     dw.n_entries = (int64_t)hw.entry_slot.size();
     dw.n_lambda = (int32_t)hw.h.size();
     dw.n_boxes = (int32_t)hw.box_lam.size();
     const Layout L = layout_for(hw);
     dw.partials_off = L.partials_off;
+    dw.rpartials_off = L.rpartials_off;
+    dw.fp_off = L.fp_off;
+    dw.diag_off = L.diag_off;
     dw.workspace_bytes = L.em_bytes;
     dw.e_off = L.e_off;
     dw.zeta_off = L.zeta_off;

@@ -19,6 +19,11 @@ LIB_PATH = os.path.join(_HERE, "libctis.so")
 
 CTIS_PLAN_HOST_ONLY = 0x1
 CTIS_PLAN_KEEP_ZEROS = 0x2
+CTIS_PLAN_TILE_PATH = 0x4
+# region shapes of the region EM path (pixels along gamma, xi), by CTIS_PLAN_REGION code
+REGION_SHAPES = [None, (8, 32), (16, 16), (32, 8)]
+CTIS_BATCH_PERSISTENT = 0x400
+CTIS_BATCH_TILE_PATH = 0x8000
 
 STATUS_NAMES = {0: "CTIS_OK", 1: "CTIS_E_ARG", 2: "CTIS_E_INDEX", 3: "CTIS_E_VALUE",
                 4: "CTIS_E_TOO_LARGE", 5: "CTIS_E_NOMEM", 6: "CTIS_E_HIP",
@@ -27,6 +32,7 @@ STATUS_NAMES = {0: "CTIS_OK", 1: "CTIS_E_ARG", 2: "CTIS_E_INDEX", 3: "CTIS_E_VAL
 # every function include/ctis.h declares
 EXPORTED = ["ctis_plan_create", "ctis_plan_destroy", "ctis_plan_get_info",
             "ctis_plan_lambda_sums", "ctis_plan_export_boxes", "ctis_plan_export_worklist",
+            "ctis_plan_export_regions", "ctis_em_diagnostics",
             "ctis_forward", "ctis_adjoint", "ctis_em_iterate", "ctis_em_forward_ratio", "ctis_em_adjoint_update", "ctis_status_str",
             "ctis_last_error", "ctis_version", "ctis_batch_create", "ctis_batch_destroy",
             "ctis_batch_get_info", "ctis_batch_forward", "ctis_batch_adjoint", "ctis_batch_em_iterate",
@@ -58,7 +64,13 @@ class _Info(ctypes.Structure):
                 ("nonnegative", ctypes.c_int32), ("device", ctypes.c_int32),
                 ("waves_forward", ctypes.c_int32), ("waves_adjoint", ctypes.c_int32),
                 ("n_entries", ctypes.c_int64), ("vjp_workspace_bytes", ctypes.c_size_t),
-                ("dropped", ctypes.c_int32)]
+                ("dropped", ctypes.c_int32),
+                ("region_fast", ctypes.c_int32), ("region_slow", ctypes.c_int32),
+                ("n_regions", ctypes.c_int32), ("n_active_regions", ctypes.c_int32),
+                ("n_region_items", ctypes.c_int64), ("em_region_path", ctypes.c_int32),
+                ("waves_region", ctypes.c_int32), ("method_madds", ctypes.c_int64),
+                ("tile_forward_madds", ctypes.c_int64), ("region_forward_madds", ctypes.c_int64),
+                ("adjoint_madds", ctypes.c_int64)]
 
 
 class _BatchInfo(ctypes.Structure):
@@ -67,7 +79,9 @@ class _BatchInfo(ctypes.Structure):
                 ("forward_units", ctypes.c_int64), ("adjoint_units", ctypes.c_int64),
                 ("waves_forward", ctypes.c_int32), ("waves_adjoint", ctypes.c_int32),
                 ("workspace_bytes", ctypes.c_size_t), ("n_plans", ctypes.c_int32),
-                ("n_entries", ctypes.c_int64), ("vjp_workspace_bytes", ctypes.c_size_t)]
+                ("n_entries", ctypes.c_int64), ("vjp_workspace_bytes", ctypes.c_size_t),
+                ("em_region_path", ctypes.c_int32), ("waves_region", ctypes.c_int32),
+                ("region_units", ctypes.c_int64)]
 
 
 class _FourierInfo(ctypes.Structure):
@@ -103,6 +117,17 @@ class PlanInfo:
     n_entries: int
     vjp_workspace_bytes: int
     dropped: bool
+    region_fast: int
+    region_slow: int
+    n_regions: int
+    n_active_regions: int
+    n_region_items: int
+    em_region_path: bool
+    waves_region: int
+    method_madds: int
+    tile_forward_madds: int
+    region_forward_madds: int
+    adjoint_madds: int
 
 
 _lock = threading.Lock()
@@ -115,7 +140,7 @@ def load_library(path: str | None = None):
     with _lock:
         if _lib is not None and path is None:
             return _lib
-        p = path or LIB_PATH
+        p = path or os.environ.get("CTIS_LIBRARY") or LIB_PATH
         if not os.path.exists(p):
             raise ImportError(f"{p} is missing: build it with `python -m paper_2006_01573_amd.build`")
         L = ctypes.CDLL(p)
@@ -134,12 +159,16 @@ def load_library(path: str | None = None):
         L.ctis_plan_export_boxes.restype = st
         L.ctis_plan_export_worklist.argtypes = [vp, vp, vp]
         L.ctis_plan_export_worklist.restype = st
+        L.ctis_plan_export_regions.argtypes = [vp, vp, vp]
+        L.ctis_plan_export_regions.restype = st
         L.ctis_forward.argtypes = [vp, vp, vp, vp]
         L.ctis_forward.restype = st
         L.ctis_adjoint.argtypes = [vp, vp, vp, vp]
         L.ctis_adjoint.restype = st
         L.ctis_em_iterate.argtypes = [vp, vp, vp, i32, vp, sz, vp]
         L.ctis_em_iterate.restype = st
+        L.ctis_em_diagnostics.argtypes = [vp, vp, vp, vp, vp, sz, vp]
+        L.ctis_em_diagnostics.restype = st
         L.ctis_em_forward_ratio.argtypes = [vp, vp, vp, vp, sz, vp]
         L.ctis_em_forward_ratio.restype = st
         L.ctis_em_adjoint_update.argtypes = [vp, vp, sz, vp, vp, vp]
@@ -248,7 +277,8 @@ class Plan:
     """
 
     def __init__(self, a, alpha, w, gamma, xi, lambda_ptr, fpa_index, value, *,
-                 box: int = 0, host_only: bool = False, keep_zeros: bool = False, device=None):
+                 box: int = 0, host_only: bool = False, keep_zeros: bool = False, tile_path: bool = False,
+                 region: int = 0, device=None):
         self._L = load_library()
         self._handle = None
         ptr = np.ascontiguousarray(lambda_ptr, dtype=np.int64)
@@ -259,7 +289,8 @@ class Plan:
         if ptr.size and ptr[-1] > min(idx.size, val.size):
             raise ValueError("fpa_index/value shorter than lambda_ptr[w]")
         flags = (CTIS_PLAN_BOX(box) | (CTIS_PLAN_HOST_ONLY if host_only else 0)
-                 | (CTIS_PLAN_KEEP_ZEROS if keep_zeros else 0))
+                 | (CTIS_PLAN_KEEP_ZEROS if keep_zeros else 0) | (CTIS_PLAN_TILE_PATH if tile_path else 0)
+                 | (REGION_SHAPES.index(tuple(region)) << 12 if region else 0))
         self.device = None
         if not host_only:
             torch = _torch()
@@ -322,6 +353,7 @@ class Plan:
         d = {k: getattr(inf, k) for k, _ in _Info._fields_}
         d["nonnegative"] = bool(d["nonnegative"])
         d["dropped"] = bool(d["dropped"])
+        d["em_region_path"] = bool(d["em_region_path"])
         return PlanInfo(**d)
 
     def lambda_sums(self) -> np.ndarray:
@@ -346,6 +378,14 @@ class Plan:
         _check(self._L, self._L.ctis_plan_export_worklist(self._handle, _ptr(tp), _ptr(ib)),
                "ctis_plan_export_worklist")
         return tp, ib
+
+    def regions(self):
+        """(region_ptr[n_regions+1], item_box[n_region_items]) of the region path."""
+        rp = np.empty(self.sizes.n_regions + 1, np.int32)
+        ib = np.empty(self.sizes.n_region_items, np.int32)
+        _check(self._L, self._L.ctis_plan_export_regions(self._handle, _ptr(rp), _ptr(ib)),
+               "ctis_plan_export_regions")
+        return rp, ib
 
     # -- compute ----------------------------------------------------------------------
     def _need_device(self):
@@ -449,6 +489,31 @@ class Plan:
         _check(self._L, st, "ctis_em_iterate")
         return f
 
+    def diagnostics(self, g, f, workspace=None, out=None):
+        """(flux sum_j h_j f_j, sum g, Poisson log-likelihood, pixels with g > 0
+        and H f <= 0) of the iterate f, in double precision on the GPU; `out`
+        (device float64[4]) receives them without a host copy if given."""
+        self._need_device()
+        torch = _torch()
+        g = self._dev_tensor(g, self.sizes.n, "g")
+        f = self._dev_tensor(f, self.sizes.m, "f")
+        ret = out is None
+        if out is None:
+            out = torch.empty(4, dtype=torch.float64, device=self.device)
+        elif not (isinstance(out, torch.Tensor) and out.dtype == torch.float64 and out.numel() == 4
+                  and out.is_contiguous() and out.device == torch.device(self.device)):
+            raise ValueError("out must be a contiguous float64 tensor of 4 elements on the plan's device")
+        if workspace is None:
+            workspace = self.workspace()
+        wp, wb = self._ws(workspace)
+        st = self._L.ctis_em_diagnostics(self._handle, ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(f.data_ptr()),
+                                         ctypes.c_void_p(out.data_ptr()), wp, wb, _stream(torch, self.device))
+        _check(self._L, st, "ctis_em_diagnostics")
+        if ret:
+            v = out.cpu().tolist()
+            return v[0], v[1], v[2], int(v[3])
+        return out
+
     # -- derivatives ------------------------------------------------------------------
     def vjp_workspace(self):
         """Workspace for em_vjp (also valid for em)."""
@@ -499,7 +564,8 @@ class Batch:
     frames.  Frame k's datacube is f_all[f_offsets[k] : f_offsets[k] + m_k]
     and its image g_all[g_offsets[k] : ...] (see include/ctis.h)."""
 
-    def __init__(self, plans, waves_forward: int = 0, waves_adjoint: int = 0, persistent: bool = False):
+    def __init__(self, plans, waves_forward: int = 0, waves_adjoint: int = 0, persistent: bool = False,
+                 waves_region: int = 0, tile_path: bool = False):
         self._L = load_library()
         self._handle = None
         self.plans = list(plans)
@@ -509,7 +575,12 @@ class Batch:
             p._need_device()
         self.device = self.plans[0].device
         arr = (ctypes.c_void_p * len(self.plans))(*[p._handle.value for p in self.plans])
-        flags = (int(waves_forward) & 0x1F) | ((int(waves_adjoint) & 0x1F) << 5) | (0x400 if persistent else 0)
+        for name, v, hi in (("waves_forward", waves_forward, 31), ("waves_adjoint", waves_adjoint, 31),
+                            ("waves_region", waves_region, 15)):
+            if not 0 <= int(v) <= hi:
+                raise ValueError(f"{name} must be in 0..{hi}")
+        flags = (int(waves_forward) | (int(waves_adjoint) << 5) | (int(waves_region) << 11)
+                 | (CTIS_BATCH_PERSISTENT if persistent else 0) | (CTIS_BATCH_TILE_PATH if tile_path else 0))
         h = ctypes.c_void_p()
         _check(self._L, self._L.ctis_batch_create(ctypes.byref(h), ctypes.cast(arr, ctypes.c_void_p),
                                                   len(self.plans), flags), "ctis_batch_create")
@@ -602,6 +673,31 @@ class Batch:
                                            _stream(torch, self.device))
         _check(self._L, st, "ctis_batch_em_iterate")
         return f_all
+
+    def diagnostics(self, g, f, workspace=None, out=None):
+        """(flux sum_j h_j f_j, sum g, Poisson log-likelihood, pixels with g > 0
+        and H f <= 0) of the iterate f, in double precision on the GPU; `out`
+        (device float64[4]) receives them without a host copy if given."""
+        self._need_device()
+        torch = _torch()
+        g = self._dev_tensor(g, self.sizes.n, "g")
+        f = self._dev_tensor(f, self.sizes.m, "f")
+        ret = out is None
+        if out is None:
+            out = torch.empty(4, dtype=torch.float64, device=self.device)
+        elif not (isinstance(out, torch.Tensor) and out.dtype == torch.float64 and out.numel() == 4
+                  and out.is_contiguous() and out.device == torch.device(self.device)):
+            raise ValueError("out must be a contiguous float64 tensor of 4 elements on the plan's device")
+        if workspace is None:
+            workspace = self.workspace()
+        wp, wb = self._ws(workspace)
+        st = self._L.ctis_em_diagnostics(self._handle, ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(f.data_ptr()),
+                                         ctypes.c_void_p(out.data_ptr()), wp, wb, _stream(torch, self.device))
+        _check(self._L, st, "ctis_em_diagnostics")
+        if ret:
+            v = out.cpu().tolist()
+            return v[0], v[1], v[2], int(v[3])
+        return out
 
     # -- derivatives ------------------------------------------------------------------
     def vjp_workspace(self):

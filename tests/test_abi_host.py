@@ -205,6 +205,58 @@ def test_worklist_matches_brute_force(oracle_mod, lib, name, geo, nnz, clustered
         assert got[t], f"support pixel {i} in an inactive tile"
 
 
+@pytest.mark.parametrize("name,geo,nnz,clustered", CASES + [
+    ("margins", W.Geometry(23, 11, 3, 60, 44), 7, False),
+    ("margins-clustered", W.Geometry(16, 12, 4, 64, 48), 9, True)])
+def test_region_grid_matches_brute_force(oracle_mod, lib, name, geo, nnz, clustered):
+    """The region path's 16 x 16 grid: the same cover rule as the tiles."""
+    rng = np.random.default_rng(zlib.crc32(name.encode()) % 10_000 + 7)
+    ptr, idx, val = W.random_kernels(geo, nnz, rng, clustered=clustered)
+    p = host_plan(geo, ptr, idx, val)
+    inf = p.info
+    _, rc, _ = p.boxes()
+    rp, ib = p.regions()
+    assert (inf.region_fast, inf.region_slow) == (16, 16)
+    assert rp[0] == 0 and rp[-1] == inf.n_region_items and np.all(np.diff(rp) >= 0)
+    got = {t: set(ib[rp[t]:rp[t + 1]].tolist()) for t in range(inf.n_regions)}
+    want = {t: set() for t in range(inf.n_regions)}
+    for k in range(inf.n_boxes):
+        for t in brute_force_tiles(geo, inf.box, rc[k], inf.region_fast, inf.region_slow):
+            want[t].add(k)
+    assert got == want
+    assert inf.n_active_regions == sum(1 for t in want if want[t])
+    # executed multiply-adds: B*B per box slot and output of every item
+    BB = inf.box ** 2
+    assert inf.region_forward_madds == inf.n_region_items * 256 * BB
+    assert inf.tile_forward_madds == inf.n_items * inf.tile_fast * inf.tile_slow * BB
+    assert inf.method_madds == geo.ell * inf.nnz
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3])
+def test_configurations_take_the_region_path(lib, cfg):
+    """The configurations leave the margin the region path needs; there the
+    region forward executes fewer multiply-adds than the tile forward."""
+    case = W.make_case(cfg)
+    p = ctis.Plan.from_case(case, host_only=True)
+    inf = p.info
+    assert inf.em_region_path
+    ratio = inf.region_forward_madds / inf.method_madds
+    assert ratio < inf.tile_forward_madds / inf.method_madds
+    assert ratio <= {1: 4.5, 2: 1.9, 3: 1.4}[cfg]
+    assert inf.adjoint_madds == inf.method_madds or cfg == 1   # the c1 field stop (16) is not a tile multiple
+
+
+def test_region_path_needs_the_margin(lib):
+    B = 3
+    for gamma, xi, want in ((60 + 14 + B, 10 + 14 + B, True), (60 + 13 + B, 40, False), (90, 10 + 13 + B, False)):
+        geo = W.Geometry(60, 10, 2, gamma, xi)
+        ptr, idx, val = W.random_kernels(geo, 9, np.random.default_rng(5), clustered=True)
+        p = host_plan(geo, ptr, idx, val, box=B)
+        assert p.info.em_region_path == want, (gamma, xi)
+    p = ctis.Plan(geo.a, geo.alpha, geo.w, 200, 200, ptr, idx, val, box=B, host_only=True, tile_path=True)
+    assert not p.info.em_region_path
+
+
 @pytest.mark.parametrize("name,geo,nnz,clustered", CASES)
 def test_support_count_matches_explicit_H(oracle_mod, lib, name, geo, nnz, clustered):
     rng = np.random.default_rng(zlib.crc32(name.encode()) % 10_000 + 1)

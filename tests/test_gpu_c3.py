@@ -94,44 +94,33 @@ def test_c3_em_200_iterations(torch, c3):
 
 
 def test_c3_em_invariants(torch, c3):
-    """Properties of the solve at every iteration: nonnegative finite
-    iterates; the EM flux identity sum_j h_j f^(k+1)_j = sum of g over the
-    pixels where H f^(k) > 0; and a Poisson log-likelihood that does not
-    decrease (Shepp-Vardi EM, cited in Sec. 2); the final flux and
-    log-likelihood against the oracle's."""
+    """Properties of the solve at every iteration, from the library's GPU
+    diagnostics (double-precision reductions): nonnegative finite iterates;
+    the EM flux identity sum_j h_j f^(k+1)_j = sum of g over the pixels where
+    H f^(k) > 0 (all of g here: no pixel with g > 0 has H f = 0); and a
+    Poisson log-likelihood that does not decrease (Shepp-Vardi EM, cited in
+    Sec. 2); the final flux and log-likelihood against the oracle's."""
     case, plan, exp, g = c3
-    geo = case.geometry
     K = case.cfg.iters
     gd = torch.from_numpy(g).cuda()
-    g64 = gd.double().reshape(-1)
-    h = torch.from_numpy(np.repeat(plan.lambda_sums().astype(np.float64), geo.ell)).cuda()
     f = torch.ones(plan.shape_f, device="cuda")
     ws = plan.workspace()
-
-    def loglik(x):
-        ghat = plan.forward(x).double().reshape(-1)
-        pos = g64 > 0
-        if bool(((ghat <= 0) & pos).any()):
-            return -float("inf"), ghat
-        safe = torch.where(pos, ghat, torch.ones_like(ghat))
-        return float(torch.where(pos, g64 * torch.log(safe), 0.0).sum() - ghat.sum()), ghat
-
     marks = {0, 1, 2, 5, 10, 25, 50, 100, 150, K - 1}
     ll = []
     for k in range(K):
         if k in marks:
-            L, ghat = loglik(f)
+            _, sum_g, L, bad = plan.diagnostics(gd, f, workspace=ws)
+            assert bad == 0
             ll.append(L)
-            if k == K - 1:
-                target = float(g64[ghat > 0].sum())
         plan.em(gd, 1, f=f, workspace=ws)
-    L_end, _ = loglik(f)
+    flux, sum_g, L_end, bad = plan.diagnostics(gd, f, workspace=ws)
     ll.append(L_end)
-    flux = float((h * f.double().reshape(-1)).sum())
-    log(f"c3: flux {flux:.6e} vs {target:.6e} (oracle {float(exp['flux200']):.6e}); "
+    log(f"c3: flux {flux:.6e} vs sum g {sum_g:.6e} (oracle {float(exp['flux200']):.6e}); "
         f"loglik {ll[0]:.6e} -> {ll[-1]:.6e} (oracle {float(exp['loglik200']):.6e})")
     assert torch.isfinite(f).all() and bool((f >= 0).all())
-    assert abs(flux - target) <= 1e-5 * target
+    assert bad == 0
+    assert abs(sum_g - float(np.sum(g, dtype=np.float64))) <= 1e-12 * sum_g
+    assert abs(flux - sum_g) <= 1e-5 * sum_g
     assert abs(flux - float(exp["flux200"])) <= 1e-5 * abs(float(exp["flux200"]))
     assert abs(L_end - float(exp["loglik200"])) <= 1e-5 * abs(float(exp["loglik200"]))
     for a, b in zip(ll, ll[1:]):

@@ -195,6 +195,28 @@ def test_em_from_the_adjoint_start(torch, ctis, c1):
     assert rel_l2(fb[: case.geometry.m], ref) <= EM_TOL and rel_l2(fb[case.geometry.m:], ref) <= EM_TOL
 
 
+def test_diagnostics_against_oracle(torch, ctis, oracle_mod, c1):
+    """GPU diagnostics (flux, sum g, Poisson log-likelihood; double-precision
+    reductions over the float projection) against the oracle's, at the start
+    and after 5 EM iterations; a pixel with g > 0 that no voxel reaches makes
+    the log-likelihood -inf."""
+    case, o, p, g = c1
+    gd = torch.from_numpy(g).cuda()
+    for f in (np.ones(p.sizes.m, np.float32), p.em(gd, 5).cpu().numpy().ravel()):
+        flux, sum_g, L, bad = p.diagnostics(gd, torch.from_numpy(f).cuda())
+        fl_ref, L_ref = o.diagnostics(g, f)
+        assert bad == 0
+        assert abs(flux - fl_ref) <= 1e-6 * abs(fl_ref)
+        assert abs(sum_g - float(np.sum(g, dtype=np.float64))) <= 1e-12 * sum_g
+        assert abs(L - L_ref) <= 1e-6 * abs(L_ref)
+    _, rows, _ = o.csc()
+    off = np.setdiff1d(np.arange(p.sizes.n), rows)
+    g2 = g.copy().ravel()
+    g2[off[0]] = 1.0
+    _, _, L, bad = p.diagnostics(torch.from_numpy(g2).cuda(), torch.ones(p.shape_f, device="cuda"))
+    assert L == -np.inf and bad == 1
+
+
 def test_adjoint_identity_gpu(torch, c1):
     case, o, p, _ = c1
     rng = np.random.default_rng(9)
