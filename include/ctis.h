@@ -235,6 +235,21 @@ ctis_status ctis_em_iterate(const ctis_plan *plan, const float *g, float *f, int
                             void *workspace, size_t workspace_bytes, void *stream);
 
 /*
+ * ctis_em_iterate without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The library keeps one file-scope device
+ * array of 16 MiB per device (held until the process ends) and uses it as
+ * the workspace; the call allocates nothing.  Same arguments, results and
+ * kernels as ctis_em_iterate.  Every call on a device shares that device's
+ * array: calls that overlap on one device (different streams, or several
+ * host threads) race and must be serialised by the caller.
+ * Errors: CTIS_E_TOO_LARGE if info.workspace_bytes exceeds 16 MiB, and those
+ * of ctis_em_iterate (no CTIS_E_WORKSPACE).
+ */
+ctis_status ctis_em_iterate_static(const ctis_plan *plan, const float *g, float *f, int32_t iters,
+                                   void *stream);
+
+/*
  * Diagnostics of an EM iterate (Sec. 2: the column sums h below eq. (em); the
  * Poisson likelihood the EM iteration increases, after Shepp and Vardi), in
  * double precision:

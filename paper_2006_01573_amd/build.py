@@ -18,7 +18,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libctis.so")
 
 ARCH = "gfx950"
-SOURCES = ["plan.cpp", "api.cpp", "batch.cpp", "vjp.cpp", "fourier.cpp", "kernels.hip", "fourier.hip"]
+SOURCES = ["plan.cpp", "api.cpp", "batch.cpp", "vjp.cpp", "fourier.cpp", "kernels.hip", "fourier.hip",
+           "static_scratch.hip"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           f"-I{INCLUDE}", f"-I{CSRC}"]
 # Device code: no packed-FP32 VALU instructions (hipcc warns that the host pass

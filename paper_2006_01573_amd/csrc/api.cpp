@@ -407,6 +407,25 @@ ctis_status ctis_em_adjoint_update(const ctis_plan *p, void *workspace, size_t w
                          "adjoint+update launch");
 }
 
+ctis_status ctis_em_iterate_static(const ctis_plan *p, const float *g, float *f, int32_t iters, void *stream) {
+    if (!p) return fail(CTIS_E_ARG, "plan is NULL");
+    if (!g || !f) return fail(CTIS_E_ARG, "g or f is NULL");
+    if (iters < 0) return fail(CTIS_E_ARG, "iters must be >= 0");
+    if (!aligned4(g) || !aligned4(f)) return fail(CTIS_E_ARG, "g and f must be 4-byte aligned");
+    if (!p->ht.nonneg) return fail(CTIS_E_NEGATIVE, "the plan has a negative calibration value");
+    if (p->workspace_bytes > kStaticScratchBytes)
+        return fail(CTIS_E_TOO_LARGE, "the plan's EM workspace (" + std::to_string(p->workspace_bytes) +
+                                          " bytes) exceeds the static scratch of " +
+                                          std::to_string(kStaticScratchBytes) + " bytes; use ctis_em_iterate");
+    if (overlaps(g, (size_t)p->n * 4, f, (size_t)p->m * 4)) return fail(CTIS_E_ARG, "g and f overlap");
+    ctis_status st = check_device(p);
+    if (st != CTIS_OK || iters == 0) return st;
+    void *scratch = nullptr;
+    st = launch_status(static_scratch(&scratch), "static scratch address");
+    if (st != CTIS_OK) return st;
+    return em_loop(p->work, g, f, iters, scratch, stream);
+}
+
 ctis_status ctis_em_diagnostics(const ctis_plan *p, const float *g, const float *f, double *out, void *workspace,
                                 size_t workspace_bytes, void *stream) {
     if (!p) return fail(CTIS_E_ARG, "plan is NULL");

@@ -235,6 +235,11 @@ ctis_status build_work(const std::vector<FrameRef> &frames, bool with_full, Host
 ctis_status upload_work(const HostWork &hw, DevWork &dw);
 void free_work(DevWork &dw);
 
+// Scratch-free EM (static_scratch.hip): a file-scope device array of this
+// size per device stands in for the workspace.
+constexpr size_t kStaticScratchBytes = size_t(16) << 20;
+int static_scratch(void **ptr);
+
 // stream-ordered EM drivers shared by plans and batches (api.cpp)
 ctis_status em_forward_half(const DevWork &w, const float *f, const float *g, void *workspace, void *stream);
 ctis_status em_loop(const DevWork &w, const float *g, float *f, int32_t iters, void *workspace, void *stream);

@@ -32,7 +32,7 @@ STATUS_NAMES = {0: "CTIS_OK", 1: "CTIS_E_ARG", 2: "CTIS_E_INDEX", 3: "CTIS_E_VAL
 # every function include/ctis.h declares
 EXPORTED = ["ctis_plan_create", "ctis_plan_destroy", "ctis_plan_get_info",
             "ctis_plan_lambda_sums", "ctis_plan_export_boxes", "ctis_plan_export_worklist",
-            "ctis_plan_export_regions", "ctis_em_diagnostics",
+            "ctis_plan_export_regions", "ctis_em_diagnostics", "ctis_em_iterate_static",
             "ctis_forward", "ctis_adjoint", "ctis_em_iterate", "ctis_em_forward_ratio", "ctis_em_adjoint_update", "ctis_status_str",
             "ctis_last_error", "ctis_version", "ctis_batch_create", "ctis_batch_destroy",
             "ctis_batch_get_info", "ctis_batch_forward", "ctis_batch_adjoint", "ctis_batch_em_iterate",
@@ -167,6 +167,8 @@ def load_library(path: str | None = None):
         L.ctis_adjoint.restype = st
         L.ctis_em_iterate.argtypes = [vp, vp, vp, i32, vp, sz, vp]
         L.ctis_em_iterate.restype = st
+        L.ctis_em_iterate_static.argtypes = [vp, vp, vp, i32, vp]
+        L.ctis_em_iterate_static.restype = st
         L.ctis_em_diagnostics.argtypes = [vp, vp, vp, vp, vp, sz, vp]
         L.ctis_em_diagnostics.restype = st
         L.ctis_em_forward_ratio.argtypes = [vp, vp, vp, vp, sz, vp]
@@ -514,6 +516,19 @@ class Plan:
             return v[0], v[1], v[2], int(v[3])
         return out
 
+    def em_static(self, g, iters: int, f):
+        """EM iterations in place on ``f`` through ctis_em_iterate_static: the
+        library's static device scratch stands in for the workspace (no
+        allocation; calls on one device must not overlap)."""
+        self._need_device()
+        torch = _torch()
+        g = self._dev_tensor(g, self.sizes.n, "g")
+        need_tensor(f, self.sizes.m, "f", self.device)
+        st = self._L.ctis_em_iterate_static(self._handle, ctypes.c_void_p(g.data_ptr()),
+                                            ctypes.c_void_p(f.data_ptr()), int(iters), _stream(torch, self.device))
+        _check(self._L, st, "ctis_em_iterate_static")
+        return f
+
     # -- derivatives ------------------------------------------------------------------
     def vjp_workspace(self):
         """Workspace for em_vjp (also valid for em)."""
@@ -698,6 +713,19 @@ class Batch:
             v = out.cpu().tolist()
             return v[0], v[1], v[2], int(v[3])
         return out
+
+    def em_static(self, g, iters: int, f):
+        """EM iterations in place on ``f`` through ctis_em_iterate_static: the
+        library's static device scratch stands in for the workspace (no
+        allocation; calls on one device must not overlap)."""
+        self._need_device()
+        torch = _torch()
+        g = self._dev_tensor(g, self.sizes.n, "g")
+        need_tensor(f, self.sizes.m, "f", self.device)
+        st = self._L.ctis_em_iterate_static(self._handle, ctypes.c_void_p(g.data_ptr()),
+                                            ctypes.c_void_p(f.data_ptr()), int(iters), _stream(torch, self.device))
+        _check(self._L, st, "ctis_em_iterate_static")
+        return f
 
     # -- derivatives ------------------------------------------------------------------
     def vjp_workspace(self):
