@@ -339,12 +339,12 @@ def bench_batched(args, torch, ctis, W, dev) -> int:
     for c, p in zip(cases, plans):
         clean = p.forward(torch.from_numpy(c.f_true.astype(np.float32)).to(dev)).double().cpu().numpy()
         images.append(c.noisy(clean))
-    progress("c4: autotuning the batch")
-    tuned = tune.autotune_batch(plans, ctis.Batch(plans).pack_g(images), iters=3, reps=2)
+    progress("c4: autotuning per frame shape")
+    tuned = tune.autotune_frames(cases, images, iters=4, reps=3)
     b = tuned.batch
     g_all = b.pack_g(images)
     ws = b.workspace()
-    f_all = torch.ones(int(b.f_offsets[-1]), dtype=torch.float32, device=dev)
+    f_all = torch.ones(b.m_total, dtype=torch.float32, device=dev)
     # capture the whole solve (reset + K iterations) once, replay it per step
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
@@ -440,9 +440,10 @@ def bench_batched(args, torch, ctis, W, dev) -> int:
         "config": {"workload": "c4 64 uneven frames, a=alpha in {32,48,64}, w in {16,32}, FPA 256/512, "
                                "3x3 orders, 50 EM iterations each, one step = all 64 frames",
                    "frames": 64, "em_iters": K, "m_total": m_all, "n_support_total": nsup,
-                   "tuned": {"waves_forward": tuned.waves_forward, "waves_adjoint": tuned.waves_adjoint,
-                             "persistent": tuned.persistent, "box": tuned.box,
-                             "candidates": len(tuned.table)}},
+                   "tuned": {"arrangement": tuned.arrangement, "batches": b.report(),
+                             "uniform_choice": tuned.uniform,
+                             "ms_per_iter_of_arrangements": tuned.ms_per_iter,
+                             "per_shape": tuned.classes, "candidates_timed": len(tuned.table)}},
         "sequential_frames_per_s": seq_fps,
         "batched_vs_sequential": batched_fps / seq_fps,
         "sequential_graph_frames_per_s": seq_graph_fps,
@@ -573,7 +574,9 @@ def bench_differentiable(args, torch, ctis, W, dev) -> int:
     nf = len(cases)
     progress(f"c5: plan and {nf} frames")
     plan = ctis.Plan.from_case(c0, keep_zeros=True)
-    b = ctis.Batch([plan] * nf)
+    # the checkpointed forward runs one EM iteration per call: the tile path,
+    # which needs no padded copy of f per call
+    b = ctis.Batch([plan] * nf, tile_path=True)
     images = []
     for c in cases:
         clean = plan.forward(torch.from_numpy(c.f_true.astype(np.float32)).to(dev)).double().cpu().numpy()

@@ -14,7 +14,10 @@ The operator is a ``ctis.Plan`` (one frame) or a ``ctis.Batch`` (frames back
 to back; frames that share a plan share its values).  Values are one float
 per calibration entry in the plan's input order (a batch: its distinct plans'
 entries back to back); plans built for derivatives with respect to the values
-need ``keep_zeros=True`` when a value may be zero.
+need ``keep_zeros=True`` when a value may be zero.  The forward runs one EM
+iteration per call (a checkpoint after each), so operators on the tile path
+(``tile_path=True``) suit it best: the region path writes its padded copy of
+f at the start of every call.
 """
 from __future__ import annotations
 

@@ -28,6 +28,10 @@ constexpr int kTileSlow = 16;
 constexpr int kRegionPixels = 256;
 constexpr int kFwdMaxWaves = 8;
 constexpr int kMaxBox = 8;
+// Work records of windows that run inside the FPA without wrapping carry
+// this flag (tile forward: in the f-offset field; back projection: the third
+// field is 1): the kernels then take scalar row offsets.
+constexpr int kDirectFlag = 1 << 30;
 constexpr int region_fast(int gx) { return 4 * gx; }
 constexpr int region_slow(int gx) { return 64 / gx; }
 // Zero border of the padded copy of f the region forward reads, per axis: a
@@ -53,14 +57,17 @@ constexpr int64_t kMaxPixels = (int64_t(1) << 29) - 1;
 //   (g_off, out_off, 0, 0)             frame offsets (floats) into g and out
 // forward record, int4: (Xs, Ys, f_off, box): window origin
 //   (r0 - (B-1) - rA, c0 - (B-1) - cA), offset of f_s in the f buffer, global
-//   box id; box = -1 ends a unit's list
+//   box id; box = -1 ends a unit's list.  A window that runs inside the FPA
+//   without a carry or wrap is recorded decoded instead: (xr, y0,
+//   f_off | kDirectFlag, box) with Xs + gamma*Ys = xr + gamma*y0 mod n
 // split meta, 2 x int4: (r0, c0, n_chunks, first slot), (gamma, xi, g_off, out_off)
 // adjoint unit meta, 3 x int4:
 //   (x0, y0, global wavelength, f_off)  field-stop tile, offset of f_s
 //   (a, alpha, gamma, xi)
 //   (u_off, 0, 0, 0)                    frame offset into u
-// adjoint record, int4: (rA, cA, 0, box), adj_stride records per global
-//   wavelength
+// adjoint record, int4: (rA, cA, direct, box), adj_stride records per global
+//   wavelength; direct = 1 if the box's windows stay inside the FPA for
+//   every field-stop tile
 //
 // Frames that share a plan share its boxes, wavelengths and values: the
 // "global" box and wavelength ids run over the distinct plans of the work, in

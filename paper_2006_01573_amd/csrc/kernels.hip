@@ -120,6 +120,12 @@ __device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, unsigned off) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
 }
 
+// raw 32-bit buffer load at byte offset voff + soff (soff wave-uniform: a
+// scalar register)
+__device__ __forceinline__ float bload2(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
 // The SY rows of one window column, from a buffer with row pitch P floats:
 // row yy sits at byte offset 4*(col + P*((y + yy) mod xi)), given
 // o0 = 4*(col + P*y) and wrap = 4*P*xi.  For xi >= SY the row index wraps at
@@ -202,6 +208,36 @@ __device__ __forceinline__ void load_forward(Pending<B> &pd, const float *f, con
     load_values<B>(pd, wtab, rec.w, lane);
 }
 
+// Forward window of an item whose window runs inside the FPA without a
+// carry into the next column or a wrap round its end (decided on the host:
+// rec = (xr, y0, f_off | kDirectFlag, box) with the window origin decoded,
+// xr + 64 + B - 1 <= gamma, y0 + 16 + B - 1 <= xi): slot (xx, yy) is
+// f_s(xr + xx, y0 + yy) inside the field stop, 0 outside.  Columns past a
+// get the out-of-range offset; rows at or past alpha land at or past the
+// block's a*alpha floats and read 0.  One vector add per row.
+template <int B>
+__device__ __forceinline__ void load_forward_direct(Pending<B> &pd, const float *f, const float *__restrict__ wtab,
+                                                    const Geo &p, int4 rec, int lane, const unsigned (&xo)[
+                                                        Win<B>::NXT > 0 ? Win<B>::NXT : 1]) {
+    using Wn = Win<B>;
+    const __amdgpu_buffer_rsrc_t fr = rsrc(f + (size_t)(unsigned)(rec.z & (kDirectFlag - 1)), p.a * p.alpha);
+    const int xm = rec.x + lane;
+    const unsigned stp = 4u * (unsigned)p.a;
+    const unsigned o0 = xm < p.a ? 4u * (unsigned)xm + stp * (unsigned)rec.y : kOutOfRange;
+#pragma unroll
+    for (int yy = 0; yy < Wn::SY; ++yy) pd.v[yy] = bload(fr, o0 + stp * (unsigned)yy);
+    // extra slot t of this lane: column 64 + e, row yy, with xo[t] = (e, yy)
+    // packed as e + 64*yy (or -1: no slot)
+#pragma unroll
+    for (int t = 0; t < Wn::NXT; ++t) {
+        const int e = (int)(xo[t] & 63u), yy = (int)(xo[t] >> 6);
+        const int xe = rec.x + TX + e;
+        pd.x[t] = bload(fr, (xo[t] != ~0u && xe < p.a) ? 4u * (unsigned)xe + stp * (unsigned)(rec.y + yy)
+                                                         : kOutOfRange);
+    }
+    load_values<B>(pd, wtab, rec.w, lane);
+}
+
 // Adjoint window of one (field-stop tile, box) pair: slot (xx, yy) <-
 // u((Xs + xx) + gamma*(Ys + yy) mod n).  Slots past the dilated field stop
 // (xx >= a + B - 1 - x0 or yy >= alpha + B - 1 - y0) only ever meet output
@@ -247,6 +283,27 @@ __device__ __forceinline__ void load_adjoint(Pending<B> &pd, __amdgpu_buffer_rsr
         }
         pd.x[t] = bload(ur, off);
     }
+    load_values<B>(pd, wtab, box, lane);
+}
+
+// Adjoint window of a box whose windows run inside the FPA without wrapping
+// for every tile of the field stop (Xs + 64 + B - 1 <= gamma and
+// Ys + 16 + B - 1 <= xi; flagged on the host): slot (xx, yy) at byte offset
+// 4*xx + 4*(Xs + gamma*(Ys + yy)), the second term wave-uniform (a scalar
+// offset), so the row loads take no vector arithmetic.  xo[t]: byte offset
+// of this lane's extra slot within the window (0 where it has none).
+template <int B>
+__device__ __forceinline__ void load_adjoint_direct(Pending<B> &pd, __amdgpu_buffer_rsrc_t ur,
+                                                    const float *__restrict__ wtab, const Geo &p, int Xs, int Ys,
+                                                    int box, int lane,
+                                                    const unsigned (&xo)[Win<B>::NXT > 0 ? Win<B>::NXT : 1]) {
+    using Wn = Win<B>;
+    const unsigned s0 = 4u * (unsigned)(Xs + p.gamma * Ys), srow = 4u * (unsigned)p.gamma;
+    const unsigned vo = 4u * (unsigned)lane;
+#pragma unroll
+    for (int yy = 0; yy < Wn::SY; ++yy) pd.v[yy] = bload2(ur, vo, s0 + srow * (unsigned)yy);
+#pragma unroll
+    for (int t = 0; t < Wn::NXT; ++t) pd.x[t] = bload2(ur, xo[t], s0);
     load_values<B>(pd, wtab, box, lane);
 }
 
@@ -376,17 +433,35 @@ __global__ void __launch_bounds__(64 * Win<B>::MAXW) k_forward(const int4 *__res
 #pragma unroll
             for (int q = 0; q < 4; ++q) acc[a][q] = 0.0f;
 
+        // this lane's extra window slots (column 64 + e, row yy) as e + 64 yy
+        unsigned xs[Wn::NXT > 0 ? Wn::NXT : 1];
+#pragma unroll
+        for (int t = 0; t < Wn::NXT; ++t) {
+            const int kk = lane + 64 * t;
+            xs[t] = kk < Wn::E * Wn::SY ? (unsigned)(kk % Wn::ED) + 64u * (unsigned)(kk / Wn::ED) : ~0u;
+        }
+
         // one window in flight: once item k's window is in LDS, the window of
         // the wave's next item (k + nw) is fetched into registers while item k
         // is correlated; the work records run one item further ahead
         Pending<B> pa;
-        if (rec0.w >= 0) load_forward<B>(pa, f, box_wf, geo, rec0, lane);
+        if (rec0.w >= 0) {
+            if (rec0.z & kDirectFlag)
+                load_forward_direct<B>(pa, f, box_wf, geo, rec0, lane, xs);
+            else
+                load_forward<B>(pa, f, box_wf, geo, rec0, lane);
+        }
         while (rec0.w >= 0) {
             store_window<B>(S, pa, lane);
             wave_lds_sync();
             k += nw;
             const int4 rec3 = record(list, k + nw, stride);
-            if (rec1.w >= 0) load_forward<B>(pa, f, box_wf, geo, rec1, lane);
+            if (rec1.w >= 0) {
+                if (rec1.z & kDirectFlag)
+                    load_forward_direct<B>(pa, f, box_wf, geo, rec1, lane, xs);
+                else
+                    load_forward<B>(pa, f, box_wf, geo, rec1, lane);
+            }
             correlate<B, Win<B>::SXP, Win<B>::REG>(acc, S, lx, ly);
             wave_lds_sync();
             rec0 = rec1;
@@ -742,14 +817,35 @@ __global__ void __launch_bounds__(64 * Win<B>::MAXW) k_adjoint(const int4 *__res
 #pragma unroll
             for (int q = 0; q < 4; ++q) acc[a][q] = 0.0f;
 
+        // byte offsets of this lane's extra window slots (column 64 + e, row
+        // yy) within a direct window
+        unsigned xo[Wn::NXT > 0 ? Wn::NXT : 1];
+#pragma unroll
+        for (int t = 0; t < Wn::NXT; ++t) {
+            const int kk = lane + 64 * t;
+            xo[t] = kk < Wn::E * Wn::SY ? 4u * (unsigned)(TX + kk % Wn::ED) + 4u * (unsigned)geo.gamma *
+                                                                                   (unsigned)(kk / Wn::ED)
+                                        : 0u;
+        }
+
         Pending<B> pa;
-        if (rec0.w >= 0) load_adjoint<B>(pa, ur, box_w, geo, rec0.x + x0, rec0.y + y0, rec0.w, lane);
+        if (rec0.w >= 0) {
+            if (rec0.z)
+                load_adjoint_direct<B>(pa, ur, box_w, geo, rec0.x + x0, rec0.y + y0, rec0.w, lane, xo);
+            else
+                load_adjoint<B>(pa, ur, box_w, geo, rec0.x + x0, rec0.y + y0, rec0.w, lane);
+        }
         while (rec0.w >= 0) {
             store_window<B>(S, pa, lane);
             wave_lds_sync();
             k += nw;
             const int4 rec3 = record(list, k + nw, stride);
-            if (rec1.w >= 0) load_adjoint<B>(pa, ur, box_w, geo, rec1.x + x0, rec1.y + y0, rec1.w, lane);
+            if (rec1.w >= 0) {
+                if (rec1.z)
+                    load_adjoint_direct<B>(pa, ur, box_w, geo, rec1.x + x0, rec1.y + y0, rec1.w, lane, xo);
+                else
+                    load_adjoint<B>(pa, ur, box_w, geo, rec1.x + x0, rec1.y + y0, rec1.w, lane);
+            }
             correlate<B, Win<B>::SXP, Win<B>::REG>(acc, S, lx, ly);
             wave_lds_sync();
             rec0 = rec1;

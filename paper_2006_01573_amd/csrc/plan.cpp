@@ -104,6 +104,11 @@ std::vector<std::pair<int32_t, int32_t>> cells(const Component &cp, const std::v
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+int64_t floor_div(int64_t a, int64_t b) {
+    const int64_t q = a / b;
+    return (a % b != 0 && (a < 0) != (b < 0)) ? q - 1 : q;
+}
+
 int64_t floor_mod(int64_t a, int64_t b) {
     const int64_t r = a % b;
     return r < 0 ? r + b : r;
@@ -584,8 +589,15 @@ ctis_status build_work(const std::vector<FrameRef> &frames, bool with_full, Host
                 const int64_t Xs = (int64_t)r0 - (B - 1) - T.box_rc[2 * (size_t)b];
                 const int64_t Ys = (int64_t)c0 - (B - 1) - T.box_rc[2 * (size_t)b + 1];
                 if (!region) {
-                    push4(L.items, (int32_t)Xs, (int32_t)Ys, (int32_t)(fr.f_base + (int64_t)s * pl->ell),
-                          fbox[(size_t)ur.frame] + b);
+                    // decoded origin; direct if the window's columns do not carry
+                    // into the next FPA column and its rows do not wrap
+                    const int64_t q0 = floor_div(Xs, pl->gamma);
+                    const int64_t xr = Xs - q0 * pl->gamma, y0 = floor_mod(Ys + q0, pl->xi);
+                    const int32_t foff = (int32_t)(fr.f_base + (int64_t)s * pl->ell);
+                    if (xr + kTileFast + B - 1 <= pl->gamma && y0 + kTileSlow + B - 1 <= pl->xi)
+                        push4(L.items, (int32_t)xr, (int32_t)y0, foff | kDirectFlag, fbox[(size_t)ur.frame] + b);
+                    else
+                        push4(L.items, (int32_t)Xs, (int32_t)Ys, foff, fbox[(size_t)ur.frame] + b);
                     continue;
                 }
                 // The window's slot (xx, yy) holds fE((Xs + xx) + gamma*(Ys + yy) mod n).
@@ -670,6 +682,9 @@ ctis_status build_work(const std::vector<FrameRef> &frames, bool with_full, Host
                 if (b0 + j < b1) {
                     rec[0] = T.box_rc[2 * (size_t)(b0 + j)];
                     rec[1] = T.box_rc[2 * (size_t)(b0 + j) + 1];
+                    // direct: the windows of every field-stop tile stay inside the FPA
+                    rec[2] = ((int64_t)rec[0] + (int64_t)T.nbx * kTileFast + B - 1 <= pl->gamma &&
+                              (int64_t)rec[1] + (int64_t)T.nby * kTileSlow + B - 1 <= pl->xi) ? 1 : 0;
                     rec[3] = hw.plan_box0[d] + b0 + j;
                 } else {
                     rec[3] = -1;

@@ -1,36 +1,57 @@
-"""Autotuner for batched reconstructions.
+"""Autotuner for batched reconstructions of frames of uneven shapes.
 
-For a set of frames it times the batched EM iteration on the GPU for every
-candidate launch configuration -- wavefronts per workgroup of the forward and
-of the back-projection kernel (each wave owns one 64x16 output tile; more
-waves split a tile's boxes more finely), one workgroup per work unit versus a
-persistent grid -- and, if asked, for several calibration box sides B (the
-window halo is B-1 pixels), and keeps the fastest.  Timing uses HIP events on
-the current stream; nothing here changes results beyond the summation order
-inside a tile.
+Candidate configurations of a batch:
+
+* forward projection: the region path with each region shape (16 x 16,
+  32 x 8 and 8 x 32 FPA pixels per lane group, i.e. two fast-axis widths and
+  two slow-axis heights around the square one) and 2, 3 or 4 wavefronts per
+  workgroup, or the tile path (64 x 16 FPA tiles) with 4, 8 or 16;
+* one workgroup per work unit, or a persistent grid whose workgroups walk
+  the unit list;
+* then the calibration box side B (the window halo is B - 1 pixels) one
+  below and one above the plan's own choice, with the winning launch setup.
+
+Two arrangements are tuned and timed whole: every frame in one batch with
+one configuration (one launch per kernel and EM iteration), and a
+configuration per frame shape (field stop, wavelengths, FPA), each tuned on
+its shape's frames, with one batch per distinct winner run back to back.  The
+faster arrangement is kept (`TunedBatch`).  Timing uses HIP events on the
+current stream.  Nothing here changes results beyond the summation order of
+the projections.
 """
 from __future__ import annotations
 
 import dataclasses
-import itertools
+
+import numpy as np
 
 from . import ctis
 
+REGION_SHAPES = ((16, 16), (32, 8), (8, 32))
+REGION_WAVES = (2, 3, 4)
+TILE_WAVES = (4, 8, 16)
 
-@dataclasses.dataclass
-class TuneResult:
-    batch: "ctis.Batch"
-    waves_forward: int
-    waves_adjoint: int
+
+@dataclasses.dataclass(frozen=True)
+class Choice:
+    """A launch configuration of one batch."""
+    path: str                     # "region" or "tile"
+    shape: tuple | None           # region shape (pixels along gamma, xi); None on the tile path
+    waves: int                    # wavefronts per forward workgroup
     persistent: bool
-    box: int
-    ms_per_iter: float
-    table: list
+    box: int                      # calibration box side B (0: the plan's choice)
+
+    def label(self) -> str:
+        sh = f"{self.shape[0]}x{self.shape[1]}" if self.shape else "64x16"
+        return (f"{self.path} {sh} W{self.waves}{' persistent' if self.persistent else ''}"
+                f" B{self.box if self.box else 'auto'}")
 
 
 def _time_em(torch, batch, g_all, iters: int, reps: int) -> float:
+    """Best time (ms) of one EM iteration of the batch over `reps` runs of
+    `iters` iterations."""
     ws = batch.workspace()
-    f = torch.ones(int(batch.f_offsets[-1]), dtype=torch.float32, device=batch.device)
+    f = torch.ones(batch.m_total, dtype=torch.float32, device=batch.device)
     batch.em(g_all, 1, f_all=f, workspace=ws)          # warm-up (code objects, caches)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -45,47 +66,182 @@ def _time_em(torch, batch, g_all, iters: int, reps: int) -> float:
     return best
 
 
-def autotune_batch(plans, g_all, iters: int = 4, reps: int = 3, waves=(4, 8, 16),
-                   persistent=(False, True)) -> TuneResult:
-    """Fastest launch configuration for a batch over ``plans`` (frames) with
-    the packed images ``g_all``."""
-    import torch
-    B = plans[0].info.box
-    max_w = 16 if B <= 5 else 8
-    cands = [(wf, wa, pe) for wf, wa, pe in itertools.product(waves, waves, persistent)
-             if wf <= max_w and wa <= max_w]
-    table = []
-    best = None
-    for wf, wa, pe in cands:
-        b = ctis.Batch(plans, waves_forward=wf, waves_adjoint=wa, persistent=pe)
-        ms = _time_em(torch, b, g_all, iters, reps)
-        table.append({"waves_forward": wf, "waves_adjoint": wa, "persistent": pe, "box": B, "ms_per_iter": ms})
-        if best is None or ms < best[0]:
-            if best is not None:
-                best[1].close()
-            best = (ms, b, wf, wa, pe)
-        else:
-            b.close()
-    ms, b, wf, wa, pe = best
-    return TuneResult(b, wf, wa, pe, B, ms, table)
+def _plans(cases, choice: Choice, cache: dict):
+    """Plans of the cases for a choice's box side and region shape (cached)."""
+    key = (choice.box, choice.shape)
+    if key not in cache:
+        kw = {"box": choice.box}
+        if choice.shape:
+            kw["region"] = choice.shape
+        cache[key] = [ctis.Plan.from_case(c, **kw) for c in cases]
+    return cache[key]
 
 
-def autotune_cases(cases, images, boxes=(0,), **kw) -> TuneResult:
-    """Also tune the box side: for each B in ``boxes`` (0 = the plan's own
-    choice) build the frames' plans with that B and tune the batch; return
-    the fastest.  ``images`` are the frames' FPA images (host arrays)."""
+def _batch(plans, choice: Choice):
+    if choice.path == "region":
+        return ctis.Batch(plans, waves_region=choice.waves, persistent=choice.persistent)
+    return ctis.Batch(plans, waves_forward=choice.waves, persistent=choice.persistent, tile_path=True)
+
+
+def _candidates(region_ok: bool, box: int):
+    out = []
+    for pe in (False, True):
+        if region_ok:
+            out += [Choice("region", sh, w, pe, 0) for sh in REGION_SHAPES for w in REGION_WAVES]
+        out += [Choice("tile", None, w, pe, 0) for w in TILE_WAVES if w <= (16 if box <= 5 else 8)]
+    return out
+
+
+def tune_frames(torch, cases, images, iters: int, reps: int, table: list, cls: str):
+    """Fastest Choice for one batch over `cases`; appends every timing to
+    `table`."""
+    cache = {}
+    base = _plans(cases, Choice("tile", None, 4, False, 0), cache)
+    B0 = base[0].info.box
     best = None
-    table = []
-    for B in boxes:
-        plans = [ctis.Plan.from_case(c, box=B) for c in cases]
+
+    def trial(choice):
+        nonlocal best
+        plans = _plans(cases, choice, cache)
+        if choice.path == "region" and not all(p.info.em_region_path for p in plans):
+            return
         if len({p.info.box for p in plans}) != 1:
-            continue
-        batch0 = ctis.Batch(plans)
-        g_all = batch0.pack_g(images)
-        batch0.close()
-        r = autotune_batch(plans, g_all, **kw)
-        table.extend(r.table)
-        if best is None or r.ms_per_iter < best.ms_per_iter:
-            best = r
-    best.table = table
-    return best
+            return
+        try:
+            b = _batch(plans, choice)
+        except ctis.CtisError:            # a launch setup the box side does not allow
+            return
+        g_all = b.pack_g(images)
+        ms = _time_em(torch, b, g_all, iters, reps)
+        b.close()
+        table.append({"frames": cls, "choice": choice.label(), "ms_per_iter": ms})
+        if best is None or ms < best[0]:
+            best = (ms, choice)
+
+    region_ok = all(p.info.em_region_path for p in base)
+    for ch in _candidates(region_ok, B0):
+        trial(ch)
+    # the halo: box sides around the plan's choice with the winning launch setup
+    ms0, ch0 = best
+    for B in (B0 - 1, B0 + 1):
+        if 1 <= B <= 8:
+            trial(dataclasses.replace(ch0, box=B))
+    for plans in cache.values():
+        for p in plans:
+            p.close()
+    return best[1], best[0]
+
+
+class TunedBatch:
+    """Frames of uneven shapes, reconstructed as one batch per distinct tuned
+    configuration.  Buffers are packed in the tuned frame order: frame k
+    (original index) holds f_all[f_offsets[pos[k]] : ...] with pos the
+    inverse of `order`."""
+
+    def __init__(self, cases, groups):
+        # groups: list of (choice, [original frame indices])
+        self.groups = []
+        self.order = [k for _, idx in groups for k in idx]
+        self.pos = np.empty(len(self.order), np.int64)
+        self.pos[self.order] = np.arange(len(self.order))
+        f0 = g0 = 0
+        self.f_offsets, self.g_offsets = [0], [0]
+        for choice, idx in groups:
+            kw = {"box": choice.box}
+            if choice.shape:
+                kw["region"] = choice.shape
+            plans = [ctis.Plan.from_case(cases[k], **kw) for k in idx]
+            b = _batch(plans, choice)
+            self.groups.append((choice, idx, plans, b, f0, g0))
+            for p in plans:
+                f0 += p.sizes.m
+                g0 += p.sizes.n
+                self.f_offsets.append(f0)
+                self.g_offsets.append(g0)
+        self.f_offsets = np.array(self.f_offsets, np.int64)
+        self.g_offsets = np.array(self.g_offsets, np.int64)
+        self.device = self.groups[0][3].device
+
+    @property
+    def m_total(self) -> int:
+        return int(self.f_offsets[-1])
+
+    def pack_g(self, images):
+        """Images of the frames (original order) packed in the tuned order."""
+        torch = ctis._torch()
+        return torch.cat([torch.as_tensor(images[k], dtype=torch.float32, device=self.device).reshape(-1)
+                          for k in self.order])
+
+    def frame_f(self, f_all, k):
+        """View of original frame k's datacube in a packed f_all."""
+        j = int(self.pos[k])
+        return f_all[self.f_offsets[j]:self.f_offsets[j + 1]]
+
+    def workspace(self):
+        """One workspace for every group (the groups run one after another)."""
+        torch = ctis._torch()
+        nbytes = max(b.info["workspace_bytes"] for _, _, _, b, _, _ in self.groups)
+        return torch.empty(max(nbytes // 4, 64), dtype=torch.float32, device=self.device)
+
+    def em(self, g_all, iters: int, f_all=None, workspace=None):
+        torch = ctis._torch()
+        if f_all is None:
+            f_all = torch.ones(self.m_total, dtype=torch.float32, device=self.device)
+        if workspace is None:
+            workspace = self.workspace()
+        for _, _, _, b, f0, g0 in self.groups:
+            b.em(g_all[g0:g0 + b.n_total], iters, f_all=f_all[f0:f0 + b.m_total], workspace=workspace)
+        return f_all
+
+    def report(self):
+        return [{"choice": ch.label(), "frames": len(idx)} for ch, idx, _, _, _, _ in self.groups]
+
+    def close(self):
+        for _, _, plans, b, _, _ in self.groups:
+            b.close()
+            for p in plans:
+                p.close()
+
+
+@dataclasses.dataclass
+class TuneResult:
+    batch: TunedBatch
+    arrangement: str              # "uniform" or "per shape"
+    ms_per_iter: dict             # whole-batch EM iteration time of both arrangements
+    uniform: str                  # the uniform arrangement's configuration
+    classes: list                 # per frame shape: its frames and the configuration tuned on them
+    table: list                   # every timing
+
+
+def autotune_frames(cases, images, iters: int = 4, reps: int = 3) -> TuneResult:
+    """Tune both arrangements and keep the faster.  `cases` carry each frame's
+    geometry and calibration (workloads.Case); `images` are the frames' FPA
+    images (host arrays)."""
+    import torch
+    table = []
+    everything = list(range(len(cases)))
+    uni, _ = tune_frames(torch, cases, images, iters, reps, table, "all")
+    classes = {}
+    for k, c in enumerate(cases):
+        g = c.geometry
+        classes.setdefault((g.a, g.alpha, g.w, g.gamma, g.xi), []).append(k)
+    chosen = []
+    for key, idx in classes.items():
+        cls = "a={} alpha={} w={} FPA {}x{}".format(*key)
+        choice, ms = tune_frames(torch, [cases[k] for k in idx], [images[k] for k in idx], iters, reps, table, cls)
+        chosen.append(({"class": cls, "frames": len(idx), "choice": choice.label(), "ms_per_iter": ms}, choice, idx))
+    merged = {}
+    for _, ch, idx in chosen:
+        merged.setdefault(ch, []).extend(idx)
+    arrangements = {"uniform": [(uni, everything)],
+                    "per shape": [(ch, sorted(idx)) for ch, idx in merged.items()]}
+    timed = {}
+    for name, groups in arrangements.items():
+        tb = TunedBatch(cases, groups)
+        timed[name] = (_time_em(torch, tb, tb.pack_g(images), iters, reps), tb)
+    keep = min(timed, key=lambda k: timed[k][0])
+    for name, (_, tb) in timed.items():
+        if name != keep:
+            tb.close()
+    return TuneResult(timed[keep][1], keep, {k: v[0] for k, v in timed.items()}, uni.label(),
+                      [c for c, _, _ in chosen], table)

@@ -109,6 +109,24 @@ def test_c4_batch_matches_oracle_every_frame(torch, ctis, c4):
     assert worst <= 1e-5
 
 
+def test_tuned_batch_matches_oracle_every_frame(torch, ctis, c4):
+    """The autotuned reconstruction (a configuration per frame shape: forward
+    path, region shape, waves, persistent grid, box side; one batch per
+    distinct choice) gives every one of the 64 frames its oracle result."""
+    from paper_2006_01573_amd import tune
+    cfgs, cases, plans, images, expected = c4
+    K = cfgs[0].iters
+    res = tune.autotune_frames(cases, images, iters=2, reps=1)
+    log(f"c4 tuned: {res.classes}")
+    assert sum(c["frames"] for c in res.classes) == len(cases)
+    tb = res.batch
+    f_all = tb.em(tb.pack_g(images), K)
+    for k in range(len(cases)):
+        e = rel_l2(tb.frame_f(f_all, k).cpu().numpy(), expected[k])
+        assert e <= EM_TOL, f"frame {k} ({cfgs[k].name}, {res.classes}) rel-L2 {e:.3e}"
+    tb.close()
+
+
 def test_batch_em_in_a_hip_graph(torch, ctis, c4):
     """The batched EM loop captured in a HIP graph and replayed several times,
     with eager work and synchronisations in between, reproduces the eager
