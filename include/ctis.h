@@ -339,7 +339,8 @@ typedef struct {
 
 /* Create a batch over n_frames >= 1 frames.  flags: CTIS_BATCH_WAVES_FORWARD /
  * _ADJOINT (waves per workgroup of the tile kernels, 4..16 for B <= 5 and
- * 4..8 above, or 0 for the built-in choice), CTIS_BATCH_WAVES_REGION (region
+ * 4..8 above, 1 for a wave per unit that walks all the unit's boxes, or 0 for
+ * the built-in choice), CTIS_BATCH_WAVES_REGION (region
  * forward, 1..8 or 0), CTIS_BATCH_PERSISTENT, CTIS_BATCH_TILE_PATH.  Errors:
  * CTIS_E_ARG (different B, host-only or other-device plan, bad flags),
  * CTIS_E_TOO_LARGE (f_all of 2^29 floats or more, g_all of 2^31 or more),

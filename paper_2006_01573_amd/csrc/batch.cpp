@@ -65,9 +65,9 @@ ctis_status ctis_batch_create(ctis_batch **out, const ctis_plan *const *plans, i
     }
     const int B = plans[0]->ht.B;
     for (int nw : {wf, wa})
-        if (nw != 0 && (nw < min_waves() || nw > max_waves(B)))
-            return fail(CTIS_E_ARG, "waves per workgroup must be 0 or in " + std::to_string(min_waves()) + ".." +
-                                        std::to_string(max_waves(B)));
+        if (nw != 0 && nw != 1 && (nw < min_waves() || nw > max_waves(B)))
+            return fail(CTIS_E_ARG, "waves per workgroup must be 0, 1 (a wave per unit) or in " +
+                                        std::to_string(min_waves()) + ".." + std::to_string(max_waves(B)));
     const int wr = (int)((flags >> 11) & 0xFu);
     if (wr > kFwdMaxWaves)
         return fail(CTIS_E_ARG, "region waves per workgroup must be 0 or in 1.." + std::to_string(kFwdMaxWaves));

@@ -43,6 +43,7 @@ namespace {
 constexpr int TX = kTileFast;
 constexpr int TY = kTileSlow;
 constexpr int kMinWaves = 4;                     // so that a wave owns <= 4 epilogue rows
+constexpr int kSoloWaves = 4;                    // solo kernels: units (waves) per workgroup
 constexpr int kRowsPerWave = TY / kMinWaves;
 constexpr unsigned kOutOfRange = 0x80000000u;   // buffer offset past num_records -> 0
 constexpr int kRsrcWord3 = 0x00020000;           // raw 32-bit buffer, gfx9 family
@@ -894,6 +895,204 @@ __global__ void __launch_bounds__(64 * Win<B>::MAXW) k_adjoint(const int4 *__res
 }
 
 // ---------------------------------------------------------------------------
+// Solo variants of the tile kernels: every wavefront owns a whole work unit
+// (one FPA tile, or one wavelength's field-stop tile) and walks all its boxes
+// with one window in flight; no cross-wave reduction, no workgroup barrier.
+// A lane writes its 4 x 4 micro-tile itself.  For batches of many small units
+// (few boxes each), where splitting a unit's boxes over the waves of a
+// workgroup leaves each wave too few items to hide a window load.
+
+// Per-lane epilogue positions: output (tx, ty) of the 64 x 16 tile for
+// micro-tile element (k, q) of lane (lx, ly): tx = 4 lx + q, ty = 4 ly + k.
+template <int B>
+__global__ void __launch_bounds__(256) k_forward_solo(const int4 *__restrict__ meta,
+                                                      const int4 *__restrict__ items, const int stride,
+                                                      const int n_units, const float *__restrict__ box_wf,
+                                                      const float *__restrict__ f, const float *__restrict__ g,
+                                                      const float *__restrict__ uaux, float *__restrict__ out,
+                                                      float *__restrict__ partials, const int mode) {
+    using Wn = Win<B>;
+    extern __shared__ float4 lds4[];
+    float *lds = reinterpret_cast<float *>(lds4);
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nw = blockDim.x >> 6;
+    float *S = lds + wv * Wn::WREG;
+    const int lx = lane & 15, ly = lane >> 4;
+
+    unsigned xs[Wn::NXT > 0 ? Wn::NXT : 1];
+#pragma unroll
+    for (int t = 0; t < Wn::NXT; ++t) {
+        const int kk = lane + 64 * t;
+        xs[t] = kk < Wn::E * Wn::SY ? (unsigned)(kk % Wn::ED) + 64u * (unsigned)(kk / Wn::ED) : ~0u;
+    }
+
+    for (int unit = blockIdx.x * nw + wv; unit < n_units; unit += gridDim.x * nw) {
+        const int4 *list = items + (size_t)unit * stride;
+        const int4 m0 = meta[3 * unit], m1 = meta[3 * unit + 1], m2 = meta[3 * unit + 2];
+        const Geo geo{m1.x, m1.y, m1.z, m1.w};
+        const int r0 = m0.x, c0 = m0.y;
+        const bool whole = m0.z == 1;
+        int k = 0;
+        int4 rec0 = record(list, 0, stride);
+        int4 rec1 = record(list, 1, stride);
+
+        float acc[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[a][q] = 0.0f;
+
+        Pending<B> pa;
+        if (rec0.w >= 0) {
+            if (rec0.z & kDirectFlag)
+                load_forward_direct<B>(pa, f, box_wf, geo, rec0, lane, xs);
+            else
+                load_forward<B>(pa, f, box_wf, geo, rec0, lane);
+        }
+        while (rec0.w >= 0) {
+            store_window<B>(S, pa, lane);
+            wave_lds_sync();
+            k += 1;
+            const int4 rec3 = record(list, k + 1, stride);
+            if (rec1.w >= 0) {
+                if (rec1.z & kDirectFlag)
+                    load_forward_direct<B>(pa, f, box_wf, geo, rec1, lane, xs);
+                else
+                    load_forward<B>(pa, f, box_wf, geo, rec1, lane);
+            }
+            correlate<B, Win<B>::SXP, Win<B>::REG>(acc, S, lx, ly);
+            wave_lds_sync();
+            rec0 = rec1;
+            rec1 = rec3;
+        }
+
+#pragma unroll
+        for (int kq = 0; kq < 4; ++kq) {
+            const int ty = 4 * ly + kq, c = c0 + ty;
+            if (!whole) {
+                *reinterpret_cast<float4 *>(partials + (size_t)m0.w * (TX * TY) + ty * TX + 4 * lx) =
+                    make_float4(acc[kq][0], acc[kq][1], acc[kq][2], acc[kq][3]);
+                continue;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = r0 + 4 * lx + q;
+                if (r < geo.gamma && c < geo.xi) {
+                    const size_t i = (size_t)r + (size_t)geo.gamma * c;
+                    const float gv = mode != kFwdPlain ? g[(size_t)m2.x + i] : 0.0f;
+                    const float uv = mode == kFwdVjp ? uaux[(size_t)m2.y + i] : 0.0f;
+                    out[(size_t)m2.y + i] = fwd_epilogue(mode, acc[kq][q], gv, uv);
+                }
+            }
+        }
+    }
+}
+
+template <int B>
+__global__ void __launch_bounds__(256) k_adjoint_solo(const int4 *__restrict__ meta,
+                                                      const int4 *__restrict__ items, const int stride,
+                                                      const int n_units, const float *__restrict__ box_w,
+                                                      const float *__restrict__ hsum, const float *__restrict__ u,
+                                                      const float *in1, const float *__restrict__ in2, float *out,
+                                                      float *__restrict__ out2, float *__restrict__ flux,
+                                                      const int mode, float *__restrict__ fpad, const int hx,
+                                                      const int hy) {
+    using Wn = Win<B>;
+    extern __shared__ float4 lds4[];
+    float *lds = reinterpret_cast<float *>(lds4);
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nw = blockDim.x >> 6;
+    float *S = lds + wv * Wn::WREG;
+    const int lx = lane & 15, ly = lane >> 4;
+
+    for (int unit = blockIdx.x * nw + wv; unit < n_units; unit += gridDim.x * nw) {
+        const int4 m0 = meta[3 * unit], m1 = meta[3 * unit + 1], m2 = meta[3 * unit + 2];
+        const int4 *list = items + (size_t)m0.z * stride;
+        const Geo geo{m1.x, m1.y, m1.z, m1.w};
+        const int x0 = m0.x, y0 = m0.y;
+        const __amdgpu_buffer_rsrc_t ur = rsrc(u + (size_t)(unsigned)m2.x, geo.gamma * geo.xi);
+        const size_t sb = (size_t)(unsigned)m0.w;
+        const float hs = hsum[m0.z];
+        int k = 0;
+        int4 rec0 = record(list, 0, stride);
+        int4 rec1 = record(list, 1, stride);
+
+        unsigned xo[Wn::NXT > 0 ? Wn::NXT : 1];
+#pragma unroll
+        for (int t = 0; t < Wn::NXT; ++t) {
+            const int kk = lane + 64 * t;
+            xo[t] = kk < Wn::E * Wn::SY ? 4u * (unsigned)(TX + kk % Wn::ED) + 4u * (unsigned)geo.gamma *
+                                                                                   (unsigned)(kk / Wn::ED)
+                                        : 0u;
+        }
+
+        float acc[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[a][q] = 0.0f;
+
+        Pending<B> pa;
+        if (rec0.w >= 0) {
+            if (rec0.z)
+                load_adjoint_direct<B>(pa, ur, box_w, geo, rec0.x + x0, rec0.y + y0, rec0.w, lane, xo);
+            else
+                load_adjoint<B>(pa, ur, box_w, geo, rec0.x + x0, rec0.y + y0, rec0.w, lane);
+        }
+        while (rec0.w >= 0) {
+            store_window<B>(S, pa, lane);
+            wave_lds_sync();
+            k += 1;
+            const int4 rec3 = record(list, k + 1, stride);
+            if (rec1.w >= 0) {
+                if (rec1.z)
+                    load_adjoint_direct<B>(pa, ur, box_w, geo, rec1.x + x0, rec1.y + y0, rec1.w, lane, xo);
+                else
+                    load_adjoint<B>(pa, ur, box_w, geo, rec1.x + x0, rec1.y + y0, rec1.w, lane);
+            }
+            correlate<B, Win<B>::SXP, Win<B>::REG>(acc, S, lx, ly);
+            wave_lds_sync();
+            rec0 = rec1;
+            rec1 = rec3;
+        }
+
+        float fl = 0.0f;   // this lane's share of sum b zeta (kAdjVjpPre)
+#pragma unroll
+        for (int kq = 0; kq < 4; ++kq) {
+            const int y = y0 + 4 * ly + kq;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int x = x0 + 4 * lx + q;
+                if (x < geo.a && y < geo.alpha) {
+                    const size_t o = sb + (size_t)x + (size_t)geo.a * y;
+                    const float v = acc[kq][q];
+                    if (mode == kAdjPlain) {
+                        out[o] = v;
+                    } else if (mode == kAdjUpdate) {
+                        const float nf = hs != 0.0f ? (in1[o] * v) / hs : 0.0f;
+                        out[o] = nf;
+                        if (fpad) fpad[(size_t)m2.y + (size_t)(x + hx) + (size_t)m2.z * (size_t)(y + hy)] = nf;
+                    } else if (mode == kAdjVjpPre) {
+                        const float bj = hs != 0.0f ? (in1[o] * in2[o]) / hs : 0.0f;
+                        out[o] = v;
+                        out2[o] = bj;
+                        fl = __builtin_fmaf(bj, v, fl);
+                    } else {
+                        out[o] = (hs != 0.0f ? (in1[o] * in2[o]) / hs : 0.0f) + v;
+                    }
+                }
+            }
+        }
+        if (mode == kAdjVjpPre) {
+            fl = wave_sum(fl);
+            if (lane == 0) flux[unit] = fl;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Derivatives with respect to the calibration values.
 //
 // For box (rA, cA) of wavelength s and its slot (dr, dc), the entry at FPA
@@ -1258,6 +1457,21 @@ int forward_B(const DevWork &w, const float *x, const float *g, const float *u, 
               hipStream_t st) {
     const DevList &L = mode == kFwdPlain ? w.fwd_full : w.fwd_em;
     if (L.n_units == 0) return 0;
+    if (L.waves == 1) {   // solo: four units per workgroup, a wave each
+        float *partials = (mode != kFwdPlain && w.n_split > 0) ? (float *)((char *)workspace + w.partials_off) : nullptr;
+        const size_t lds = (size_t)kSoloWaves * Win<B>::WREG * sizeof(float);
+        const int groups = (L.n_units + kSoloWaves - 1) / kSoloWaves;
+        hipLaunchKernelGGL(k_forward_solo<B>, dim3(grid_for(groups, lds, kSoloWaves, w.persistent)),
+                           dim3(64 * kSoloWaves), lds, st, L.meta, L.items, L.stride, L.n_units, w.box_wf, x, g, u,
+                           out, partials, mode);
+        if (partials) {
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return (int)e;
+            hipLaunchKernelGGL(k_finish_split, dim3(w.n_split), dim3(256), 0, st, w.split_meta,
+                               (const float *)partials, g, u, out, mode);
+        }
+        return (int)hipGetLastError();
+    }
     const size_t lds = (size_t)L.waves * Win<B>::WREG * sizeof(float);
     if (lds > 65536) {
         const int e = enable_large_lds<B>();
@@ -1321,6 +1535,14 @@ int adjoint_B(const DevWork &w, const float *r, const float *in1, const float *i
               float *flux, int mode, hipStream_t st, float *fpad) {
     const DevList &L = w.adj;
     if (L.n_units == 0) return 0;
+    if (L.waves == 1) {   // solo: four units per workgroup, a wave each
+        const size_t lds = (size_t)kSoloWaves * Win<B>::WREG * sizeof(float);
+        const int groups = (L.n_units + kSoloWaves - 1) / kSoloWaves;
+        hipLaunchKernelGGL(k_adjoint_solo<B>, dim3(grid_for(groups, lds, kSoloWaves, w.persistent)),
+                           dim3(64 * kSoloWaves), lds, st, L.meta, L.items, L.stride, L.n_units, w.box_w, w.h, r, in1,
+                           in2, out, out2, flux, mode, fpad, w.halo_x, w.halo_y);
+        return (int)hipGetLastError();
+    }
     const size_t lds = (size_t)L.waves * Win<B>::WREG * sizeof(float);
     if (lds > 65536) {
         const int e = enable_large_lds<B>();

@@ -8,6 +8,9 @@ Candidate configurations of a batch:
   workgroup, or the tile path (64 x 16 FPA tiles) with 4, 8 or 16;
 * one workgroup per work unit, or a persistent grid whose workgroups walk
   the unit list;
+* then, with the winning forward setup, the back projection's waves per
+  workgroup: the built-in choice, 4 or 8 waves sharing a unit's boxes, or a
+  wavefront per unit (1);
 * then the calibration box side B (the window halo is B - 1 pixels) one
   below and one above the plan's own choice, with the winning launch setup.
 
@@ -29,7 +32,8 @@ from . import ctis
 
 REGION_SHAPES = ((16, 16), (32, 8), (8, 32))
 REGION_WAVES = (2, 3, 4)
-TILE_WAVES = (4, 8, 16)
+TILE_WAVES = (1, 4, 8, 16)
+ADJOINT_WAVES = (1, 4, 8)
 
 
 @dataclasses.dataclass(frozen=True)
@@ -37,14 +41,15 @@ class Choice:
     """A launch configuration of one batch."""
     path: str                     # "region" or "tile"
     shape: tuple | None           # region shape (pixels along gamma, xi); None on the tile path
-    waves: int                    # wavefronts per forward workgroup
+    waves: int                    # wavefronts per forward workgroup (1: a wave per unit)
     persistent: bool
     box: int                      # calibration box side B (0: the plan's choice)
+    adj_waves: int = 0            # back projection's waves per workgroup (0: built-in, 1: a wave per unit)
 
     def label(self) -> str:
         sh = f"{self.shape[0]}x{self.shape[1]}" if self.shape else "64x16"
         return (f"{self.path} {sh} W{self.waves}{' persistent' if self.persistent else ''}"
-                f" B{self.box if self.box else 'auto'}")
+                f" adjoint W{self.adj_waves if self.adj_waves else 'auto'} B{self.box if self.box else 'auto'}")
 
 
 def _time_em(torch, batch, g_all, iters: int, reps: int) -> float:
@@ -79,8 +84,10 @@ def _plans(cases, choice: Choice, cache: dict):
 
 def _batch(plans, choice: Choice):
     if choice.path == "region":
-        return ctis.Batch(plans, waves_region=choice.waves, persistent=choice.persistent)
-    return ctis.Batch(plans, waves_forward=choice.waves, persistent=choice.persistent, tile_path=True)
+        return ctis.Batch(plans, waves_region=choice.waves, waves_adjoint=choice.adj_waves,
+                          persistent=choice.persistent)
+    return ctis.Batch(plans, waves_forward=choice.waves, waves_adjoint=choice.adj_waves,
+                      persistent=choice.persistent, tile_path=True)
 
 
 def _candidates(region_ok: bool, box: int):
@@ -121,6 +128,11 @@ def tune_frames(torch, cases, images, iters: int, reps: int, table: list, cls: s
     region_ok = all(p.info.em_region_path for p in base)
     for ch in _candidates(region_ok, B0):
         trial(ch)
+    # the back projection's launch setup with the winning forward one
+    _, chf = best
+    for wa in ADJOINT_WAVES:
+        if wa <= (16 if B0 <= 5 else 8):
+            trial(dataclasses.replace(chf, adj_waves=wa))
     # the halo: box sides around the plan's choice with the winning launch setup
     ms0, ch0 = best
     for B in (B0 - 1, B0 + 1):

@@ -109,6 +109,63 @@ def test_c4_batch_matches_oracle_every_frame(torch, ctis, c4):
     assert worst <= 1e-5
 
 
+@pytest.mark.parametrize("tile_path", [True, False], ids=["tile", "region"])
+def test_c4_solo_kernels_match_oracle_every_frame(torch, ctis, c4, tile_path):
+    """A wavefront per work unit (waves = 1: each wave walks all of its unit's
+    boxes and writes its own micro-tiles) in the back projection, and in the
+    forward projection on the tile path; every frame against its oracle,
+    also on a persistent grid."""
+    cfgs, cases, plans, images, expected = c4
+    K = cfgs[0].iters
+    for persistent in (False, True):
+        kw = {"waves_forward": 1} if tile_path else {}
+        b = ctis.Batch(plans, waves_adjoint=1, persistent=persistent, tile_path=tile_path, **kw)
+        assert b.info["waves_adjoint"] == 1 and (not tile_path or b.info["waves_forward"] == 1)
+        f_all = b.em(b.pack_g(images), K).cpu().numpy()
+        worst = max(rel_l2(f_all[b.f_offsets[k]:b.f_offsets[k + 1]], expected[k]) for k in range(len(plans)))
+        log(f"c4 solo tile_path={tile_path} persistent={persistent}: worst rel-L2 {worst:.2e}")
+        assert worst <= EM_TOL
+        b.close()
+
+
+def test_solo_projections_and_split_tiles(torch, ctis, oracle_mod):
+    """Solo forward and back projections of uneven frames (one frame's FPA
+    tiles carry more boxes than a unit takes, so they are split and summed by
+    the second kernel) against the oracle, for every box side."""
+    geo_hot = W.Geometry(8, 8, 90, 64, 48)
+    rng = np.random.default_rng(21)
+    ptr, idx, val = [0], [], []
+    for s in range(geo_hot.w):
+        r, c = 30 + rng.integers(0, 3), 20 + rng.integers(0, 3)
+        for dr in range(2):
+            idx.append(r + dr + geo_hot.gamma * c)
+            val.append(rng.uniform(0.2, 1.0))
+        ptr.append(len(idx))
+    hot = (np.array(ptr, np.int64), np.array(idx, np.int32), np.array(val, np.float32))
+    for box in (1, 3, 5, 8):
+        geos = [W.Geometry(5, 4, 3, 23, 17), W.Geometry(70, 6, 2, 90, 30), geo_hot]
+        kern = [W.random_kernels(g, 12, rng, clustered=True) for g in geos[:2]] + [hot]
+        plans = [ctis.Plan(g.a, g.alpha, g.w, g.gamma, g.xi, *k, box=box) for g, k in zip(geos, kern)]
+        b = ctis.Batch(plans, waves_forward=1, waves_adjoint=1, tile_path=True)
+        orc = [oracle_mod.Oracle(g.a, g.alpha, g.w, g.gamma, g.xi, *k) for g, k in zip(geos, kern)]
+        M, N = int(b.f_offsets[-1]), int(b.g_offsets[-1])
+        f = rng.random(M).astype(np.float32)
+        r = rng.random(N).astype(np.float32)
+        log(f"solo projections B={box}")
+        g_all = b.forward(torch.from_numpy(f).cuda()).cpu().numpy()
+        z_all = b.adjoint(torch.from_numpy(r).cuda()).cpu().numpy()
+        fo, go = b.f_offsets, b.g_offsets
+        for k in range(len(geos)):
+            assert rel_l2(g_all[go[k]:go[k + 1]], orc[k].forward(f[fo[k]:fo[k + 1]])) <= PROJ_TOL
+            assert rel_l2(z_all[fo[k]:fo[k + 1]], orc[k].adjoint(r[go[k]:go[k + 1]])) <= PROJ_TOL
+        gim = np.concatenate([orc[k].forward(np.ones(g.m)) * rng.uniform(0.5, 1.5, g.n)
+                              for k, g in enumerate(geos)]).astype(np.float32)
+        fe = b.em(torch.from_numpy(gim).cuda(), 6).cpu().numpy()
+        for k in range(len(geos)):
+            assert rel_l2(fe[fo[k]:fo[k + 1]], orc[k].em(gim[go[k]:go[k + 1]], 6)) <= EM_TOL
+        b.close()
+
+
 def test_tuned_batch_matches_oracle_every_frame(torch, ctis, c4):
     """The autotuned reconstruction (a configuration per frame shape: forward
     path, region shape, waves, persistent grid, box side; one batch per
