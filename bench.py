@@ -47,9 +47,10 @@ def kernel_source_sha() -> str:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def measured_traffic(config_id: int, kernel: str):
+def measured_traffic(config_id: int, kernel: str, choice: str | None = None):
     """HBM bytes per launch from committed rocprofv3 FETCH_SIZE / WRITE_SIZE
-    counters, if they were taken on the current kernel source."""
+    counters, if they were taken on the current kernel source (and, for the
+    batch, with the same launch choice)."""
     try:
         with open(TRAFFIC_FILE) as fh:
             d = json.load(fh)
@@ -57,8 +58,9 @@ def measured_traffic(config_id: int, kernel: str):
         return None
     if d.get("kernel_source_sha") != kernel_source_sha():
         return None
-    e = d.get("workloads", {}).get(str(config_id), {}).get(kernel)
-    if not e:
+    w = d.get("workloads", {}).get(str(config_id), {})
+    e = w.get(kernel)
+    if not e or (choice is not None and w.get("choice") != choice):
         return None
     return float(e["bytes_per_launch"])
 
@@ -126,6 +128,11 @@ def main(argv=None) -> int:
     ap.add_argument("--blob-radius", type=int, default=0, metavar="R",
                     help="with --path fourier: replace the configuration's calibration blobs by "
                          "(2R+1)^2 blobs (denser calibrations: the gather/Fourier crossover)")
+    ap.add_argument("--c4-choice", default="", metavar="LABEL",
+                    help="config 4: one batch with this launch choice (as the tuner labels it, e.g. "
+                         "'tile 64x16 W4 adjoint W1 Bauto') instead of autotuning")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="config 4: skip the 64 sequential single-frame solves")
     ap.add_argument("--tile-path", action="store_true",
                     help="configs 1-3: EM on the tile path (64 x 16 FPA tiles read straight from f) instead "
                          "of the region path (16 x 16 regions read from a zero-bordered copy of f)")
@@ -339,9 +346,14 @@ def bench_batched(args, torch, ctis, W, dev) -> int:
     for c, p in zip(cases, plans):
         clean = p.forward(torch.from_numpy(c.f_true.astype(np.float32)).to(dev)).double().cpu().numpy()
         images.append(c.noisy(clean))
-    progress("c4: autotuning per frame shape")
-    tuned = tune.autotune_frames(cases, images, iters=4, reps=3)
-    b = tuned.batch
+    if args.c4_choice:
+        progress(f"c4: one batch with the given launch choice ({args.c4_choice})")
+        tuned = None
+        b = tune.fixed_frames(cases, tune.Choice.parse(args.c4_choice))
+    else:
+        progress("c4: autotuning per frame shape")
+        tuned = tune.autotune_frames(cases, images, iters=4, reps=3)
+        b = tuned.batch
     g_all = b.pack_g(images)
     ws = b.workspace()
     f_all = torch.ones(b.m_total, dtype=torch.float32, device=dev)
@@ -374,56 +386,118 @@ def bench_batched(args, torch, ctis, W, dev) -> int:
     if not torch.isfinite(out).all() or (out < 0).any():
         print("bench.py: EM produced a negative or non-finite value", file=sys.stderr)
         return 1
-    # sequential: 64 plain single-frame solves per step
-    progress("c4: timing sequential single-frame solves")
-    gs = [torch.from_numpy(im).to(dev) for im in images]
-    fs = [torch.empty(p.shape_f, dtype=torch.float32, device=dev) for p in plans]
-    wss = [p.workspace() for p in plans]
+    seq = {}
+    if not args.no_sequential:
+        # sequential: 64 plain single-frame solves per step
+        progress("c4: timing sequential single-frame solves")
+        gs = [torch.from_numpy(im).to(dev) for im in images]
+        fs = [torch.empty(p.shape_f, dtype=torch.float32, device=dev) for p in plans]
+        wss = [p.workspace() for p in plans]
 
-    def seq_step():
-        for p, gk, fk, wk in zip(plans, gs, fs, wss):
-            fk.fill_(1.0)
-            p.em(gk, K, f=fk, workspace=wk)
+        def seq_step():
+            for p, gk, fk, wk in zip(plans, gs, fs, wss):
+                fk.fill_(1.0)
+                p.em(gk, K, f=fk, workspace=wk)
 
-    seq_step()
-    torch.cuda.synchronize()
-    seq_steps = max(1, args.steps // 2)
-    e0.record()
-    for _ in range(seq_steps):
         seq_step()
-    e1.record()
-    torch.cuda.synchronize()
-    seq_fps = 64 * seq_steps / (e0.elapsed_time(e1) / 1e3)
-    # the same 64 solves, each frame's solve replayed from its own HIP graph
-    progress("c4: timing sequential single-frame solves from HIP graphs")
-    graphs = []
-    for p, gk, fk, wk in zip(plans, gs, fs, wss):
-        def one(p=p, gk=gk, fk=fk, wk=wk):
-            fk.fill_(1.0)
-            p.em(gk, K, f=fk, workspace=wk)
-        graphs.append(_graph_of(torch, one))
-    e0.record()
-    for _ in range(seq_steps):
-        for gr_k in graphs:
-            gr_k.replay()
-    e1.record()
-    torch.cuda.synchronize()
-    seq_graph_fps = 64 * seq_steps / (e0.elapsed_time(e1) / 1e3)
-    # per-kernel durations of the batched EM halves (back to back, events around)
+        torch.cuda.synchronize()
+        seq_steps = max(1, args.steps // 2)
+        e0.record()
+        for _ in range(seq_steps):
+            seq_step()
+        e1.record()
+        torch.cuda.synchronize()
+        seq_fps = 64 * seq_steps / (e0.elapsed_time(e1) / 1e3)
+        # the same 64 solves, each frame's solve replayed from its own HIP graph
+        progress("c4: timing sequential single-frame solves from HIP graphs")
+        graphs = []
+        for p, gk, fk, wk in zip(plans, gs, fs, wss):
+            def one(p=p, gk=gk, fk=fk, wk=wk):
+                fk.fill_(1.0)
+                p.em(gk, K, f=fk, workspace=wk)
+            graphs.append(_graph_of(torch, one))
+        e0.record()
+        for _ in range(seq_steps):
+            for gr_k in graphs:
+                gr_k.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        seq_graph_fps = 64 * seq_steps / (e0.elapsed_time(e1) / 1e3)
+        seq = {"sequential_frames_per_s": seq_fps, "batched_vs_sequential": batched_fps / seq_fps,
+               "sequential_graph_frames_per_s": seq_graph_fps,
+               "batched_vs_sequential_graph": batched_fps / seq_graph_fps}
+    # per-kernel durations: each batch's EM halves launched `reps` times back
+    # to back inside a HIP graph (own workspace per batch, fixed inputs), HIP
+    # events around 5 replays on the graph's stream.  On the region path the
+    # forward half also writes the padded copy of f, which the EM loop does
+    # once per solve, so there the forward's duration is the batch's
+    # graph-launched EM iteration (`reps` iterations in one call) less its
+    # back projection.
+    progress("c4: per-kernel timing pass")
+    reps = 20
     infos = [p.info for p in plans]
     m_all = sum(i.m for i in infos)
     nsup = sum(i.n_support for i in infos)
     flops = sum(2 * i.ell * i.nnz for i in infos)
-    launches = 20
-    u_ws = ws
-    e0.record()
-    for _ in range(launches):
-        b.em(g_all, 1, f_all=f_all, workspace=u_ws)
-    e1.record()
-    torch.cuda.synchronize()
-    it_ms = e0.elapsed_time(e1) / launches
-    bytes_it = 4 * (3 * m_all + 3 * nsup)
-    achieved = bytes_it / (it_ms * 1e-3) / 1e9
+    parts = b.parts(g_all, f_all)
+    avg = {"forward_ratio": 0.0, "adjoint_update": 0.0}
+
+    def graph_time(fn):
+        gr = _graph_of(torch, fn)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(5):
+            gr.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / (5 * reps)
+
+    region_parts = 0
+    for bk, gk, fk in parts:
+        wk = bk.workspace()
+        f_in = fk.clone()
+        f_tmp = torch.empty_like(f_in)
+        bk.em_forward_ratio(f_in, gk, wk)
+        t_adj = graph_time(lambda: [bk.em_adjoint_update(wk, f_in, f_tmp) for _ in range(reps)])
+        if bk.info["em_region_path"]:
+            region_parts += 1
+            f_it = f_in.clone()
+            t_fwd = graph_time(lambda: bk.em(gk, reps, f_all=f_it, workspace=wk)) - t_adj
+        else:
+            t_fwd = graph_time(lambda: [bk.em_forward_ratio(f_in, gk, wk) for _ in range(reps)])
+        avg["adjoint_update"] += t_adj
+        avg["forward_ratio"] += t_fwd
+    it_s_total = avg["forward_ratio"] + avg["adjoint_update"]
+    bytes_ = {"forward_ratio": 4 * (m_all + 2 * nsup), "adjoint_update": 4 * (2 * m_all + nsup)}
+    dom = max(avg, key=avg.get)
+    t_hbm = bytes_[dom] / (HBM_PEAK_GBS * 1e9)
+    t_alu = flops / (FP32_VALU_PEAK_TFLOPS * 1e12)
+    groups = b.report()
+    traffic = measured_traffic(4, dom, groups[0]["choice"]) if len(groups) == 1 else None
+    if t_hbm >= t_alu:
+        achieved = bytes_[dom] / avg[dom] / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic}
+    else:
+        achieved = flops / avg[dom] / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP32_VALU_PEAK_TFLOPS, "traffic": traffic,
+                "frac_of_unpacked_fp32": achieved / FP32_VALU_UNPACKED_TFLOPS}
+    roof.update({"kernel": dom + " (all 64 frames)", "launches_per_iteration": len(parts),
+                 "forward_timing": ("EM iteration less back projection (graph launched)" if region_parts
+                                    else "graph of back-to-back forward halves"),
+                 "avg_launch_us": avg[dom] * 1e6,
+                 "algorithmic_bytes_per_launch": bytes_[dom], "algorithmic_flop_per_launch": flops,
+                 "other_kernel": {k: {"avg_launch_us": avg[k] * 1e6, "achieved_GBps": bytes_[k] / avg[k] / 1e9,
+                                      "achieved_TFLOPs": flops / avg[k] / 1e12}
+                                  for k in avg if k != dom},
+                 "hbm_GBps_per_iteration": (bytes_["forward_ratio"] + bytes_["adjoint_update"]) / it_s_total / 1e9})
+    if tuned is not None:
+        tuned_info = {"arrangement": tuned.arrangement, "batches": b.report(), "uniform_choice": tuned.uniform,
+                      "ms_per_iter_of_arrangements": tuned.ms_per_iter, "per_shape": tuned.classes,
+                      "candidates_timed": len(tuned.table)}
+    else:
+        tuned_info = {"arrangement": "given", "batches": b.report()}
     line = {
         "metric": METRIC,
         "value": batched_fps,
@@ -440,20 +514,10 @@ def bench_batched(args, torch, ctis, W, dev) -> int:
         "config": {"workload": "c4 64 uneven frames, a=alpha in {32,48,64}, w in {16,32}, FPA 256/512, "
                                "3x3 orders, 50 EM iterations each, one step = all 64 frames",
                    "frames": 64, "em_iters": K, "m_total": m_all, "n_support_total": nsup,
-                   "tuned": {"arrangement": tuned.arrangement, "batches": b.report(),
-                             "uniform_choice": tuned.uniform,
-                             "ms_per_iter_of_arrangements": tuned.ms_per_iter,
-                             "per_shape": tuned.classes, "candidates_timed": len(tuned.table)}},
-        "sequential_frames_per_s": seq_fps,
-        "batched_vs_sequential": batched_fps / seq_fps,
-        "sequential_graph_frames_per_s": seq_graph_fps,
-        "batched_vs_sequential_graph": batched_fps / seq_graph_fps,
-        "em_iteration_all_frames_us": it_ms * 1e3,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "forward_ratio + adjoint_update (one EM iteration of all frames)",
-                     "algorithmic_bytes_per_iteration": bytes_it,
-                     "algorithmic_flop_per_iteration": 2 * flops},
+                   "tuned": tuned_info},
+        **seq,
+        "em_iteration_all_frames_us": ms * 1e3 / (args.steps * K),
+        "roofline": roof,
     }
     print(json.dumps(line), flush=True)
     return 0

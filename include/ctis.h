@@ -358,6 +358,18 @@ ctis_status ctis_batch_adjoint(const ctis_batch *batch, const float *r_all, floa
  * ctis_em_iterate; CTIS_E_NEGATIVE if any plan has a negative value. */
 ctis_status ctis_batch_em_iterate(const ctis_batch *batch, const float *g_all, float *f_all, int32_t iters,
                                   void *workspace, size_t workspace_bytes, void *stream);
+/* The two halves of one EM iteration of every frame, as ctis_em_forward_ratio
+ * and ctis_em_adjoint_update for one frame (same semantics per frame, same
+ * argument checks, same workspace as ctis_batch_em_iterate): the forward half
+ * leaves u = g / (H f) of every frame at the start of the workspace (frame
+ * k's block at g_offset_k) and, on the region path, refreshes the padded copy
+ * of f_all that it reads; the update half reads u and writes f_out (f_in ==
+ * f_out allowed).  In sequence they give ctis_batch_em_iterate's result bit
+ * for bit. */
+ctis_status ctis_batch_em_forward_ratio(const ctis_batch *batch, const float *f_all, const float *g_all,
+                                        void *workspace, size_t workspace_bytes, void *stream);
+ctis_status ctis_batch_em_adjoint_update(const ctis_batch *batch, void *workspace, size_t workspace_bytes,
+                                         const float *f_in, float *f_out, void *stream);
 
 /*
  * Derivatives of EM (reverse mode), for losses of f after K unrolled

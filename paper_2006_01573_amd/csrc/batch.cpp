@@ -178,4 +178,40 @@ ctis_status ctis_batch_em_iterate(const ctis_batch *b, const float *g_all, float
     return em_loop(b->work, g_all, f_all, iters, workspace, stream);
 }
 
+ctis_status ctis_batch_em_forward_ratio(const ctis_batch *b, const float *f_all, const float *g_all, void *workspace,
+                                        size_t workspace_bytes, void *stream) {
+    if (!b) return fail(CTIS_E_ARG, "batch is NULL");
+    if (!g_all || !f_all || !aligned4(g_all) || !aligned4(f_all))
+        return fail(CTIS_E_ARG, "g_all and f_all must be non-NULL and 4-byte aligned");
+    if (!b->nonneg) return fail(CTIS_E_NEGATIVE, "a plan of the batch has a negative calibration value");
+    if (!workspace || workspace_bytes < b->work.workspace_bytes)
+        return fail(CTIS_E_WORKSPACE, "workspace needs " + std::to_string(b->work.workspace_bytes) + " bytes");
+    if (((uintptr_t)workspace & 255u) != 0) return fail(CTIS_E_WORKSPACE, "workspace must be 256-byte aligned");
+    const size_t fb = (size_t)b->f_floats * 4, gb = (size_t)b->g_floats * 4, wb = b->work.workspace_bytes;
+    if (overlaps(workspace, wb, f_all, fb) || overlaps(workspace, wb, g_all, gb))
+        return fail(CTIS_E_ARG, "the workspace must not overlap f_all or g_all");
+    ctis_status st = batch_device(b);
+    if (st != CTIS_OK) return st;
+    return em_forward_half(b->work, f_all, g_all, workspace, stream);
+}
+
+ctis_status ctis_batch_em_adjoint_update(const ctis_batch *b, void *workspace, size_t workspace_bytes,
+                                         const float *f_in, float *f_out, void *stream) {
+    if (!b) return fail(CTIS_E_ARG, "batch is NULL");
+    if (!f_in || !f_out || !aligned4(f_in) || !aligned4(f_out))
+        return fail(CTIS_E_ARG, "f_in and f_out must be non-NULL and 4-byte aligned");
+    if (!b->nonneg) return fail(CTIS_E_NEGATIVE, "a plan of the batch has a negative calibration value");
+    if (!workspace || workspace_bytes < b->work.workspace_bytes)
+        return fail(CTIS_E_WORKSPACE, "workspace needs " + std::to_string(b->work.workspace_bytes) + " bytes");
+    if (((uintptr_t)workspace & 255u) != 0) return fail(CTIS_E_WORKSPACE, "workspace must be 256-byte aligned");
+    const size_t fb = (size_t)b->f_floats * 4, wb = b->work.workspace_bytes;
+    if (f_in != f_out && overlaps(f_in, fb, f_out, fb)) return fail(CTIS_E_ARG, "f_in and f_out overlap");
+    if (overlaps(workspace, wb, f_out, fb)) return fail(CTIS_E_ARG, "the workspace and f_out overlap");
+    ctis_status st = batch_device(b);
+    if (st != CTIS_OK) return st;
+    return launched(launch_adjoint(b->work, (const float *)workspace, f_in, nullptr, f_out, nullptr, nullptr,
+                                   kAdjUpdate, stream, workspace),
+                    "batch adjoint+update launch");
+}
+
 }  // extern "C"

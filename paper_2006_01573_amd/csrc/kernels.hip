@@ -209,13 +209,16 @@ __device__ __forceinline__ void load_forward(Pending<B> &pd, const float *f, con
     load_values<B>(pd, wtab, rec.w, lane);
 }
 
-// Forward window of an item whose window runs inside the FPA without a
-// carry into the next column or a wrap round its end (decided on the host:
-// rec = (xr, y0, f_off | kDirectFlag, box) with the window origin decoded,
-// xr + 64 + B - 1 <= gamma, y0 + 16 + B - 1 <= xi): slot (xx, yy) is
-// f_s(xr + xx, y0 + yy) inside the field stop, 0 outside.  Columns past a
-// get the out-of-range offset; rows at or past alpha land at or past the
-// block's a*alpha floats and read 0.  One vector add per row.
+// Forward window of an item whose window reads the same values as a plain
+// 2-D window over a zero-bordered f_s (decided on the host, rec = (x0, y0,
+// f_off | kDirectFlag, box)): either the decoded origin runs inside the FPA
+// without a carry into the next column or a wrap round its end, or the
+// origin, possibly negative, keeps every position that the 1-D cyclic shift
+// wraps on an FPA column or row outside the field stop.  Slot (xx, yy) is
+// f_s(x0 + xx, y0 + yy) inside the field stop, 0 outside: a column outside
+// [0, a) (compared unsigned) gets the out-of-range offset; a row at or past
+// alpha lands at or past the block's a*alpha floats and a negative row wraps
+// the unsigned offset past it, both reading 0.  One vector add per row.
 template <int B>
 __device__ __forceinline__ void load_forward_direct(Pending<B> &pd, const float *f, const float *__restrict__ wtab,
                                                     const Geo &p, int4 rec, int lane, const unsigned (&xo)[
@@ -224,7 +227,7 @@ __device__ __forceinline__ void load_forward_direct(Pending<B> &pd, const float 
     const __amdgpu_buffer_rsrc_t fr = rsrc(f + (size_t)(unsigned)(rec.z & (kDirectFlag - 1)), p.a * p.alpha);
     const int xm = rec.x + lane;
     const unsigned stp = 4u * (unsigned)p.a;
-    const unsigned o0 = xm < p.a ? 4u * (unsigned)xm + stp * (unsigned)rec.y : kOutOfRange;
+    const unsigned o0 = (unsigned)xm < (unsigned)p.a ? 4u * (unsigned)xm + stp * (unsigned)rec.y : kOutOfRange;
 #pragma unroll
     for (int yy = 0; yy < Wn::SY; ++yy) pd.v[yy] = bload(fr, o0 + stp * (unsigned)yy);
     // extra slot t of this lane: column 64 + e, row yy, with xo[t] = (e, yy)
@@ -233,8 +236,9 @@ __device__ __forceinline__ void load_forward_direct(Pending<B> &pd, const float 
     for (int t = 0; t < Wn::NXT; ++t) {
         const int e = (int)(xo[t] & 63u), yy = (int)(xo[t] >> 6);
         const int xe = rec.x + TX + e;
-        pd.x[t] = bload(fr, (xo[t] != ~0u && xe < p.a) ? 4u * (unsigned)xe + stp * (unsigned)(rec.y + yy)
-                                                         : kOutOfRange);
+        pd.x[t] = bload(fr, (xo[t] != ~0u && (unsigned)xe < (unsigned)p.a)
+                                ? 4u * (unsigned)xe + stp * (unsigned)(rec.y + yy)
+                                : kOutOfRange);
     }
     load_values<B>(pd, wtab, rec.w, lane);
 }
@@ -287,12 +291,14 @@ __device__ __forceinline__ void load_adjoint(Pending<B> &pd, __amdgpu_buffer_rsr
     load_values<B>(pd, wtab, box, lane);
 }
 
-// Adjoint window of a box whose windows run inside the FPA without wrapping
-// for every tile of the field stop (Xs + 64 + B - 1 <= gamma and
-// Ys + 16 + B - 1 <= xi; flagged on the host): slot (xx, yy) at byte offset
+// Adjoint window of a box whose image of the dilated field stop runs inside
+// the FPA without a carry or a wrap, and whose last tile's window ends inside
+// u (flagged on the host): slot (xx, yy) at byte offset
 // 4*xx + 4*(Xs + gamma*(Ys + yy)), the second term wave-uniform (a scalar
-// offset), so the row loads take no vector arithmetic.  xo[t]: byte offset
-// of this lane's extra slot within the window (0 where it has none).
+// offset), so the row loads take no vector arithmetic.  Slots of lanes past
+// the field stop may hold other pixels of u; those lanes' outputs are never
+// written.  xo[t]: byte offset of this lane's extra slot within the window
+// (0 where it has none).
 template <int B>
 __device__ __forceinline__ void load_adjoint_direct(Pending<B> &pd, __amdgpu_buffer_rsrc_t ur,
                                                     const float *__restrict__ wtab, const Geo &p, int Xs, int Ys,
@@ -649,18 +655,6 @@ __global__ void __launch_bounds__(64 * kFwdMaxWaves) k_forward_region(
         int4 rec0 = record(list, k, stride);
         int4 rec1 = record(list, k + step, stride);
 
-        // operands of the epilogue (output o = tid + nt*j of the region), fetched up front
-        float gpre[kOut], upre[kOut];
-#pragma unroll
-        for (int j = 0; j < kOut; ++j) {
-            const int o = tid + nt * j;
-            const int r = r0 + o % RX, c = c0 + o / RX;
-            const bool in = o < kRegion && mode != kFwdPlain && whole && r < gamma && c < xi;
-            const size_t i = (size_t)r + (size_t)gamma * c;
-            gpre[j] = in ? g[(size_t)m2.x + i] : 0.0f;
-            upre[j] = (in && mode == kFwdVjp) ? uaux[(size_t)m2.y + i] : 0.0f;
-        }
-
         float acc[4][4];
 #pragma unroll
         for (int a = 0; a < 4; ++a)
@@ -686,6 +680,19 @@ __global__ void __launch_bounds__(64 * kFwdMaxWaves) k_forward_region(
                 rec0 = rec1;
                 rec1 = rec3;
             } while (__builtin_amdgcn_readfirstlane(rec0.w) >= 0);
+        }
+
+        // operands of the epilogue (output o = tid + nt*j of the region),
+        // fetched while the groups and waves are summed
+        float gpre[kOut], upre[kOut];
+#pragma unroll
+        for (int j = 0; j < kOut; ++j) {
+            const int o = tid + nt * j;
+            const int r = r0 + o % RX, c = c0 + o / RX;
+            const bool in = o < kRegion && mode != kFwdPlain && whole && r < gamma && c < xi;
+            const size_t i = (size_t)r + (size_t)gamma * c;
+            gpre[j] = in ? g[(size_t)m2.x + i] : 0.0f;
+            upre[j] = (in && mode == kFwdVjp) ? uaux[(size_t)m2.y + i] : 0.0f;
         }
 
         // sum of the four groups (lanes l, l^16, l^32 and l^48 hold the same

@@ -411,6 +411,17 @@ void push4(std::vector<int32_t> &v, int32_t a, int32_t b, int32_t c, int32_t d) 
     v.push_back(d);
 }
 
+// A window of sx x sy positions at the (undecoded, possibly negative) origin
+// (Xs, Ys) of E f_s reads exactly what a 2-D window over f_s bordered with
+// zeros reads, when no position of it lies past the FPA's last column or
+// row, and every position the 1-D cyclic shift carries into the previous
+// FPA column (a negative column) or round the end of the FPA (a negative row)
+// lands on a column at or past a, or a row at or past alpha, where E f_s is
+// 0: Xs > a - gamma and Ys > alpha - xi.
+bool direct_2d(int64_t Xs, int64_t Ys, int64_t a, int64_t alpha, int64_t gamma, int64_t xi, int64_t sx, int64_t sy) {
+    return Xs > a - gamma && Xs + sx <= gamma && Ys > alpha - xi && Ys + sy <= xi;
+}
+
 struct UnitRef {
     int32_t frame, tile, chunk, n_chunks, slot, work;
 };
@@ -596,6 +607,9 @@ ctis_status build_work(const std::vector<FrameRef> &frames, bool with_full, Host
                     const int32_t foff = (int32_t)(fr.f_base + (int64_t)s * pl->ell);
                     if (xr + kTileFast + B - 1 <= pl->gamma && y0 + kTileSlow + B - 1 <= pl->xi)
                         push4(L.items, (int32_t)xr, (int32_t)y0, foff | kDirectFlag, fbox[(size_t)ur.frame] + b);
+                    else if (direct_2d(Xs, Ys, pl->a, pl->alpha, pl->gamma, pl->xi, kTileFast + B - 1,
+                                       kTileSlow + B - 1))
+                        push4(L.items, (int32_t)Xs, (int32_t)Ys, foff | kDirectFlag, fbox[(size_t)ur.frame] + b);
                     else
                         push4(L.items, (int32_t)Xs, (int32_t)Ys, foff, fbox[(size_t)ur.frame] + b);
                     continue;
@@ -682,9 +696,18 @@ ctis_status build_work(const std::vector<FrameRef> &frames, bool with_full, Host
                 if (b0 + j < b1) {
                     rec[0] = T.box_rc[2 * (size_t)(b0 + j)];
                     rec[1] = T.box_rc[2 * (size_t)(b0 + j) + 1];
-                    // direct: the windows of every field-stop tile stay inside the FPA
-                    rec[2] = ((int64_t)rec[0] + (int64_t)T.nbx * kTileFast + B - 1 <= pl->gamma &&
-                              (int64_t)rec[1] + (int64_t)T.nby * kTileSlow + B - 1 <= pl->xi) ? 1 : 0;
+                    // direct: what the voxels inside the field stop read stays inside
+                    // the FPA (the box's image of the dilated field stop neither
+                    // carries into the next FPA column nor wraps round the FPA's
+                    // end), and the last tile's whole window ends inside u (the
+                    // loader's row offset is a scalar offset, which is kept in
+                    // bounds rather than left to the range check).  Lanes of a
+                    // tile past a or alpha may then read other pixels of u; their
+                    // outputs are never written.
+                    const int64_t last = (int64_t)rec[0] + (int64_t)T.nbx * kTileFast + B - 2 +
+                                         (int64_t)pl->gamma * ((int64_t)rec[1] + (int64_t)T.nby * kTileSlow + B - 2);
+                    rec[2] = ((int64_t)rec[0] + pl->a + B - 1 <= pl->gamma &&
+                              (int64_t)rec[1] + pl->alpha + B - 1 <= pl->xi && last < (int64_t)pl->n) ? 1 : 0;
                     rec[3] = hw.plan_box0[d] + b0 + j;
                 } else {
                     rec[3] = -1;

@@ -36,7 +36,7 @@ EXPORTED = ["ctis_plan_create", "ctis_plan_destroy", "ctis_plan_get_info",
             "ctis_forward", "ctis_adjoint", "ctis_em_iterate", "ctis_em_forward_ratio", "ctis_em_adjoint_update", "ctis_status_str",
             "ctis_last_error", "ctis_version", "ctis_batch_create", "ctis_batch_destroy",
             "ctis_batch_get_info", "ctis_batch_forward", "ctis_batch_adjoint", "ctis_batch_em_iterate",
-            "ctis_em_vjp", "ctis_plan_set_values", "ctis_batch_em_vjp", "ctis_batch_set_values",
+            "ctis_batch_em_forward_ratio", "ctis_batch_em_adjoint_update", "ctis_em_vjp", "ctis_plan_set_values", "ctis_batch_em_vjp", "ctis_batch_set_values",
             "ctis_batch_plan_entries", "ctis_fourier_create", "ctis_fourier_destroy", "ctis_fourier_get_info",
             "ctis_fourier_forward", "ctis_fourier_adjoint", "ctis_fourier_em_iterate"]
 
@@ -187,6 +187,10 @@ def load_library(path: str | None = None):
         L.ctis_batch_adjoint.restype = st
         L.ctis_batch_em_iterate.argtypes = [vp, vp, vp, i32, vp, sz, vp]
         L.ctis_batch_em_iterate.restype = st
+        L.ctis_batch_em_forward_ratio.argtypes = [vp, vp, vp, vp, sz, vp]
+        L.ctis_batch_em_forward_ratio.restype = st
+        L.ctis_batch_em_adjoint_update.argtypes = [vp, vp, sz, vp, vp, vp]
+        L.ctis_batch_em_adjoint_update.restype = st
         L.ctis_em_vjp.argtypes = [vp, vp, vp, vp, vp, vp, i32, vp, sz, vp]
         L.ctis_em_vjp.restype = st
         L.ctis_plan_set_values.argtypes = [vp, vp, vp]
@@ -688,6 +692,30 @@ class Batch:
                                            _stream(torch, self.device))
         _check(self._L, st, "ctis_batch_em_iterate")
         return f_all
+
+    def em_forward_ratio(self, f_all, g_all, workspace):
+        """u = g / (H f) of every frame into the start of the workspace (one EM
+        half of all frames)."""
+        torch = _torch()
+        need_tensor(f_all, self.m_total, "f_all", self.device)
+        need_tensor(g_all, self.n_total, "g_all", self.device)
+        wp, wb = self._ws(workspace, self.info["workspace_bytes"])
+        st = self._L.ctis_batch_em_forward_ratio(self._handle, ctypes.c_void_p(f_all.data_ptr()),
+                                                 ctypes.c_void_p(g_all.data_ptr()), wp, wb, _stream(torch, self.device))
+        _check(self._L, st, "ctis_batch_em_forward_ratio")
+        return workspace[: self.n_total]
+
+    def em_adjoint_update(self, workspace, f_in, f_out):
+        """f_out = f_in * (H^T u) / h of every frame, u from the workspace (the
+        other EM half)."""
+        torch = _torch()
+        need_tensor(f_in, self.m_total, "f_in", self.device)
+        need_tensor(f_out, self.m_total, "f_out", self.device)
+        wp, wb = self._ws(workspace, self.info["workspace_bytes"])
+        st = self._L.ctis_batch_em_adjoint_update(self._handle, wp, wb, ctypes.c_void_p(f_in.data_ptr()),
+                                                  ctypes.c_void_p(f_out.data_ptr()), _stream(torch, self.device))
+        _check(self._L, st, "ctis_batch_em_adjoint_update")
+        return f_out
 
     def diagnostics(self, g, f, workspace=None, out=None):
         """(flux sum_j h_j f_j, sum g, Poisson log-likelihood, pixels with g > 0

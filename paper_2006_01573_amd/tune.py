@@ -51,6 +51,23 @@ class Choice:
         return (f"{self.path} {sh} W{self.waves}{' persistent' if self.persistent else ''}"
                 f" adjoint W{self.adj_waves if self.adj_waves else 'auto'} B{self.box if self.box else 'auto'}")
 
+    @classmethod
+    def parse(cls, label: str) -> "Choice":
+        """The Choice a label() string names, e.g. "tile 64x16 W4 adjoint W1 Bauto"."""
+        t = label.split()
+        try:
+            path, sh, w = t[0], t[1], t[2]
+            persistent = "persistent" in t
+            rest = t[3 + persistent:]
+            if path not in ("region", "tile") or rest[0] != "adjoint" or not w.startswith("W"):
+                raise ValueError
+            shape = None if path == "tile" else tuple(int(x) for x in sh.split("x"))
+            aw = 0 if rest[1] == "Wauto" else int(rest[1][1:])
+            box = 0 if rest[2] == "Bauto" else int(rest[2][1:])
+            return cls(path, shape, int(w[1:]), persistent, box, aw)
+        except (IndexError, ValueError):
+            raise ValueError(f"not a launch choice: {label!r}") from None
+
 
 def _time_em(torch, batch, g_all, iters: int, reps: int) -> float:
     """Best time (ms) of one EM iteration of the batch over `reps` runs of
@@ -208,6 +225,10 @@ class TunedBatch:
     def report(self):
         return [{"choice": ch.label(), "frames": len(idx)} for ch, idx, _, _, _, _ in self.groups]
 
+    def parts(self, g_all, f_all):
+        """(batch, its slice of g_all, its slice of f_all) per group."""
+        return [(b, g_all[g0:g0 + b.n_total], f_all[f0:f0 + b.m_total]) for _, _, _, b, f0, g0 in self.groups]
+
     def close(self):
         for _, _, plans, b, _, _ in self.groups:
             b.close()
@@ -223,6 +244,11 @@ class TuneResult:
     uniform: str                  # the uniform arrangement's configuration
     classes: list                 # per frame shape: its frames and the configuration tuned on them
     table: list                   # every timing
+
+
+def fixed_frames(cases, choice: Choice) -> TunedBatch:
+    """Every frame in one batch with a given configuration (no tuning)."""
+    return TunedBatch(cases, [(choice, list(range(len(cases))))])
 
 
 def autotune_frames(cases, images, iters: int = 4, reps: int = 3) -> TuneResult:

@@ -166,6 +166,26 @@ def test_solo_projections_and_split_tiles(torch, ctis, oracle_mod):
         b.close()
 
 
+@pytest.mark.parametrize("tile_path", [True, False], ids=["tile", "region"])
+def test_batch_halves_compose_to_em_iterate(torch, ctis, c4, tile_path):
+    """The two EM halves of a batch (forward + ratio, then back projection +
+    update, which on the region path keeps the padded copy current) repeat
+    ctis_batch_em_iterate bit for bit."""
+    cfgs, cases, plans, images, _ = c4
+    b = ctis.Batch(plans[:12], tile_path=tile_path)
+    assert b.info["em_region_path"] == (0 if tile_path else 1)
+    g_all = b.pack_g(images[:12])
+    ref = b.em(g_all, 4)
+    f = torch.ones(b.m_total, device="cuda")
+    tmp = torch.empty_like(f)
+    ws = b.workspace()
+    for _ in range(4):
+        b.em_forward_ratio(f, g_all, ws)
+        b.em_adjoint_update(ws, f, tmp)
+        f, tmp = tmp, f
+    assert torch.equal(f, ref)
+
+
 def test_tuned_batch_matches_oracle_every_frame(torch, ctis, c4):
     """The autotuned reconstruction (a configuration per frame shape: forward
     path, region shape, waves, persistent grid, box side; one batch per
