@@ -320,6 +320,10 @@ ctis_status ctis_em_adjoint_update(const ctis_plan *plan, void *workspace, size_
                                           one workgroup per work unit                    */
 #define CTIS_BATCH_WAVES_REGION(n) (((uint32_t)(n) & 0xFu) << 11)  /* region forward, 0 = chosen */
 #define CTIS_BATCH_TILE_PATH 0x8000u   /* EM on the tile path even where the region path applies */
+#define CTIS_BATCH_REGION_SOLO 0x10000u /* region forward with a 16-lane group per region walking
+                                           all of its boxes (four regions per wavefront), for
+                                           batches of many short regions; the region waves
+                                           setting is then unused                          */
 
 typedef struct {
     int32_t n_frames;
@@ -341,7 +345,8 @@ typedef struct {
  * _ADJOINT (waves per workgroup of the tile kernels, 4..16 for B <= 5 and
  * 4..8 above, 1 for a wave per unit that walks all the unit's boxes, or 0 for
  * the built-in choice), CTIS_BATCH_WAVES_REGION (region
- * forward, 1..8 or 0), CTIS_BATCH_PERSISTENT, CTIS_BATCH_TILE_PATH.  Errors:
+ * forward, 1..8 or 0), CTIS_BATCH_PERSISTENT, CTIS_BATCH_TILE_PATH,
+ * CTIS_BATCH_REGION_SOLO.  Errors:
  * CTIS_E_ARG (different B, host-only or other-device plan, bad flags),
  * CTIS_E_TOO_LARGE (f_all of 2^29 floats or more, g_all of 2^31 or more),
  * CTIS_E_NOMEM, CTIS_E_HIP. */

@@ -39,7 +39,8 @@ ctis_status ctis_batch_create(ctis_batch **out, const ctis_plan *const *plans, i
     if (!out) return fail(CTIS_E_ARG, "out is NULL");
     *out = nullptr;
     if (!plans || n_frames < 1) return fail(CTIS_E_ARG, "need at least one plan");
-    if (flags & ~(0x3FFu | CTIS_BATCH_PERSISTENT | CTIS_BATCH_WAVES_REGION(0xF) | CTIS_BATCH_TILE_PATH))
+    if (flags & ~(0x3FFu | CTIS_BATCH_PERSISTENT | CTIS_BATCH_WAVES_REGION(0xF) | CTIS_BATCH_TILE_PATH |
+                  CTIS_BATCH_REGION_SOLO))
         return fail(CTIS_E_ARG, "unknown flag bits");
     const int wf = (int)(flags & 0x1Fu), wa = (int)((flags >> 5) & 0x1Fu);
     int dev = -1;
@@ -87,6 +88,7 @@ ctis_status ctis_batch_create(ctis_batch **out, const ctis_plan *const *plans, i
         if (flags & CTIS_BATCH_TILE_PATH) hw.pad_ok = false;
         st = upload_work(hw, b->work);
         b->work.persistent = (flags & CTIS_BATCH_PERSISTENT) != 0;
+        b->work.region_solo = (flags & CTIS_BATCH_REGION_SOLO) != 0;
     }
     if (st != CTIS_OK) {
         delete b;

@@ -115,6 +115,7 @@ struct DevWork {
     size_t diag_off = 0;         // byte offset of the diagnostics partials
     size_t workspace_bytes = 0;  // u region + partial tiles + partial regions + padded f + diagnostics
     bool persistent = false;     // grid-stride workgroups instead of one per unit
+    bool region_solo = false;    // region forward with a lane group per unit
     // value gradients and value updates
     const int32_t *entry_slot = nullptr, *box_lam = nullptr, *lam_box0 = nullptr;
     const int32_t *lam_units_ptr = nullptr, *lam_units = nullptr;

@@ -80,6 +80,21 @@ __device__ __forceinline__ int4 record(const int4 *__restrict__ list, int k, int
     return k < stride ? list[k] : make_int4(0, 0, 0, -1);
 }
 
+// Unit lists are ordered for one unit per workgroup, position p running on
+// XCD p mod 8 (workgroups are dealt to the 8 XCDs round-robin; batches put a
+// frame's units on one XCD).  A solo workgroup takes `per_wg` units, so
+// virtual workgroup v (blockIdx.x, then strided by the grid, a multiple of 8
+// when persistent) takes the positions 8 (per_wg (v / 8) + i) + v mod 8,
+// i < per_wg: all of them on v's own XCD.
+__device__ __forceinline__ int solo_unit(int v, int i, int per_wg) {
+    return 8 * (per_wg * (v >> 3) + i) + (v & 7);
+}
+
+// Virtual workgroups that cover n_units positions, per_wg at a time per XCD.
+__host__ __device__ __forceinline__ int solo_groups(int n_units, int per_wg) {
+    return 8 * ((((n_units + 7) >> 3) + per_wg - 1) / per_wg);
+}
+
 __device__ __forceinline__ void floor_divmod(int x, int b, int &q, int &r) {
     q = x / b;
     r = x - q * b;
@@ -735,6 +750,103 @@ __global__ void __launch_bounds__(64 * kFwdMaxWaves) k_forward_region(
     }
 }
 
+// Solo region forward: every group of 16 lanes owns a whole unit (one FPA
+// region, or one chunk of a split region) and walks all of its boxes, so a
+// wavefront advances four units side by side (neighbours in the work-sorted
+// unit list, so of about equal length; a group whose list has ended loads
+// zeros); no cross-group or cross-wave reduction, no workgroup barrier, each
+// group parks its region in its window area and writes it row by row.  For
+// batches of many short regions, where the cooperative kernel's set-up and
+// reductions outweigh a unit's few passes.
+template <int B, int GX>
+__global__ void __launch_bounds__(64 * kSoloWaves) k_forward_region_solo(
+    const int4 *__restrict__ meta, const int4 *__restrict__ items, const int stride, const int n_units,
+    const float *__restrict__ box_wf, const int n_wf, const float *__restrict__ fp, const int fp_floats,
+    const float *__restrict__ g, const float *__restrict__ uaux, float *__restrict__ out,
+    float *__restrict__ partials, const int mode) {
+    using Wn = RWin<B, GX>;
+    constexpr int RX = Wn::RX;
+    extern __shared__ float4 lds4[];
+    float *lds = reinterpret_cast<float *>(lds4);
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nw = blockDim.x >> 6;
+    const int gi = lane >> 4, gl = lane & 15, lx = gl % GX, ly = gl / GX;
+    float *S = lds + wv * Wn::WAVE + gi * Wn::GREG;
+    const __amdgpu_buffer_rsrc_t fr = rsrc(fp, fp_floats);
+    const __amdgpu_buffer_rsrc_t wr = rsrc(box_wf, n_wf);
+
+    const int nv = solo_groups(n_units, nw * kGroups);
+    for (int v = blockIdx.x; v < nv; v += gridDim.x) {
+        const int first = solo_unit(v, wv * kGroups, nw * kGroups);
+        if (first >= n_units) continue;   // so are the wave's other three
+        const int unit = solo_unit(v, wv * kGroups + gi, nw * kGroups);
+        const bool active = unit < n_units;
+        const int u = active ? unit : first;   // a valid unit for the loads; its results are dropped
+        const int4 *list = items + (size_t)u * stride;
+        const int4 m0 = meta[3 * u], m1 = meta[3 * u + 1], m2 = meta[3 * u + 2];
+        const int gamma = m1.z, xi = m1.w;
+        unsigned poff[Wn::NT];
+#pragma unroll
+        for (int t = 0; t < Wn::NT; ++t) {
+            const int k = gl + kGroupLanes * t;
+            poff[t] = k < Wn::NSLOT ? 16u * (unsigned)(k % Wn::SX4) + 4u * (unsigned)m2.z * (unsigned)(k / Wn::SX4)
+                                    : 0u;
+        }
+        const int kend = active ? stride : 0;   // an inactive group reads empty records
+        float acc[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[a][q] = 0.0f;
+
+        int k = 0;
+        int4 rec0 = record(list, k, kend);
+        int4 rec1 = record(list, k + 1, kend);
+        RPend<B, GX> pa;
+        load_region<B, GX>(pa, fr, wr, rec0, gl, poff);
+        while (__builtin_amdgcn_ballot_w64(rec0.w >= 0) != 0) {
+            store_region<B, GX>(S, pa, gl);
+            wave_lds_sync();
+            k += 1;
+            const int4 rec3 = record(list, k + 1, kend);
+            load_region<B, GX>(pa, fr, wr, rec1, gl, poff);
+            correlate<B, Wn::SXP, Wn::REG>(acc, S, lx, ly);
+            wave_lds_sync();
+            rec0 = rec1;
+            rec1 = rec3;
+        }
+        // the group's region, parked row-major in its window area, leaves
+        // row by row (contiguous stores of 16 lanes)
+#pragma unroll
+        for (int kq = 0; kq < 4; ++kq)
+            *reinterpret_cast<float4 *>(S + (4 * ly + kq) * RX + 4 * lx) =
+                make_float4(acc[kq][0], acc[kq][1], acc[kq][2], acc[kq][3]);
+        wave_lds_sync();
+        if (active) {
+            const int r0 = m0.x, c0 = m0.y;
+            const bool whole = m0.z == 1;
+#pragma unroll
+            for (int j = 0; j < kRegion / kGroupLanes; ++j) {
+                const int o = gl + kGroupLanes * j;
+                const float v = S[o];
+                if (!whole) {   // a chunk of a split region: its partial region
+                    partials[(size_t)m0.w * kRegion + o] = v;
+                    continue;
+                }
+                const int r = r0 + o % RX, c = c0 + o / RX;
+                if (r < gamma && c < xi) {
+                    const size_t i = (size_t)r + (size_t)gamma * c;
+                    const float gv = mode != kFwdPlain ? g[(size_t)m2.x + i] : 0.0f;
+                    const float uv = mode == kFwdVjp ? uaux[(size_t)m2.y + i] : 0.0f;
+                    out[(size_t)m2.y + i] = fwd_epilogue(mode, v, gv, uv);
+                }
+            }
+        }
+        wave_lds_sync();   // the next unit's first window overwrites the parked region
+    }
+}
+
 // Sum the partial regions (rx pixels wide) of every split FPA region in
 // chunk order and apply the forward epilogue.  One workgroup (a thread per
 // output) per split region.
@@ -905,12 +1017,12 @@ __global__ void __launch_bounds__(64 * Win<B>::MAXW) k_adjoint(const int4 *__res
 // Solo variants of the tile kernels: every wavefront owns a whole work unit
 // (one FPA tile, or one wavelength's field-stop tile) and walks all its boxes
 // with one window in flight; no cross-wave reduction, no workgroup barrier.
-// A lane writes its 4 x 4 micro-tile itself.  For batches of many small units
+// The wave parks its tile in its own window area and writes it row by row.  For batches of many small units
 // (few boxes each), where splitting a unit's boxes over the waves of a
 // workgroup leaves each wave too few items to hide a window load.
 
-// Per-lane epilogue positions: output (tx, ty) of the 64 x 16 tile for
-// micro-tile element (k, q) of lane (lx, ly): tx = 4 lx + q, ty = 4 ly + k.
+// Micro-tile element (k, q) of lane (lx, ly) is output (tx, ty) = (4 lx + q,
+// 4 ly + k) of the 64 x 16 tile.
 template <int B>
 __global__ void __launch_bounds__(256) k_forward_solo(const int4 *__restrict__ meta,
                                                       const int4 *__restrict__ items, const int stride,
@@ -934,7 +1046,10 @@ __global__ void __launch_bounds__(256) k_forward_solo(const int4 *__restrict__ m
         xs[t] = kk < Wn::E * Wn::SY ? (unsigned)(kk % Wn::ED) + 64u * (unsigned)(kk / Wn::ED) : ~0u;
     }
 
-    for (int unit = blockIdx.x * nw + wv; unit < n_units; unit += gridDim.x * nw) {
+    const int nv = solo_groups(n_units, nw);
+    for (int v = blockIdx.x; v < nv; v += gridDim.x) {
+        const int unit = solo_unit(v, wv, nw);
+        if (unit >= n_units) continue;
         const int4 *list = items + (size_t)unit * stride;
         const int4 m0 = meta[3 * unit], m1 = meta[3 * unit + 1], m2 = meta[3 * unit + 2];
         const Geo geo{m1.x, m1.y, m1.z, m1.w};
@@ -974,25 +1089,30 @@ __global__ void __launch_bounds__(256) k_forward_solo(const int4 *__restrict__ m
             rec1 = rec3;
         }
 
+        // the tile, parked row-major in the wave's window area, leaves row by
+        // row (256-byte stores)
 #pragma unroll
-        for (int kq = 0; kq < 4; ++kq) {
-            const int ty = 4 * ly + kq, c = c0 + ty;
+        for (int kq = 0; kq < 4; ++kq)
+            *reinterpret_cast<float4 *>(S + (4 * ly + kq) * TX + 4 * lx) =
+                make_float4(acc[kq][0], acc[kq][1], acc[kq][2], acc[kq][3]);
+        wave_lds_sync();
+        const int r = r0 + lane;
+#pragma unroll
+        for (int ty = 0; ty < TY; ++ty) {
+            const float v = S[ty * TX + lane];
             if (!whole) {
-                *reinterpret_cast<float4 *>(partials + (size_t)m0.w * (TX * TY) + ty * TX + 4 * lx) =
-                    make_float4(acc[kq][0], acc[kq][1], acc[kq][2], acc[kq][3]);
+                partials[(size_t)m0.w * (TX * TY) + ty * TX + lane] = v;
                 continue;
             }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int r = r0 + 4 * lx + q;
-                if (r < geo.gamma && c < geo.xi) {
-                    const size_t i = (size_t)r + (size_t)geo.gamma * c;
-                    const float gv = mode != kFwdPlain ? g[(size_t)m2.x + i] : 0.0f;
-                    const float uv = mode == kFwdVjp ? uaux[(size_t)m2.y + i] : 0.0f;
-                    out[(size_t)m2.y + i] = fwd_epilogue(mode, acc[kq][q], gv, uv);
-                }
+            const int c = c0 + ty;
+            if (r < geo.gamma && c < geo.xi) {
+                const size_t i = (size_t)r + (size_t)geo.gamma * c;
+                const float gv = mode != kFwdPlain ? g[(size_t)m2.x + i] : 0.0f;
+                const float uv = mode == kFwdVjp ? uaux[(size_t)m2.y + i] : 0.0f;
+                out[(size_t)m2.y + i] = fwd_epilogue(mode, v, gv, uv);
             }
         }
+        wave_lds_sync();   // the next unit's first window overwrites the parked tile
     }
 }
 
@@ -1014,7 +1134,10 @@ __global__ void __launch_bounds__(256) k_adjoint_solo(const int4 *__restrict__ m
     float *S = lds + wv * Wn::WREG;
     const int lx = lane & 15, ly = lane >> 4;
 
-    for (int unit = blockIdx.x * nw + wv; unit < n_units; unit += gridDim.x * nw) {
+    const int nv = solo_groups(n_units, nw);
+    for (int v = blockIdx.x; v < nv; v += gridDim.x) {
+        const int unit = solo_unit(v, wv, nw);
+        if (unit >= n_units) continue;
         const int4 m0 = meta[3 * unit], m1 = meta[3 * unit + 1], m2 = meta[3 * unit + 2];
         const int4 *list = items + (size_t)m0.z * stride;
         const Geo geo{m1.x, m1.y, m1.z, m1.w};
@@ -1065,30 +1188,32 @@ __global__ void __launch_bounds__(256) k_adjoint_solo(const int4 *__restrict__ m
             rec1 = rec3;
         }
 
+#pragma unroll
+        for (int kq = 0; kq < 4; ++kq)
+            *reinterpret_cast<float4 *>(S + (4 * ly + kq) * TX + 4 * lx) =
+                make_float4(acc[kq][0], acc[kq][1], acc[kq][2], acc[kq][3]);
+        wave_lds_sync();
         float fl = 0.0f;   // this lane's share of sum b zeta (kAdjVjpPre)
+        const int x = x0 + lane;
 #pragma unroll
-        for (int kq = 0; kq < 4; ++kq) {
-            const int y = y0 + 4 * ly + kq;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int x = x0 + 4 * lx + q;
-                if (x < geo.a && y < geo.alpha) {
-                    const size_t o = sb + (size_t)x + (size_t)geo.a * y;
-                    const float v = acc[kq][q];
-                    if (mode == kAdjPlain) {
-                        out[o] = v;
-                    } else if (mode == kAdjUpdate) {
-                        const float nf = hs != 0.0f ? (in1[o] * v) / hs : 0.0f;
-                        out[o] = nf;
-                        if (fpad) fpad[(size_t)m2.y + (size_t)(x + hx) + (size_t)m2.z * (size_t)(y + hy)] = nf;
-                    } else if (mode == kAdjVjpPre) {
-                        const float bj = hs != 0.0f ? (in1[o] * in2[o]) / hs : 0.0f;
-                        out[o] = v;
-                        out2[o] = bj;
-                        fl = __builtin_fmaf(bj, v, fl);
-                    } else {
-                        out[o] = (hs != 0.0f ? (in1[o] * in2[o]) / hs : 0.0f) + v;
-                    }
+        for (int ty = 0; ty < TY; ++ty) {
+            const int y = y0 + ty;
+            if (x < geo.a && y < geo.alpha) {
+                const size_t o = sb + (size_t)x + (size_t)geo.a * y;
+                const float v = S[ty * TX + lane];
+                if (mode == kAdjPlain) {
+                    out[o] = v;
+                } else if (mode == kAdjUpdate) {
+                    const float nf = hs != 0.0f ? (in1[o] * v) / hs : 0.0f;
+                    out[o] = nf;
+                    if (fpad) fpad[(size_t)m2.y + (size_t)(x + hx) + (size_t)m2.z * (size_t)(y + hy)] = nf;
+                } else if (mode == kAdjVjpPre) {
+                    const float bj = hs != 0.0f ? (in1[o] * in2[o]) / hs : 0.0f;
+                    out[o] = v;
+                    out2[o] = bj;
+                    fl = __builtin_fmaf(bj, v, fl);
+                } else {
+                    out[o] = (hs != 0.0f ? (in1[o] * in2[o]) / hs : 0.0f) + v;
                 }
             }
         }
@@ -1096,6 +1221,7 @@ __global__ void __launch_bounds__(256) k_adjoint_solo(const int4 *__restrict__ m
             fl = wave_sum(fl);
             if (lane == 0) flux[unit] = fl;
         }
+        wave_lds_sync();   // the next unit's first window overwrites the parked tile
     }
 }
 
@@ -1467,7 +1593,7 @@ int forward_B(const DevWork &w, const float *x, const float *g, const float *u, 
     if (L.waves == 1) {   // solo: four units per workgroup, a wave each
         float *partials = (mode != kFwdPlain && w.n_split > 0) ? (float *)((char *)workspace + w.partials_off) : nullptr;
         const size_t lds = (size_t)kSoloWaves * Win<B>::WREG * sizeof(float);
-        const int groups = (L.n_units + kSoloWaves - 1) / kSoloWaves;
+        const int groups = solo_groups(L.n_units, kSoloWaves);
         hipLaunchKernelGGL(k_forward_solo<B>, dim3(grid_for(groups, lds, kSoloWaves, w.persistent)),
                            dim3(64 * kSoloWaves), lds, st, L.meta, L.items, L.stride, L.n_units, w.box_wf, x, g, u,
                            out, partials, mode);
@@ -1502,7 +1628,7 @@ int forward_region_B(const DevWork &w, const float *g, const float *u, float *ou
     const DevList &L = w.fwd_pad;
     if (L.n_units == 0) return 0;
     const size_t lds = (size_t)L.waves * RWin<B, GX>::WAVE * sizeof(float);
-    if (lds > 65536) {
+    if (!w.region_solo && lds > 65536) {
         static std::once_flag once;
         static hipError_t err = hipSuccess;
         std::call_once(once, []() {
@@ -1514,9 +1640,17 @@ int forward_region_B(const DevWork &w, const float *g, const float *u, float *ou
     }
     const float *fp = (const float *)((const char *)workspace + w.fp_off);
     float *partials = w.n_rsplit > 0 ? (float *)((char *)workspace + w.rpartials_off) : nullptr;
-    hipLaunchKernelGGL((k_forward_region<B, GX>), dim3(grid_for(L.n_units, lds, L.waves, w.persistent)),
-                       dim3(64 * L.waves), lds, st, L.meta, L.items, L.stride, L.n_units, w.box_wf, w.n_wf, fp,
-                       w.fp_floats, g, u, out, partials, mode);
+    if (w.region_solo) {   // a lane group per unit, four units per wave
+        const size_t slds = (size_t)kSoloWaves * RWin<B, GX>::WAVE * sizeof(float);
+        const int groups = solo_groups(L.n_units, kGroups * kSoloWaves);
+        hipLaunchKernelGGL((k_forward_region_solo<B, GX>), dim3(grid_for(groups, slds, kSoloWaves, w.persistent)),
+                           dim3(64 * kSoloWaves), slds, st, L.meta, L.items, L.stride, L.n_units, w.box_wf, w.n_wf,
+                           fp, w.fp_floats, g, u, out, partials, mode);
+    } else {
+        hipLaunchKernelGGL((k_forward_region<B, GX>), dim3(grid_for(L.n_units, lds, L.waves, w.persistent)),
+                           dim3(64 * L.waves), lds, st, L.meta, L.items, L.stride, L.n_units, w.box_wf, w.n_wf, fp,
+                           w.fp_floats, g, u, out, partials, mode);
+    }
     if (partials) {
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return (int)e;
@@ -1544,7 +1678,7 @@ int adjoint_B(const DevWork &w, const float *r, const float *in1, const float *i
     if (L.n_units == 0) return 0;
     if (L.waves == 1) {   // solo: four units per workgroup, a wave each
         const size_t lds = (size_t)kSoloWaves * Win<B>::WREG * sizeof(float);
-        const int groups = (L.n_units + kSoloWaves - 1) / kSoloWaves;
+        const int groups = solo_groups(L.n_units, kSoloWaves);
         hipLaunchKernelGGL(k_adjoint_solo<B>, dim3(grid_for(groups, lds, kSoloWaves, w.persistent)),
                            dim3(64 * kSoloWaves), lds, st, L.meta, L.items, L.stride, L.n_units, w.box_w, w.h, r, in1,
                            in2, out, out2, flux, mode, fpad, w.halo_x, w.halo_y);

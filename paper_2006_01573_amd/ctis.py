@@ -24,6 +24,7 @@ CTIS_PLAN_TILE_PATH = 0x4
 REGION_SHAPES = [None, (8, 32), (16, 16), (32, 8)]
 CTIS_BATCH_PERSISTENT = 0x400
 CTIS_BATCH_TILE_PATH = 0x8000
+CTIS_BATCH_REGION_SOLO = 0x10000
 
 STATUS_NAMES = {0: "CTIS_OK", 1: "CTIS_E_ARG", 2: "CTIS_E_INDEX", 3: "CTIS_E_VALUE",
                 4: "CTIS_E_TOO_LARGE", 5: "CTIS_E_NOMEM", 6: "CTIS_E_HIP",
@@ -584,7 +585,7 @@ class Batch:
     and its image g_all[g_offsets[k] : ...] (see include/ctis.h)."""
 
     def __init__(self, plans, waves_forward: int = 0, waves_adjoint: int = 0, persistent: bool = False,
-                 waves_region: int = 0, tile_path: bool = False):
+                 waves_region: int = 0, tile_path: bool = False, region_solo: bool = False):
         self._L = load_library()
         self._handle = None
         self.plans = list(plans)
@@ -599,7 +600,8 @@ class Batch:
             if not 0 <= int(v) <= hi:
                 raise ValueError(f"{name} must be in 0..{hi}")
         flags = (int(waves_forward) | (int(waves_adjoint) << 5) | (int(waves_region) << 11)
-                 | (CTIS_BATCH_PERSISTENT if persistent else 0) | (CTIS_BATCH_TILE_PATH if tile_path else 0))
+                 | (CTIS_BATCH_PERSISTENT if persistent else 0) | (CTIS_BATCH_TILE_PATH if tile_path else 0)
+                 | (CTIS_BATCH_REGION_SOLO if region_solo else 0))
         h = ctypes.c_void_p()
         _check(self._L, self._L.ctis_batch_create(ctypes.byref(h), ctypes.cast(arr, ctypes.c_void_p),
                                                   len(self.plans), flags), "ctis_batch_create")

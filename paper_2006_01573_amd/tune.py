@@ -5,7 +5,9 @@ Candidate configurations of a batch:
 * forward projection: the region path with each region shape (16 x 16,
   32 x 8 and 8 x 32 FPA pixels per lane group, i.e. two fast-axis widths and
   two slow-axis heights around the square one) and 2, 3 or 4 wavefronts per
-  workgroup, or the tile path (64 x 16 FPA tiles) with 4, 8 or 16;
+  workgroup sharing each region's boxes, or with a lane group per region
+  ("solo": four regions per wavefront), or the tile path (64 x 16 FPA tiles)
+  with 1 (a wavefront per tile), 4, 8 or 16;
 * one workgroup per work unit, or a persistent grid whose workgroups walk
   the unit list;
 * then, with the winning forward setup, the back projection's waves per
@@ -39,7 +41,7 @@ ADJOINT_WAVES = (1, 4, 8)
 @dataclasses.dataclass(frozen=True)
 class Choice:
     """A launch configuration of one batch."""
-    path: str                     # "region" or "tile"
+    path: str                     # "region", "solo" (region, a lane group per region) or "tile"
     shape: tuple | None           # region shape (pixels along gamma, xi); None on the tile path
     waves: int                    # wavefronts per forward workgroup (1: a wave per unit)
     persistent: bool
@@ -59,7 +61,7 @@ class Choice:
             path, sh, w = t[0], t[1], t[2]
             persistent = "persistent" in t
             rest = t[3 + persistent:]
-            if path not in ("region", "tile") or rest[0] != "adjoint" or not w.startswith("W"):
+            if path not in ("region", "solo", "tile") or rest[0] != "adjoint" or not w.startswith("W"):
                 raise ValueError
             shape = None if path == "tile" else tuple(int(x) for x in sh.split("x"))
             aw = 0 if rest[1] == "Wauto" else int(rest[1][1:])
@@ -100,6 +102,8 @@ def _plans(cases, choice: Choice, cache: dict):
 
 
 def _batch(plans, choice: Choice):
+    if choice.path == "solo":
+        return ctis.Batch(plans, region_solo=True, waves_adjoint=choice.adj_waves, persistent=choice.persistent)
     if choice.path == "region":
         return ctis.Batch(plans, waves_region=choice.waves, waves_adjoint=choice.adj_waves,
                           persistent=choice.persistent)
@@ -112,6 +116,7 @@ def _candidates(region_ok: bool, box: int):
     for pe in (False, True):
         if region_ok:
             out += [Choice("region", sh, w, pe, 0) for sh in REGION_SHAPES for w in REGION_WAVES]
+            out += [Choice("solo", sh, 4, pe, 0) for sh in REGION_SHAPES]
         out += [Choice("tile", None, w, pe, 0) for w in TILE_WAVES if w <= (16 if box <= 5 else 8)]
     return out
 
@@ -127,7 +132,7 @@ def tune_frames(torch, cases, images, iters: int, reps: int, table: list, cls: s
     def trial(choice):
         nonlocal best
         plans = _plans(cases, choice, cache)
-        if choice.path == "region" and not all(p.info.em_region_path for p in plans):
+        if choice.path in ("region", "solo") and not all(p.info.em_region_path for p in plans):
             return
         if len({p.info.box for p in plans}) != 1:
             return

@@ -109,21 +109,25 @@ def test_c4_batch_matches_oracle_every_frame(torch, ctis, c4):
     assert worst <= 1e-5
 
 
-@pytest.mark.parametrize("tile_path", [True, False], ids=["tile", "region"])
-def test_c4_solo_kernels_match_oracle_every_frame(torch, ctis, c4, tile_path):
+@pytest.mark.parametrize("path", ["tile", "region", "region_solo"])
+def test_c4_solo_kernels_match_oracle_every_frame(torch, ctis, c4, path):
     """A wavefront per work unit (waves = 1: each wave walks all of its unit's
     boxes and writes its own micro-tiles) in the back projection, and in the
-    forward projection on the tile path; every frame against its oracle,
+    forward projection on the tile path; on the region path with a lane group
+    per region (four regions per wavefront); every frame against its oracle,
     also on a persistent grid."""
     cfgs, cases, plans, images, expected = c4
     K = cfgs[0].iters
+    tile_path = path == "tile"
     for persistent in (False, True):
         kw = {"waves_forward": 1} if tile_path else {}
-        b = ctis.Batch(plans, waves_adjoint=1, persistent=persistent, tile_path=tile_path, **kw)
+        b = ctis.Batch(plans, waves_adjoint=1, persistent=persistent, tile_path=tile_path,
+                       region_solo=path == "region_solo", **kw)
         assert b.info["waves_adjoint"] == 1 and (not tile_path or b.info["waves_forward"] == 1)
+        assert b.info["em_region_path"] == (0 if tile_path else 1)
         f_all = b.em(b.pack_g(images), K).cpu().numpy()
         worst = max(rel_l2(f_all[b.f_offsets[k]:b.f_offsets[k + 1]], expected[k]) for k in range(len(plans)))
-        log(f"c4 solo tile_path={tile_path} persistent={persistent}: worst rel-L2 {worst:.2e}")
+        log(f"c4 solo {path} persistent={persistent}: worst rel-L2 {worst:.2e}")
         assert worst <= EM_TOL
         b.close()
 

@@ -88,6 +88,25 @@ def test_region_em_with_wrapping_images(torch, ctis, oracle_mod, box, geo):
     assert rel_l2(f, o.em(g, 3, f0=f0.astype(np.float64))) <= EM_TOL
 
 
+@pytest.mark.parametrize("box,geo", WRAP[::3], ids=[f"B{b}-g{g.gamma}-xi{g.xi}" for b, g in WRAP[::3]])
+def test_solo_regions_with_wrapping_images(torch, ctis, oracle_mod, box, geo):
+    """A lane group per region (a batch of the frame and a second frame,
+    region_solo), with images that wrap round the FPA: EM against the
+    oracle."""
+    rng = np.random.default_rng(60 * box + geo.xi)
+    kern = W.random_kernels(geo, 4 + box, rng, clustered=box % 2 == 0)
+    log(f"solo regions wrap B={box} geo={geo}")
+    p = ctis.Plan(geo.a, geo.alpha, geo.w, geo.gamma, geo.xi, *kern, box=box)
+    b = ctis.Batch([p, p], region_solo=True)
+    assert b.info["em_region_path"] == 1
+    o, g1 = frame(oracle_mod, geo, kern, rng)
+    _, g2 = frame(oracle_mod, geo, kern, rng)
+    f = b.em(b.pack_g([g1, g2]), 3).cpu().numpy()
+    fo = b.f_offsets
+    assert rel_l2(f[fo[0]:fo[1]], o.em(g1, 3)) <= EM_TOL
+    assert rel_l2(f[fo[1]:fo[2]], o.em(g2, 3)) <= EM_TOL
+
+
 def test_region_and_tile_paths_agree_c2(torch, ctis, oracle_mod):
     """The c2 frame (100 EM iterations) on both paths, each against the oracle."""
     case = W.make_case(2)
@@ -130,6 +149,12 @@ def test_split_regions(torch, ctis, oracle_mod):
         f = torch.ones(p.shape_f, device="cuda")
         p.em(gd, k, f=f, workspace=ws)
         assert rel_l2(f.cpu().numpy(), o.em(g, k)) <= EM_TOL
+    # the same with a lane group per region (split chunks write partial regions)
+    b = ctis.Batch([p], region_solo=True)
+    wsb = b.workspace()
+    for k in (1, 4):
+        f = b.em(gd, k, workspace=wsb).cpu().numpy()
+        assert rel_l2(f, o.em(g, k)) <= EM_TOL
 
 
 def test_region_halves_compose_to_em_iterate(torch, ctis):
