@@ -609,20 +609,39 @@ __device__ __forceinline__ void load_region(RPend<B, GX> &pd, __amdgpu_buffer_rs
     }
 }
 
-// Window into S[0, REG), box values into S[REG, REG + B*B).
+// Window into S[0, REG), box values into S[REG, REG + B*B).  Piece k (row
+// k / SX4, column quad k % SX4) lands at float 4k: the row pitch is 4 SX4.
 template <int B, int GX>
 __device__ __forceinline__ void store_region(float *S, const RPend<B, GX> &pd, int gl) {
     using Wn = RWin<B, GX>;
+    static_assert(Wn::SXP == 4 * Wn::SX4, "pieces are packed row after row");
 #pragma unroll
     for (int t = 0; t < Wn::NT; ++t) {
         const int k = gl + kGroupLanes * t;
-        if (t + 1 < Wn::NT || k < Wn::NSLOT)
-            *reinterpret_cast<float4 *>(S + (k / Wn::SX4) * Wn::SXP + 4 * (k % Wn::SX4)) = pd.v[t];
+        if (t + 1 < Wn::NT || k < Wn::NSLOT) *reinterpret_cast<float4 *>(S + 4 * k) = pd.v[t];
     }
 #pragma unroll
     for (int t = 0; t < Wn::NWT; ++t) {
         const int k = gl + kGroupLanes * t;
         if (k < Wn::BB) S[Wn::REG + k] = pd.wt[t];
+    }
+}
+
+// Byte offset, from the window origin in the padded copy (row pitch P
+// floats), of piece t of group lane gl: piece k = gl + 16 t sits at row
+// k / SX4, column quad k % SX4, found from gl's own row and column by a
+// compile-time step and one carry; 0 for a lane without a piece t.
+template <int B, int GX>
+__device__ __forceinline__ void region_piece_offsets(unsigned int (&poff)[RWin<B, GX>::NT], int gl, int P) {
+    using Wn = RWin<B, GX>;
+    const int row0 = gl / Wn::SX4, col0 = gl - row0 * Wn::SX4;
+    const unsigned prow = 4u * (unsigned)P;
+#pragma unroll
+    for (int t = 0; t < Wn::NT; ++t) {
+        const int dr = (kGroupLanes * t) / Wn::SX4, dc = (kGroupLanes * t) % Wn::SX4;
+        const bool carry = col0 + dc >= Wn::SX4;
+        const int row = row0 + dr + (carry ? 1 : 0), col = col0 + dc - (carry ? Wn::SX4 : 0);
+        poff[t] = gl + kGroupLanes * t < Wn::NSLOT ? 16u * (unsigned)col + prow * (unsigned)row : 0u;
     }
 }
 
@@ -659,12 +678,7 @@ __global__ void __launch_bounds__(64 * kFwdMaxWaves) k_forward_region(
         const bool whole = m0.z == 1;
         // byte offsets of this lane's window pieces from the window origin
         unsigned poff[Wn::NT];
-#pragma unroll
-        for (int t = 0; t < Wn::NT; ++t) {
-            const int k = gl + kGroupLanes * t;
-            poff[t] = k < Wn::NSLOT ? 16u * (unsigned)(k % Wn::SX4) + 4u * (unsigned)m2.z * (unsigned)(k / Wn::SX4)
-                                    : 0u;
-        }
+        region_piece_offsets<B, GX>(poff, gl, m2.z);
         const int step = kGroups * nw;
         int k = kGroups * wv + gi;
         int4 rec0 = record(list, k, stride);
@@ -787,12 +801,7 @@ __global__ void __launch_bounds__(64 * kSoloWaves) k_forward_region_solo(
         const int4 m0 = meta[3 * u], m1 = meta[3 * u + 1], m2 = meta[3 * u + 2];
         const int gamma = m1.z, xi = m1.w;
         unsigned poff[Wn::NT];
-#pragma unroll
-        for (int t = 0; t < Wn::NT; ++t) {
-            const int k = gl + kGroupLanes * t;
-            poff[t] = k < Wn::NSLOT ? 16u * (unsigned)(k % Wn::SX4) + 4u * (unsigned)m2.z * (unsigned)(k / Wn::SX4)
-                                    : 0u;
-        }
+        region_piece_offsets<B, GX>(poff, gl, m2.z);
         const int kend = active ? stride : 0;   // an inactive group reads empty records
         float acc[4][4];
 #pragma unroll
