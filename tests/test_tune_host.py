@@ -1,0 +1,30 @@
+"""CPU checks of the autotuner's launch choices: every candidate's label
+parses back to the same choice (the benchmark's --c4-choice and the recorded
+profiling choice rely on it), and malformed labels are refused."""
+import pytest
+
+from paper_2006_01573_amd import tune
+
+
+def test_every_candidate_label_round_trips():
+    cands = tune._candidates(True, 3) + tune._candidates(False, 7)
+    assert {c.path for c in cands} == {"region", "solo", "tile"}
+    for c in cands:
+        for extra in ({}, {"adj_waves": 1}, {"adj_waves": 8, "box": 4}):
+            ch = tune.Choice(c.path, c.shape, c.waves, c.persistent, extra.get("box", c.box),
+                             extra.get("adj_waves", c.adj_waves))
+            assert tune.Choice.parse(ch.label()) == ch
+
+
+def test_candidates_respect_the_box_side():
+    # more than 8 waves per workgroup only for B <= 5
+    assert max(c.waves for c in tune._candidates(False, 5)) == 16
+    assert max(c.waves for c in tune._candidates(False, 6)) == 8
+    assert not any(c.path != "tile" for c in tune._candidates(False, 3))
+
+
+@pytest.mark.parametrize("label", ["", "tile", "mesh 64x16 W4 adjoint W1 Bauto", "tile 64x16 4 adjoint W1 Bauto",
+                                   "region 16x16 W2 adjoint Wx B3", "solo 16x16 W4 persistent adjoint"])
+def test_malformed_labels_are_refused(label):
+    with pytest.raises(ValueError):
+        tune.Choice.parse(label)
