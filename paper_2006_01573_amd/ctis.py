@@ -582,7 +582,15 @@ class Batch:
     """Frames with their own plans (uneven sizes), reconstructed together: one
     forward+ratio and one adjoint+update launch per EM iteration for all
     frames.  Frame k's datacube is f_all[f_offsets[k] : f_offsets[k] + m_k]
-    and its image g_all[g_offsets[k] : ...] (see include/ctis.h)."""
+    and its image g_all[g_offsets[k] : ...] (see include/ctis.h).
+
+    Launch options (all results agree with the oracle; only speed differs):
+    waves_forward / waves_adjoint: waves per workgroup of the tile kernels
+    (1 = a wavefront per unit walking all its boxes, 0 = built-in);
+    waves_region: waves per workgroup of the region forward; persistent:
+    workgroups walk the unit list; tile_path: EM forward on FPA tiles even
+    where the region path applies; region_solo: region forward with a lane
+    group per region (four regions per wavefront)."""
 
     def __init__(self, plans, waves_forward: int = 0, waves_adjoint: int = 0, persistent: bool = False,
                  waves_region: int = 0, tile_path: bool = False, region_solo: bool = False):
