@@ -684,6 +684,25 @@ __global__ void __launch_bounds__(64 * kFwdMaxWaves) k_forward_region(
         int4 rec0 = record(list, k, stride);
         int4 rec1 = record(list, k + step, stride);
 
+        // operands of the epilogue (output o = tid + nt*j of the region): up
+        // to B = 3 fetched here, off the critical path of short units (the
+        // registers are there); for larger boxes after the item loop, which
+        // keeps the loop at fewer VGPRs
+        constexpr bool kEarly = B <= 3;
+        float gpre[kOut], upre[kOut];
+        auto fetch_operands = [&]() {
+#pragma unroll
+            for (int j = 0; j < kOut; ++j) {
+                const int o = tid + nt * j;
+                const int r = r0 + o % RX, c = c0 + o / RX;
+                const bool in = o < kRegion && mode != kFwdPlain && whole && r < gamma && c < xi;
+                const size_t i = (size_t)r + (size_t)gamma * c;
+                gpre[j] = in ? g[(size_t)m2.x + i] : 0.0f;
+                upre[j] = (in && mode == kFwdVjp) ? uaux[(size_t)m2.y + i] : 0.0f;
+            }
+        };
+        if (kEarly) fetch_operands();
+
         float acc[4][4];
 #pragma unroll
         for (int a = 0; a < 4; ++a)
@@ -711,18 +730,7 @@ __global__ void __launch_bounds__(64 * kFwdMaxWaves) k_forward_region(
             } while (__builtin_amdgcn_readfirstlane(rec0.w) >= 0);
         }
 
-        // operands of the epilogue (output o = tid + nt*j of the region),
-        // fetched while the groups and waves are summed
-        float gpre[kOut], upre[kOut];
-#pragma unroll
-        for (int j = 0; j < kOut; ++j) {
-            const int o = tid + nt * j;
-            const int r = r0 + o % RX, c = c0 + o / RX;
-            const bool in = o < kRegion && mode != kFwdPlain && whole && r < gamma && c < xi;
-            const size_t i = (size_t)r + (size_t)gamma * c;
-            gpre[j] = in ? g[(size_t)m2.x + i] : 0.0f;
-            upre[j] = (in && mode == kFwdVjp) ? uaux[(size_t)m2.y + i] : 0.0f;
-        }
+        if (!kEarly) fetch_operands();   // while the groups and waves are summed
 
         // sum of the four groups (lanes l, l^16, l^32 and l^48 hold the same
         // outputs): every group gets ((g0 + g1) + (g2 + g3))
