@@ -98,6 +98,10 @@ def _load():
         L.oracle_adjoint.restype = ci
         L.oracle_em.argtypes = [P, f64p, f64p, ci, P]
         L.oracle_em.restype = ci
+        L.oracle_smart.argtypes = [P, f64p, f64p, ci]
+        L.oracle_smart.restype = ci
+        L.oracle_sart.argtypes = [P, f64p, f64p, ci, ctypes.c_double]
+        L.oracle_sart.restype = ci
         L.oracle_diagnostics.argtypes = [P, f64p, f64p, f64p,
                                          ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_double)]
@@ -263,6 +267,32 @@ class Oracle:
         _check(st)
         if trace:
             return f, tr[: 2 * iters].reshape(iters, 2)
+        return f
+
+    def _start(self, g, f0):
+        g = np.ascontiguousarray(np.asarray(g, dtype=np.float64).reshape(-1))
+        if g.size != self.n:
+            raise OracleError("g must have n entries")
+        f = (np.ones(self.m) if f0 is None
+             else np.array(np.asarray(f0, dtype=np.float64).reshape(-1), copy=True))
+        if f.size != self.m:
+            raise OracleError("f0 must have m entries")
+        return g, f
+
+    def smart(self, g, iters: int, f0=None) -> np.ndarray:
+        """K iterations of simultaneous MART from f0 (default all ones):
+        f' = f exp(H^T log(g / H f) / h), log terms 0 where g or H f <= 0."""
+        self._need_h()
+        g, f = self._start(g, f0)
+        _check(self._L.oracle_smart(self._h, g, f, int(iters)))
+        return f
+
+    def sart(self, g, iters: int, f0=None, relax: float = 1.0) -> np.ndarray:
+        """K iterations of simultaneous ART kept nonnegative, from f0 (default
+        all ones): f' = max(0, f + relax H^T((g - H f) / H1) / h)."""
+        self._need_h()
+        g, f = self._start(g, f0)
+        _check(self._L.oracle_sart(self._h, g, f, int(iters), float(relax)))
         return f
 
     def em_float32_probe(self, g, iters: int, f0=None) -> np.ndarray:

@@ -285,6 +285,71 @@ int oracle_em(const oracle_t *o, const double *g, double *f, int iters, double *
 }
 
 /*
+ * The simultaneous forms of the other two solvers Sec. 2 names (MART and
+ * ART, cited there to Gordon, Bender and Herman), built from the same two
+ * products.  The cited methods correct one ray (one row of H) at a time;
+ * here every ray's correction is applied at once, each voxel taking the
+ * H-weighted mean of the corrections of the rays through it:
+ *
+ *   SMART (multiplicative):  ghat = H f,
+ *     l_i = log(g_i / ghat_i)          (0 where g_i <= 0 or ghat_i <= 0),
+ *     f'_j = f_j exp((H^T l)_j / h_j)  (0 where h_j == 0);
+ *   SART (additive, kept nonnegative), relaxation lam:  ghat = H f,
+ *     R = H 1 (row sums of H),
+ *     r_i = (g_i - ghat_i) / R_i        (0 where R_i == 0),
+ *     f'_j = max(0, f_j + lam (H^T r)_j / h_j)   (0 where h_j == 0).
+ *
+ * The zero rules follow those of EM (a ray with no data or no projection
+ * carries no information).  g[n], f[m] in double, f updated in place.
+ */
+int oracle_smart(const oracle_t *o, const double *g, double *f, int iters) {
+    if (!o->rowptr || iters < 0) return OR_E_ARG;
+    for (int64_t t = 0; t < o->cptr[o->w]; ++t)
+        if (o->cval[t] < 0.0) return OR_E_NEGATIVE;
+    double *ghat = (double *)malloc(sizeof(double) * (size_t)o->n);
+    double *l = (double *)malloc(sizeof(double) * (size_t)o->n);
+    double *z = (double *)malloc(sizeof(double) * (size_t)o->m);
+    if (!ghat || !l || !z) { free(ghat); free(l); free(z); return OR_E_NOMEM; }
+    for (int k = 0; k < iters; ++k) {
+        oracle_forward(o, f, ghat);
+        for (int64_t i = 0; i < o->n; ++i)
+            l[i] = (g[i] > 0.0 && ghat[i] > 0.0) ? log(g[i] / ghat[i]) : 0.0;
+        oracle_adjoint(o, l, z);
+        for (int64_t j = 0; j < o->m; ++j)
+            f[j] = o->h[j] != 0.0 ? f[j] * exp(z[j] / o->h[j]) : 0.0;
+    }
+    free(ghat); free(l); free(z);
+    return OR_OK;
+}
+
+int oracle_sart(const oracle_t *o, const double *g, double *f, int iters, double lam) {
+    if (!o->rowptr || iters < 0) return OR_E_ARG;
+    double *ghat = (double *)malloc(sizeof(double) * (size_t)o->n);
+    double *R = (double *)malloc(sizeof(double) * (size_t)o->n);
+    double *r = (double *)malloc(sizeof(double) * (size_t)o->n);
+    double *z = (double *)malloc(sizeof(double) * (size_t)o->m);
+    double *one = (double *)malloc(sizeof(double) * (size_t)o->m);
+    if (!ghat || !R || !r || !z || !one) {
+        free(ghat); free(R); free(r); free(z); free(one);
+        return OR_E_NOMEM;
+    }
+    for (int64_t j = 0; j < o->m; ++j) one[j] = 1.0;
+    oracle_forward(o, one, R);                            /* R = H 1 */
+    for (int k = 0; k < iters; ++k) {
+        oracle_forward(o, f, ghat);
+        for (int64_t i = 0; i < o->n; ++i)
+            r[i] = R[i] != 0.0 ? (g[i] - ghat[i]) / R[i] : 0.0;
+        oracle_adjoint(o, r, z);
+        for (int64_t j = 0; j < o->m; ++j) {
+            const double v = o->h[j] != 0.0 ? f[j] + lam * z[j] / o->h[j] : 0.0;
+            f[j] = v > 0.0 ? v : 0.0;
+        }
+    }
+    free(ghat); free(R); free(r); free(z); free(one);
+    return OR_OK;
+}
+
+/*
  * Single rows / columns of H straight from the definition, without the
  * assembled matrix (for sampled checks at sizes where assembly is too big):
  *   row i:    (H f)_i = sum_s sum_t c_s[t] * f_s(E^{-1}((i - t) mod n)),
