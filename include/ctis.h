@@ -137,6 +137,8 @@ typedef struct {
     int64_t tile_forward_madds;
     int64_t region_forward_madds;
     int64_t adjoint_madds;
+    size_t solve_workspace_bytes;  /* workspace of ctis_solve_iterate with SART
+                                      (EM and SMART need workspace_bytes)      */
 } ctis_plan_info;
 
 /*
@@ -233,6 +235,32 @@ ctis_status ctis_adjoint(const ctis_plan *plan, const float *r, float *z_out, vo
  */
 ctis_status ctis_em_iterate(const ctis_plan *plan, const float *g, float *f, int32_t iters,
                             void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Other solvers on the same projections (Sec. 2 names MART and ART beside
+ * EM and cites them to Gordon, Bender and Herman; Sec. 3 notes that the
+ * decomposition does not depend on the solver).  The cited methods correct
+ * one ray (one row of H) at a time; these are their simultaneous forms, in
+ * which every voxel takes the H-weighted mean of the corrections of the rays
+ * through it, one forward and one back projection per iteration:
+ *   CTIS_SOLVER_SMART: f'_j = f_j exp((H^T l)_j / h_j),
+ *       l_i = log(g_i / (H f)_i), 0 where g_i <= 0 or (H f)_i <= 0;
+ *   CTIS_SOLVER_SART:  f'_j = max(0, f_j + relax (H^T r)_j / h_j),
+ *       r_i = (g_i - (H f)_i) / R_i, R = H 1 (0 where R_i == 0),
+ *       relax in (0, 2);
+ *   CTIS_SOLVER_EM:    ctis_em_iterate (relax unused);
+ * f'_j = 0 where h_j == 0.  iters iterations in place on f (DEVICE, the
+ * start vector in, the result out); g DEVICE; workspace DEVICE, 256-byte
+ * aligned, at least info.solve_workspace_bytes for SART and
+ * info.workspace_bytes otherwise; f, g and the workspace must not overlap.
+ * Errors: CTIS_E_ARG (unknown solver, relax outside (0, 2) for SART, NULL,
+ * misaligned or overlapping buffers, iters < 0), CTIS_E_NEGATIVE (EM or
+ * SMART with a negative calibration value; SART accepts any sign),
+ * CTIS_E_WORKSPACE, CTIS_E_HIP.
+ */
+typedef enum { CTIS_SOLVER_EM = 0, CTIS_SOLVER_SMART = 1, CTIS_SOLVER_SART = 2 } ctis_solver;
+ctis_status ctis_solve_iterate(const ctis_plan *plan, int32_t solver, const float *g, float *f, int32_t iters,
+                               float relax, void *workspace, size_t workspace_bytes, void *stream);
 
 /*
  * ctis_em_iterate without a workspace argument, for callers that cannot
@@ -339,6 +367,8 @@ typedef struct {
                                       allows it, CTIS_BATCH_TILE_PATH not set)  */
     int32_t waves_region;
     int64_t region_units;
+    size_t solve_workspace_bytes;  /* workspace of ctis_batch_solve_iterate with
+                                      SART                                     */
 } ctis_batch_info;
 
 /* Create a batch over n_frames >= 1 frames.  flags: CTIS_BATCH_WAVES_FORWARD /
@@ -375,6 +405,13 @@ ctis_status ctis_batch_em_forward_ratio(const ctis_batch *batch, const float *f_
                                         void *workspace, size_t workspace_bytes, void *stream);
 ctis_status ctis_batch_em_adjoint_update(const ctis_batch *batch, void *workspace, size_t workspace_bytes,
                                          const float *f_in, float *f_out, void *stream);
+/* ctis_solve_iterate for every frame of the batch at once (workspace at
+ * least info.solve_workspace_bytes for SART, info.workspace_bytes
+ * otherwise; CTIS_E_NEGATIVE if a plan of the batch has a negative value and
+ * the solver is EM or SMART). */
+ctis_status ctis_batch_solve_iterate(const ctis_batch *batch, int32_t solver, const float *g_all, float *f_all,
+                                     int32_t iters, float relax, void *workspace, size_t workspace_bytes,
+                                     void *stream);
 
 /*
  * Derivatives of EM (reverse mode), for losses of f after K unrolled

@@ -85,6 +85,47 @@ ctis_status em_loop(const DevWork &w, const float *g, float *f, int32_t iters, v
     return CTIS_OK;
 }
 
+// Iterations of SMART or SART in place (EM: em_loop), the operation order of
+// EM's loop with other epilogues: forward with the log-ratio (SMART) or the
+// residual over R = H 1 (SART, R formed first from a vector of ones), then
+// the back projection with the multiplicative or the additive, clamped
+// update, which also keeps the padded copy of f current on the region path.
+ctis_status solve_loop(const DevWork &w, int solver, const float *g, float *f, int32_t iters, float relax,
+                       void *workspace, void *stream) {
+    if (solver == CTIS_SOLVER_EM) return em_loop(w, g, f, iters, workspace, stream);
+    if (iters <= 0) return CTIS_OK;
+    float *u = (float *)workspace;
+    const float *R = nullptr;
+    ctis_status st = CTIS_OK;
+    if (solver == CTIS_SOLVER_SART) {
+        float *Rw = (float *)((char *)workspace + w.solve_r_off);
+        float *ones = (float *)((char *)workspace + w.solve_ones_off);
+        st = launch_status(launch_fill(ones, w.f_floats, 1.0f, stream), "fill launch");
+        if (st != CTIS_OK) return st;
+        st = launch_status(launch_forward(w, ones, nullptr, nullptr, Rw, kFwdPlain, nullptr, stream),
+                           "row-sum projection launch");
+        if (st != CTIS_OK) return st;
+        R = Rw;
+    }
+    const int fmode = solver == CTIS_SOLVER_SMART ? kFwdLogRatio : kFwdResidual;
+    const int amode = solver == CTIS_SOLVER_SMART ? kAdjMulExp : kAdjAddClamp;
+    if (w.pad_ok) {
+        st = launch_status(launch_pad(w, f, workspace, stream), "pad launch");
+        if (st != CTIS_OK) return st;
+    }
+    for (int32_t k = 0; k < iters; ++k) {
+        if (w.pad_ok)
+            st = launch_status(launch_forward_pad(w, g, R, u, fmode, workspace, stream), "forward launch");
+        else
+            st = launch_status(launch_forward(w, f, g, R, u, fmode, workspace, stream), "forward launch");
+        if (st != CTIS_OK) return st;
+        st = launch_status(launch_adjoint(w, u, f, nullptr, f, nullptr, nullptr, amode, stream, workspace, relax),
+                           "adjoint+update launch");
+        if (st != CTIS_OK) return st;
+    }
+    return CTIS_OK;
+}
+
 ctis_status refresh_host_tables(const ctis_plan *p) {
     if (!p->host_stale) return CTIS_OK;
     ctis_status st = check_device(p);
@@ -207,6 +248,7 @@ ctis_status ctis_plan_create(ctis_plan **out, int32_t a, int32_t alpha, int32_t 
         }
         p->workspace_bytes = p->work.workspace_bytes;
         p->vjp_workspace_bytes = p->work.vjp_workspace_bytes;
+        p->solve_workspace_bytes = p->work.solve_workspace_bytes;
     } else {
         // host-only plans still report the workspace an EM call would need
         HostWork hw;
@@ -222,6 +264,7 @@ ctis_status ctis_plan_create(ctis_plan **out, int32_t a, int32_t alpha, int32_t 
         const Layout L = layout_for(hw);
         p->workspace_bytes = L.em_bytes;
         p->vjp_workspace_bytes = L.vjp_bytes;
+        p->solve_workspace_bytes = L.solve_bytes;
         p->work.fwd_em.waves = hw.fwd_em.waves;
         p->work.fwd_pad.waves = hw.fwd_pad.waves;
         p->work.adj.waves = hw.adj.waves;
@@ -281,6 +324,7 @@ ctis_status ctis_plan_get_info(const ctis_plan *p, ctis_plan_info *info) {
     info->waves_adjoint = p->work.adj.waves;
     info->n_entries = p->ht.n_in;
     info->vjp_workspace_bytes = p->vjp_workspace_bytes;
+    info->solve_workspace_bytes = p->solve_workspace_bytes;
     info->dropped = p->ht.dropped ? 1 : 0;
     return CTIS_OK;
 }
@@ -370,6 +414,30 @@ ctis_status ctis_em_iterate(const ctis_plan *p, const float *g, float *f, int32_
     ctis_status st = em_check(p, g, f, iters, workspace, workspace_bytes);
     if (st != CTIS_OK || iters == 0) return st;
     return em_loop(p->work, g, f, iters, workspace, stream);
+}
+
+ctis_status ctis_solve_iterate(const ctis_plan *p, int32_t solver, const float *g, float *f, int32_t iters,
+                               float relax, void *workspace, size_t workspace_bytes, void *stream) {
+    if (!p) return fail(CTIS_E_ARG, "plan is NULL");
+    if (solver != CTIS_SOLVER_EM && solver != CTIS_SOLVER_SMART && solver != CTIS_SOLVER_SART)
+        return fail(CTIS_E_ARG, "unknown solver " + std::to_string(solver));
+    if (solver == CTIS_SOLVER_SART && !(relax > 0.0f && relax < 2.0f))
+        return fail(CTIS_E_ARG, "the SART relaxation must lie in (0, 2)");
+    if (!g || !f) return fail(CTIS_E_ARG, "g or f is NULL");
+    if (!aligned4(g) || !aligned4(f)) return fail(CTIS_E_ARG, "g and f must be 4-byte aligned");
+    if (iters < 0) return fail(CTIS_E_ARG, "iters must be >= 0");
+    if (solver != CTIS_SOLVER_SART && !p->ht.nonneg)
+        return fail(CTIS_E_NEGATIVE, "the plan has a negative calibration value");
+    const size_t need = solver == CTIS_SOLVER_SART ? p->solve_workspace_bytes : p->workspace_bytes;
+    if (!workspace || workspace_bytes < need)
+        return fail(CTIS_E_WORKSPACE, "workspace needs " + std::to_string(need) + " bytes");
+    if (((uintptr_t)workspace & 255u) != 0) return fail(CTIS_E_WORKSPACE, "workspace must be 256-byte aligned");
+    if (overlaps(g, (size_t)p->n * 4, f, (size_t)p->m * 4) || overlaps(workspace, need, f, (size_t)p->m * 4) ||
+        overlaps(workspace, need, g, (size_t)p->n * 4))
+        return fail(CTIS_E_ARG, "g, f and the workspace must not overlap");
+    ctis_status st = check_device(p);
+    if (st != CTIS_OK || iters == 0) return st;
+    return solve_loop(p->work, solver, g, f, iters, relax, workspace, stream);
 }
 
 ctis_status ctis_em_forward_ratio(const ctis_plan *p, const float *f, const float *g, void *workspace,

@@ -134,6 +134,7 @@ ctis_status ctis_batch_get_info(const ctis_batch *b, ctis_batch_info *info) {
     info->waves_region = b->work.fwd_pad.waves;
     info->region_units = b->work.fwd_pad.n_units;
     info->workspace_bytes = b->work.workspace_bytes;
+    info->solve_workspace_bytes = b->work.solve_workspace_bytes;
     info->n_plans = (int32_t)b->plan_entry0.size();
     info->n_entries = b->work.n_entries;
     info->vjp_workspace_bytes = b->work.vjp_workspace_bytes;
@@ -178,6 +179,31 @@ ctis_status ctis_batch_em_iterate(const ctis_batch *b, const float *g_all, float
     ctis_status st = batch_device(b);
     if (st != CTIS_OK) return st;
     return em_loop(b->work, g_all, f_all, iters, workspace, stream);
+}
+
+ctis_status ctis_batch_solve_iterate(const ctis_batch *b, int32_t solver, const float *g_all, float *f_all,
+                                     int32_t iters, float relax, void *workspace, size_t workspace_bytes,
+                                     void *stream) {
+    if (!b) return fail(CTIS_E_ARG, "batch is NULL");
+    if (solver != CTIS_SOLVER_EM && solver != CTIS_SOLVER_SMART && solver != CTIS_SOLVER_SART)
+        return fail(CTIS_E_ARG, "unknown solver " + std::to_string(solver));
+    if (solver == CTIS_SOLVER_SART && !(relax > 0.0f && relax < 2.0f))
+        return fail(CTIS_E_ARG, "the SART relaxation must lie in (0, 2)");
+    if (!g_all || !f_all || !aligned4(g_all) || !aligned4(f_all))
+        return fail(CTIS_E_ARG, "g_all and f_all must be non-NULL and 4-byte aligned");
+    if (iters < 0) return fail(CTIS_E_ARG, "iters must be >= 0");
+    if (solver != CTIS_SOLVER_SART && !b->nonneg)
+        return fail(CTIS_E_NEGATIVE, "a plan of the batch has a negative calibration value");
+    const size_t need = solver == CTIS_SOLVER_SART ? b->work.solve_workspace_bytes : b->work.workspace_bytes;
+    if (!workspace || workspace_bytes < need)
+        return fail(CTIS_E_WORKSPACE, "workspace needs " + std::to_string(need) + " bytes");
+    if (((uintptr_t)workspace & 255u) != 0) return fail(CTIS_E_WORKSPACE, "workspace must be 256-byte aligned");
+    const size_t fb = (size_t)b->f_floats * 4, gb = (size_t)b->g_floats * 4;
+    if (overlaps(g_all, gb, f_all, fb) || overlaps(workspace, need, f_all, fb) || overlaps(workspace, need, g_all, gb))
+        return fail(CTIS_E_ARG, "g_all, f_all and the workspace must not overlap");
+    ctis_status st = batch_device(b);
+    if (st != CTIS_OK || iters == 0) return st;
+    return solve_loop(b->work, solver, g_all, f_all, iters, relax, workspace, stream);
 }
 
 ctis_status ctis_batch_em_forward_ratio(const ctis_batch *b, const float *f_all, const float *g_all, void *workspace,

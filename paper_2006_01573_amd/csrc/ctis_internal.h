@@ -125,6 +125,9 @@ struct DevWork {
     // VJP workspace: the EM workspace (u, partial tiles) followed by
     // e, zeta, b, per-unit flux partials and per-(unit, box) value partials
     size_t e_off = 0, zeta_off = 0, b_off = 0, hpart_off = 0, vg_off = 0, vjp_workspace_bytes = 0;
+    // SART workspace: the EM workspace, then R = H 1 (like g) and a vector of
+    // ones (like f), over the derivative parts (never used together)
+    size_t solve_r_off = 0, solve_ones_off = 0, solve_workspace_bytes = 0;
     void *mem = nullptr;         // device allocation holding the tables
 };
 
@@ -144,6 +147,7 @@ struct HostWork {
     int32_t pad_rows = 0;
     std::vector<float> box_w, box_wf, h;
     int64_t u_floats = 0;        // u region of the EM workspace
+    int64_t g_floats = 0;        // extent of the g buffer
     int64_t f_floats = 0;        // extent of the f buffer
     // value tables (layout as in DevWork)
     std::vector<int32_t> entry_slot, box_lam, lam_box0, lam_units_ptr, lam_units, slot_entries_ptr, slot_entries;
@@ -157,7 +161,7 @@ struct HostWork {
 // Workspace layout of a work description (byte offsets, 256-byte aligned).
 struct Layout {
     size_t partials_off, rpartials_off, fp_off, diag_off, em_bytes, e_off, zeta_off, b_off, hpart_off, vg_off,
-        vjp_bytes;
+        vjp_bytes, solve_r_off, solve_ones_off, solve_bytes;
 };
 
 // Forward work list over a grid of FPA cells (tf x ts pixels): for every
@@ -201,7 +205,7 @@ struct ctis_plan {
     ctis::HostTables ht;
     int32_t device = -1;
     ctis::DevWork work;          // the plan as a batch of one frame
-    size_t workspace_bytes = 0, vjp_workspace_bytes = 0;
+    size_t workspace_bytes = 0, vjp_workspace_bytes = 0, solve_workspace_bytes = 0;
     // ctis_plan_set_values rewrites the device copies of the box values and
     // column sums; the host copies in `ht` are re-read from the device by
     // refresh_host_tables before the next host-side reader uses them
@@ -251,6 +255,10 @@ int static_scratch(void **ptr);
 // stream-ordered EM drivers shared by plans and batches (api.cpp)
 ctis_status em_forward_half(const DevWork &w, const float *f, const float *g, void *workspace, void *stream);
 ctis_status em_loop(const DevWork &w, const float *g, float *f, int32_t iters, void *workspace, void *stream);
+// iters iterations of a solver (CTIS_SOLVER_*) in place; SART needs the
+// solve workspace
+ctis_status solve_loop(const DevWork &w, int solver, const float *g, float *f, int32_t iters, float relax,
+                       void *workspace, void *stream);
 
 // kernel launchers (kernels.hip); return hipError_t as int
 int max_waves(int box);         // tile kernels: waves per workgroup
@@ -258,18 +266,27 @@ int min_waves();
 
 // Epilogues of the forward projection v = (H x)_i:
 enum FwdMode : int {
-    kFwdPlain = 0,   // out = v                                  (every FPA tile)
-    kFwdRatio = 1,   // out = g / v, 0 where v <= 0              (EM: u)
-    kFwdVjp = 2,     // out = -v u^2 / g, 0 where u == 0          (EM derivative: e)
+    kFwdPlain = 0,     // out = v                                  (every FPA tile)
+    kFwdRatio = 1,     // out = g / v, 0 where v <= 0              (EM: u)
+    kFwdVjp = 2,       // out = -v u^2 / g, 0 where u == 0          (EM derivative: e; aux = u)
+    kFwdLogRatio = 3,  // out = log(g / v), 0 where g <= 0 or v <= 0 (SMART)
+    kFwdResidual = 4,  // out = (g - v) / R, 0 where R == 0         (SART; aux = R = H 1,
+                       //                                            laid out like g)
 };
 // Epilogues of the back projection v = (H^T r)_j:
 enum AdjMode : int {
-    kAdjPlain = 0,   // out = v
-    kAdjUpdate = 1,  // out = in1 v / h, 0 where h == 0          (EM update)
-    kAdjVjpPre = 2,  // out = v (zeta), out2 = in1 in2 / h (b = y f / h),
-                     // flux[unit] = sum over the unit's voxels of b v
-    kAdjVjpGrad = 3, // out = in1 in2 / h + v (y zeta / h + H^T e)
+    kAdjPlain = 0,     // out = v
+    kAdjUpdate = 1,    // out = in1 v / h, 0 where h == 0          (EM update)
+    kAdjVjpPre = 2,    // out = v (zeta), out2 = in1 in2 / h (b = y f / h),
+                       // flux[unit] = sum over the unit's voxels of b v
+    kAdjVjpGrad = 3,   // out = in1 in2 / h + v (y zeta / h + H^T e)
+    kAdjMulExp = 4,    // out = in1 exp(v / h), 0 where h == 0     (SMART update)
+    kAdjAddClamp = 5,  // out = max(0, in1 + relax v / h), 0 where h == 0 (SART update)
 };
+// the modes that replace f (and its padded copy) by an update
+inline constexpr bool adj_updates(int mode) {
+    return mode == kAdjUpdate || mode == kAdjMulExp || mode == kAdjAddClamp;
+}
 int launch_forward(const DevWork &w, const float *x, const float *g, const float *u, float *out, int mode,
                    void *workspace, void *stream);
 // Region path (w.pad_ok): launch_pad writes the zero-bordered copy of x into
@@ -277,10 +294,12 @@ int launch_forward(const DevWork &w, const float *x, const float *g, const float
 int launch_pad(const DevWork &w, const float *x, void *workspace, void *stream);
 int launch_forward_pad(const DevWork &w, const float *g, const float *u, float *out, int mode, void *workspace,
                        void *stream);
-// `fpad`: with kAdjUpdate, also write the updated f into the padded copy at
-// that workspace (nullptr: not)
+// `fpad`: with an update mode, also write the updated f into the padded copy
+// at that workspace (nullptr: not); `relax`: kAdjAddClamp's relaxation
 int launch_adjoint(const DevWork &w, const float *r, const float *in1, const float *in2, float *out, float *out2,
-                   float *flux, int mode, void *stream, void *fpad = nullptr);
+                   float *flux, int mode, void *stream, void *fpad = nullptr, float relax = 1.0f);
+// x[0, n) = v
+int launch_fill(float *x, int64_t n, float v, void *stream);
 // per-(adjoint unit, box) partial derivatives of the calibration values, then
 // their sums per entry into dv (accumulated if `accumulate`)
 int launch_value_grad(const DevWork &w, const float *u, const float *e, const float *b, const float *f,

@@ -401,10 +401,32 @@ __device__ __forceinline__ float row_sum(const float *lds, int nw, int row, int 
 // Forward epilogue: v = (H x)_i, gv = g_i, uv = u_i.
 //   ratio: u = g / v (0 where v <= 0);
 //   vjp:   e = -v u / ghat = -v u (u / g), 0 where u == 0 (u != 0 implies g != 0)
+//   logratio: log(g / v) (0 where g <= 0 or v <= 0);
+//   residual: (g - v) / R, uv = R (0 where R == 0)
 __device__ __forceinline__ float fwd_epilogue(int mode, float v, float gv, float uv) {
     if (mode == kFwdRatio) return v > 0.0f ? gv / v : 0.0f;
     if (mode == kFwdVjp) return uv != 0.0f ? -(v * uv) * (uv / gv) : 0.0f;
+    if (mode == kFwdLogRatio) return (gv > 0.0f && v > 0.0f) ? logf(gv / v) : 0.0f;
+    if (mode == kFwdResidual) return uv != 0.0f ? (gv - v) / uv : 0.0f;
     return v;
+}
+
+// Whether a forward epilogue reads the auxiliary vector, and at which frame
+// offset: u (kFwdVjp) is laid out like the output, R (kFwdResidual) like g.
+__device__ __forceinline__ bool fwd_aux(int mode) { return mode == kFwdVjp || mode == kFwdResidual; }
+__device__ __forceinline__ size_t fwd_aux_off(int mode, int g_off, int out_off) {
+    return (size_t)(unsigned)(mode == kFwdResidual ? g_off : out_off);
+}
+
+// Update epilogues of the back projection v = (H^T r)_j of voxel j with the
+// column sum hs and the current value fj:
+//   EM:    fj v / hs;   SMART: fj exp(v / hs);   SART: max(0, fj + relax v / hs);
+// 0 where hs == 0 (a voxel that no pixel sees).
+__device__ __forceinline__ float adj_update(int mode, float fj, float v, float hs, float relax) {
+    if (hs == 0.0f) return 0.0f;
+    if (mode == kAdjMulExp) return fj * expf(v / hs);
+    if (mode == kAdjAddClamp) return fmaxf(0.0f, fj + relax * (v / hs));
+    return (fj * v) / hs;
 }
 
 // Forward projection.  Workgroups walk the unit list (grid stride); a unit is
@@ -446,7 +468,7 @@ __global__ void __launch_bounds__(64 * Win<B>::MAXW) k_forward(const int4 *__res
             const bool in = mode != kFwdPlain && whole && r < geo.gamma && c < geo.xi;
             const size_t i = (size_t)r + (size_t)geo.gamma * c;
             gpre[j] = in ? g[(size_t)m2.x + i] : 0.0f;
-            upre[j] = (in && mode == kFwdVjp) ? uaux[(size_t)m2.y + i] : 0.0f;
+            upre[j] = (in && fwd_aux(mode)) ? uaux[fwd_aux_off(mode, m2.x, m2.y) + i] : 0.0f;
         }
 
         float acc[4][4];
@@ -521,7 +543,7 @@ __global__ void __launch_bounds__(256) k_finish_split(const int4 *__restrict__ s
         if (r >= s1.x || c >= s1.y) continue;
         const size_t i = (size_t)r + (size_t)s1.x * c;
         const float gv = mode != kFwdPlain ? g[(size_t)s1.z + i] : 0.0f;
-        const float uv = mode == kFwdVjp ? uaux[(size_t)s1.w + i] : 0.0f;
+        const float uv = fwd_aux(mode) ? uaux[fwd_aux_off(mode, s1.z, s1.w) + i] : 0.0f;
         float v = 0.0f;
         for (int ch = 0; ch < s0.z; ++ch) v += partials[((size_t)s0.w + ch) * (TX * TY) + row * TX + lane];
         out[(size_t)s1.w + i] = fwd_epilogue(mode, v, gv, uv);
@@ -698,7 +720,7 @@ __global__ void __launch_bounds__(64 * kFwdMaxWaves) k_forward_region(
                 const bool in = o < kRegion && mode != kFwdPlain && whole && r < gamma && c < xi;
                 const size_t i = (size_t)r + (size_t)gamma * c;
                 gpre[j] = in ? g[(size_t)m2.x + i] : 0.0f;
-                upre[j] = (in && mode == kFwdVjp) ? uaux[(size_t)m2.y + i] : 0.0f;
+                upre[j] = (in && fwd_aux(mode)) ? uaux[fwd_aux_off(mode, m2.x, m2.y) + i] : 0.0f;
             }
         };
         if (kEarly) fetch_operands();
@@ -855,7 +877,7 @@ __global__ void __launch_bounds__(64 * kSoloWaves) k_forward_region_solo(
                 if (r < gamma && c < xi) {
                     const size_t i = (size_t)r + (size_t)gamma * c;
                     const float gv = mode != kFwdPlain ? g[(size_t)m2.x + i] : 0.0f;
-                    const float uv = mode == kFwdVjp ? uaux[(size_t)m2.y + i] : 0.0f;
+                    const float uv = fwd_aux(mode) ? uaux[fwd_aux_off(mode, m2.x, m2.y) + i] : 0.0f;
                     out[(size_t)m2.y + i] = fwd_epilogue(mode, v, gv, uv);
                 }
             }
@@ -878,10 +900,16 @@ __global__ void __launch_bounds__(kRegion) k_finish_regions(const int4 *__restri
     if (r >= s1.x || c >= s1.y) return;
     const size_t i = (size_t)r + (size_t)s1.x * c;
     const float gv = mode != kFwdPlain ? g[(size_t)s1.z + i] : 0.0f;
-    const float uv = mode == kFwdVjp ? uaux[(size_t)s1.w + i] : 0.0f;
+    const float uv = fwd_aux(mode) ? uaux[fwd_aux_off(mode, s1.z, s1.w) + i] : 0.0f;
     float v = 0.0f;
     for (int ch = 0; ch < s0.z; ++ch) v += partials[((size_t)s0.w + ch) * kRegion + o];
     out[(size_t)s1.w + i] = fwd_epilogue(mode, v, gv, uv);
+}
+
+// x[0, n) = v (grid-strided); a kernel rather than a memset so that a
+// captured graph replays it like any other node.
+__global__ void __launch_bounds__(256) k_fill(float *__restrict__ x, const int64_t n, const float v) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) x[i] = v;
 }
 
 // Zero-bordered copy of x for the region forward.  Block b = (x offset,
@@ -915,7 +943,7 @@ __global__ void __launch_bounds__(64 * Win<B>::MAXW) k_adjoint(const int4 *__res
                                                                const float *__restrict__ in2, float *out,
                                                                float *__restrict__ out2, float *__restrict__ flux,
                                                                const int mode, float *__restrict__ fpad,
-                                                               const int hx, const int hy) {
+                                                               const int hx, const int hy, const float relax) {
     using Wn = Win<B>;
     extern __shared__ float4 lds4[];
     float *lds = reinterpret_cast<float *>(lds4);
@@ -944,7 +972,7 @@ __global__ void __launch_bounds__(64 * Win<B>::MAXW) k_adjoint(const int4 *__res
             const bool in = x < geo.a && y < geo.alpha;
             const size_t o = sb + (size_t)x + (size_t)geo.a * y;
             p1[j] = (in && mode != kAdjPlain) ? in1[o] : 0.0f;
-            p2[j] = (in && mode >= kAdjVjpPre) ? in2[o] : 0.0f;
+            p2[j] = (in && (mode == kAdjVjpPre || mode == kAdjVjpGrad)) ? in2[o] : 0.0f;
         }
         const float hs = hsum[m0.z];
 
@@ -998,8 +1026,8 @@ __global__ void __launch_bounds__(64 * Win<B>::MAXW) k_adjoint(const int4 *__res
                 const size_t o = sb + (size_t)x + (size_t)geo.a * y;
                 if (mode == kAdjPlain) {
                     out[o] = v;
-                } else if (mode == kAdjUpdate) {
-                    const float nf = hs != 0.0f ? (p1[j] * v) / hs : 0.0f;
+                } else if (adj_updates(mode)) {
+                    const float nf = adj_update(mode, p1[j], v, hs, relax);
                     out[o] = nf;
                     // the padded copy of f the region forward reads (block offset
                     // m2.y, row pitch m2.z)
@@ -1125,7 +1153,7 @@ __global__ void __launch_bounds__(256) k_forward_solo(const int4 *__restrict__ m
             if (r < geo.gamma && c < geo.xi) {
                 const size_t i = (size_t)r + (size_t)geo.gamma * c;
                 const float gv = mode != kFwdPlain ? g[(size_t)m2.x + i] : 0.0f;
-                const float uv = mode == kFwdVjp ? uaux[(size_t)m2.y + i] : 0.0f;
+                const float uv = fwd_aux(mode) ? uaux[fwd_aux_off(mode, m2.x, m2.y) + i] : 0.0f;
                 out[(size_t)m2.y + i] = fwd_epilogue(mode, v, gv, uv);
             }
         }
@@ -1141,7 +1169,7 @@ __global__ void __launch_bounds__(256) k_adjoint_solo(const int4 *__restrict__ m
                                                       const float *in1, const float *__restrict__ in2, float *out,
                                                       float *__restrict__ out2, float *__restrict__ flux,
                                                       const int mode, float *__restrict__ fpad, const int hx,
-                                                      const int hy) {
+                                                      const int hy, const float relax) {
     using Wn = Win<B>;
     extern __shared__ float4 lds4[];
     float *lds = reinterpret_cast<float *>(lds4);
@@ -1220,8 +1248,8 @@ __global__ void __launch_bounds__(256) k_adjoint_solo(const int4 *__restrict__ m
                 const float v = S[ty * TX + lane];
                 if (mode == kAdjPlain) {
                     out[o] = v;
-                } else if (mode == kAdjUpdate) {
-                    const float nf = hs != 0.0f ? (in1[o] * v) / hs : 0.0f;
+                } else if (adj_updates(mode)) {
+                    const float nf = adj_update(mode, in1[o], v, hs, relax);
                     out[o] = nf;
                     if (fpad) fpad[(size_t)m2.y + (size_t)(x + hx) + (size_t)m2.z * (size_t)(y + hy)] = nf;
                 } else if (mode == kAdjVjpPre) {
@@ -1690,7 +1718,7 @@ int forward_region_gx(const DevWork &w, const float *g, const float *u, float *o
 
 template <int B>
 int adjoint_B(const DevWork &w, const float *r, const float *in1, const float *in2, float *out, float *out2,
-              float *flux, int mode, hipStream_t st, float *fpad) {
+              float *flux, int mode, hipStream_t st, float *fpad, float relax) {
     const DevList &L = w.adj;
     if (L.n_units == 0) return 0;
     if (L.waves == 1) {   // solo: four units per workgroup, a wave each
@@ -1698,7 +1726,7 @@ int adjoint_B(const DevWork &w, const float *r, const float *in1, const float *i
         const int groups = solo_groups(L.n_units, kSoloWaves);
         hipLaunchKernelGGL(k_adjoint_solo<B>, dim3(grid_for(groups, lds, kSoloWaves, w.persistent)),
                            dim3(64 * kSoloWaves), lds, st, L.meta, L.items, L.stride, L.n_units, w.box_w, w.h, r, in1,
-                           in2, out, out2, flux, mode, fpad, w.halo_x, w.halo_y);
+                           in2, out, out2, flux, mode, fpad, w.halo_x, w.halo_y, relax);
         return (int)hipGetLastError();
     }
     const size_t lds = (size_t)L.waves * Win<B>::WREG * sizeof(float);
@@ -1708,7 +1736,7 @@ int adjoint_B(const DevWork &w, const float *r, const float *in1, const float *i
     }
     hipLaunchKernelGGL(k_adjoint<B>, dim3(grid_for(L.n_units, lds, L.waves, w.persistent)), dim3(64 * L.waves), lds, st,
                        L.meta, L.items, L.stride, L.n_units, w.box_w, w.h, r, in1, in2, out, out2, flux, mode, fpad,
-                       w.halo_x, w.halo_y);
+                       w.halo_x, w.halo_y, relax);
     return (int)hipGetLastError();
 }
 
@@ -1746,20 +1774,27 @@ int launch_forward(const DevWork &w, const float *x, const float *g, const float
 }
 
 int launch_adjoint(const DevWork &w, const float *r, const float *in1, const float *in2, float *out, float *out2,
-                   float *flux, int mode, void *stream, void *fpad_ws) {
+                   float *flux, int mode, void *stream, void *fpad_ws, float relax) {
     hipStream_t st = (hipStream_t)stream;
-    float *fpad = (fpad_ws && mode == kAdjUpdate && w.pad_ok) ? (float *)((char *)fpad_ws + w.fp_off) : nullptr;
+    float *fpad = (fpad_ws && adj_updates(mode) && w.pad_ok) ? (float *)((char *)fpad_ws + w.fp_off) : nullptr;
     switch (w.B) {
-        case 1: return adjoint_B<1>(w, r, in1, in2, out, out2, flux, mode, st, fpad);
-        case 2: return adjoint_B<2>(w, r, in1, in2, out, out2, flux, mode, st, fpad);
-        case 3: return adjoint_B<3>(w, r, in1, in2, out, out2, flux, mode, st, fpad);
-        case 4: return adjoint_B<4>(w, r, in1, in2, out, out2, flux, mode, st, fpad);
-        case 5: return adjoint_B<5>(w, r, in1, in2, out, out2, flux, mode, st, fpad);
-        case 6: return adjoint_B<6>(w, r, in1, in2, out, out2, flux, mode, st, fpad);
-        case 7: return adjoint_B<7>(w, r, in1, in2, out, out2, flux, mode, st, fpad);
-        case 8: return adjoint_B<8>(w, r, in1, in2, out, out2, flux, mode, st, fpad);
+        case 1: return adjoint_B<1>(w, r, in1, in2, out, out2, flux, mode, st, fpad, relax);
+        case 2: return adjoint_B<2>(w, r, in1, in2, out, out2, flux, mode, st, fpad, relax);
+        case 3: return adjoint_B<3>(w, r, in1, in2, out, out2, flux, mode, st, fpad, relax);
+        case 4: return adjoint_B<4>(w, r, in1, in2, out, out2, flux, mode, st, fpad, relax);
+        case 5: return adjoint_B<5>(w, r, in1, in2, out, out2, flux, mode, st, fpad, relax);
+        case 6: return adjoint_B<6>(w, r, in1, in2, out, out2, flux, mode, st, fpad, relax);
+        case 7: return adjoint_B<7>(w, r, in1, in2, out, out2, flux, mode, st, fpad, relax);
+        case 8: return adjoint_B<8>(w, r, in1, in2, out, out2, flux, mode, st, fpad, relax);
     }
     return (int)hipErrorInvalidValue;
+}
+
+int launch_fill(float *x, int64_t n, float v, void *stream) {
+    if (n <= 0) return 0;
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 65535);
+    hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(256), 0, (hipStream_t)stream, x, n, v);
+    return (int)hipGetLastError();
 }
 
 int launch_pad(const DevWork &w, const float *x, void *workspace, void *stream) {

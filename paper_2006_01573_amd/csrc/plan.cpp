@@ -516,6 +516,7 @@ ctis_status build_work(const std::vector<FrameRef> &frames, bool with_full, Host
         }
         max_boxes = std::max(max_boxes, T.max_boxes);
         hw.u_floats = std::max<int64_t>(hw.u_floats, frames[k].u_base + pl->n);
+        hw.g_floats = std::max<int64_t>(hw.g_floats, frames[k].g_base + pl->n);
         hw.f_floats = std::max<int64_t>(hw.f_floats, frames[k].f_base + pl->m);
     }
     std::vector<int32_t> fbox(frames.size()), flam(frames.size());
@@ -793,6 +794,9 @@ Layout layout_for(const HostWork &hw) {
     L.hpart_off = L.b_off + up256((size_t)hw.f_floats * sizeof(float));
     L.vg_off = L.hpart_off + up256((size_t)hw.adj.n_units * sizeof(float));
     L.vjp_bytes = L.vg_off + up256((size_t)hw.adj.n_units * hw.adj.stride * hw.B * hw.B * sizeof(float));
+    L.solve_r_off = L.e_off;
+    L.solve_ones_off = L.solve_r_off + up256((size_t)hw.g_floats * sizeof(float));
+    L.solve_bytes = L.solve_ones_off + up256((size_t)hw.f_floats * sizeof(float));
     return L;
 }
 
@@ -900,6 +904,9 @@ ctis_status upload_work(const HostWork &hw, DevWork &dw) {
     dw.hpart_off = L.hpart_off;
     dw.vg_off = L.vg_off;
     dw.vjp_workspace_bytes = L.vjp_bytes;
+    dw.solve_r_off = L.solve_r_off;
+    dw.solve_ones_off = L.solve_ones_off;
+    dw.solve_workspace_bytes = L.solve_bytes;
     dw.mem = mem;
     return CTIS_OK;
 }

@@ -25,6 +25,7 @@ REGION_SHAPES = [None, (8, 32), (16, 16), (32, 8)]
 CTIS_BATCH_PERSISTENT = 0x400
 CTIS_BATCH_TILE_PATH = 0x8000
 CTIS_BATCH_REGION_SOLO = 0x10000
+SOLVERS = {"em": 0, "smart": 1, "sart": 2}   # ctis_solver
 
 STATUS_NAMES = {0: "CTIS_OK", 1: "CTIS_E_ARG", 2: "CTIS_E_INDEX", 3: "CTIS_E_VALUE",
                 4: "CTIS_E_TOO_LARGE", 5: "CTIS_E_NOMEM", 6: "CTIS_E_HIP",
@@ -37,7 +38,8 @@ EXPORTED = ["ctis_plan_create", "ctis_plan_destroy", "ctis_plan_get_info",
             "ctis_forward", "ctis_adjoint", "ctis_em_iterate", "ctis_em_forward_ratio", "ctis_em_adjoint_update", "ctis_status_str",
             "ctis_last_error", "ctis_version", "ctis_batch_create", "ctis_batch_destroy",
             "ctis_batch_get_info", "ctis_batch_forward", "ctis_batch_adjoint", "ctis_batch_em_iterate",
-            "ctis_batch_em_forward_ratio", "ctis_batch_em_adjoint_update", "ctis_em_vjp", "ctis_plan_set_values", "ctis_batch_em_vjp", "ctis_batch_set_values",
+            "ctis_batch_em_forward_ratio", "ctis_batch_em_adjoint_update", "ctis_solve_iterate",
+            "ctis_batch_solve_iterate", "ctis_em_vjp", "ctis_plan_set_values", "ctis_batch_em_vjp", "ctis_batch_set_values",
             "ctis_batch_plan_entries", "ctis_fourier_create", "ctis_fourier_destroy", "ctis_fourier_get_info",
             "ctis_fourier_forward", "ctis_fourier_adjoint", "ctis_fourier_em_iterate"]
 
@@ -71,7 +73,7 @@ class _Info(ctypes.Structure):
                 ("n_region_items", ctypes.c_int64), ("em_region_path", ctypes.c_int32),
                 ("waves_region", ctypes.c_int32), ("method_madds", ctypes.c_int64),
                 ("tile_forward_madds", ctypes.c_int64), ("region_forward_madds", ctypes.c_int64),
-                ("adjoint_madds", ctypes.c_int64)]
+                ("adjoint_madds", ctypes.c_int64), ("solve_workspace_bytes", ctypes.c_size_t)]
 
 
 class _BatchInfo(ctypes.Structure):
@@ -82,7 +84,7 @@ class _BatchInfo(ctypes.Structure):
                 ("workspace_bytes", ctypes.c_size_t), ("n_plans", ctypes.c_int32),
                 ("n_entries", ctypes.c_int64), ("vjp_workspace_bytes", ctypes.c_size_t),
                 ("em_region_path", ctypes.c_int32), ("waves_region", ctypes.c_int32),
-                ("region_units", ctypes.c_int64)]
+                ("region_units", ctypes.c_int64), ("solve_workspace_bytes", ctypes.c_size_t)]
 
 
 class _FourierInfo(ctypes.Structure):
@@ -129,6 +131,7 @@ class PlanInfo:
     tile_forward_madds: int
     region_forward_madds: int
     adjoint_madds: int
+    solve_workspace_bytes: int
 
 
 _lock = threading.Lock()
@@ -192,6 +195,10 @@ def load_library(path: str | None = None):
         L.ctis_batch_em_forward_ratio.restype = st
         L.ctis_batch_em_adjoint_update.argtypes = [vp, vp, sz, vp, vp, vp]
         L.ctis_batch_em_adjoint_update.restype = st
+        L.ctis_solve_iterate.argtypes = [vp, i32, vp, vp, i32, ctypes.c_float, vp, sz, vp]
+        L.ctis_solve_iterate.restype = st
+        L.ctis_batch_solve_iterate.argtypes = [vp, i32, vp, vp, i32, ctypes.c_float, vp, sz, vp]
+        L.ctis_batch_solve_iterate.restype = st
         L.ctis_em_vjp.argtypes = [vp, vp, vp, vp, vp, vp, i32, vp, sz, vp]
         L.ctis_em_vjp.restype = st
         L.ctis_plan_set_values.argtypes = [vp, vp, vp]
@@ -496,6 +503,35 @@ class Plan:
         _check(self._L, st, "ctis_em_iterate")
         return f
 
+    def solve_workspace(self):
+        """A workspace large enough for every solver (SART's included)."""
+        torch = _torch()
+        return torch.empty(max(self.sizes.solve_workspace_bytes // 4, 64), dtype=torch.float32, device=self.device)
+
+    def solve(self, g, iters: int, solver: str = "smart", relax: float = 1.0, f0=None, f=None, workspace=None):
+        """``iters`` iterations of "em", "smart" (simultaneous MART) or "sart"
+        (simultaneous ART kept nonnegative, relaxation ``relax`` in (0, 2)) from
+        f0 (default all ones); ``f`` is updated in place if given."""
+        self._need_device()
+        torch = _torch()
+        if solver not in SOLVERS:
+            raise ValueError(f"solver must be one of {sorted(SOLVERS)}")
+        g = self._dev_tensor(g, self.sizes.n, "g")
+        if f is None:
+            f = (torch.ones(self.shape_f, dtype=torch.float32, device=self.device) if f0 is None
+                 else self._dev_tensor(f0, self.sizes.m, "f0").clone())
+        else:
+            need_tensor(f, self.sizes.m, "f", self.device)
+        if workspace is None:
+            workspace = self.solve_workspace()
+        need = self.sizes.solve_workspace_bytes if solver == "sart" else self.sizes.workspace_bytes
+        wp, wb = self._ws(workspace, need)
+        st = self._L.ctis_solve_iterate(self._handle, SOLVERS[solver], ctypes.c_void_p(g.data_ptr()),
+                                        ctypes.c_void_p(f.data_ptr()), int(iters), float(relax), wp, wb,
+                                        _stream(torch, self.device))
+        _check(self._L, st, "ctis_solve_iterate")
+        return f
+
     def diagnostics(self, g, f, workspace=None, out=None):
         """(flux sum_j h_j f_j, sum g, Poisson log-likelihood, pixels with g > 0
         and H f <= 0) of the iterate f, in double precision on the GPU; `out`
@@ -701,6 +737,32 @@ class Batch:
                                            ctypes.c_void_p(f_all.data_ptr()), int(iters), wp, wb,
                                            _stream(torch, self.device))
         _check(self._L, st, "ctis_batch_em_iterate")
+        return f_all
+
+    def solve_workspace(self):
+        """A workspace large enough for every solver (SART's included)."""
+        torch = _torch()
+        return torch.empty(max(self.info["solve_workspace_bytes"] // 4, 64), dtype=torch.float32,
+                           device=self.device)
+
+    def solve(self, g_all, iters: int, solver: str = "smart", relax: float = 1.0, f_all=None, workspace=None):
+        """Plan.solve for every frame at once (f_all updated in place if given,
+        else a new all-ones start)."""
+        torch = _torch()
+        if solver not in SOLVERS:
+            raise ValueError(f"solver must be one of {sorted(SOLVERS)}")
+        need_tensor(g_all, self.n_total, "g_all", self.device)
+        if f_all is None:
+            f_all = torch.ones(self.m_total, dtype=torch.float32, device=self.device)
+        need_tensor(f_all, self.m_total, "f_all", self.device)
+        if workspace is None:
+            workspace = self.solve_workspace()
+        need = self.info["solve_workspace_bytes"] if solver == "sart" else self.info["workspace_bytes"]
+        wp, wb = self._ws(workspace, need)
+        st = self._L.ctis_batch_solve_iterate(self._handle, SOLVERS[solver], ctypes.c_void_p(g_all.data_ptr()),
+                                              ctypes.c_void_p(f_all.data_ptr()), int(iters), float(relax), wp, wb,
+                                              _stream(torch, self.device))
+        _check(self._L, st, "ctis_batch_solve_iterate")
         return f_all
 
     def em_forward_ratio(self, f_all, g_all, workspace):
