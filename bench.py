@@ -76,10 +76,12 @@ def host_cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(case, g_host: np.ndarray, iters_per_step: int, seconds: float):
-    """The FP64 oracle (explicit H, OpenMP) on the host: EM iterations from
-    all ones until `seconds` have passed, on all host cores and then on one
-    core.  Assembly of the explicit H is excluded (and timed separately)."""
+def cpu_baseline(case, g_host: np.ndarray, iters_per_step: int, seconds: float, solver: str = "em",
+                 relax: float = 1.0):
+    """The FP64 oracle (explicit H, OpenMP) on the host: iterations of the
+    solver from all ones until `seconds` have passed, on all host cores and
+    then on one core.  Assembly of the explicit H is excluded (and timed
+    separately)."""
     import oracle
     progress("cpu baseline: assembling the explicit H")
     t0 = time.perf_counter()
@@ -90,7 +92,12 @@ def cpu_baseline(case, g_host: np.ndarray, iters_per_step: int, seconds: float):
         done, f = 0, None
         t1 = time.perf_counter()
         while True:
-            f = o.em(g_host, 1, f0=f)
+            if solver == "em":
+                f = o.em(g_host, 1, f0=f)
+            elif solver == "smart":
+                f = o.smart(g_host, 1, f0=f)
+            else:
+                f = o.sart(g_host, 1, f0=f, relax=relax)
             done += 1
             el = time.perf_counter() - t1
             if el >= budget or done >= 100_000:
@@ -105,12 +112,13 @@ def cpu_baseline(case, g_host: np.ndarray, iters_per_step: int, seconds: float):
     done1, el1 = sample(seconds)
     o.close()
     rate1 = done1 / el1
-    return {"value": rate, "unit": "EM iterations/s", "cores": all_threads, "kind": "oracle",
-            "sample": f"{done} EM iterations of the same frame from all ones ({el:.1f} s, FP64 explicit "
+    unit = "EM iterations/s" if solver == "em" else f"{solver.upper()} iterations/s"
+    return {"value": rate, "unit": unit, "cores": all_threads, "kind": "oracle",
+            "sample": f"{done} {solver.upper()} iterations of the same frame from all ones ({el:.1f} s, FP64 explicit "
                       f"sparse H, assembly of {t_asm:.1f} s excluded); one step of {iters_per_step} "
                       f"iterations would take {iters_per_step / rate:.2f} s",
             "host_cpu": host_cpu_model(),
-            "one_core": {"value": rate1, "unit": "EM iterations/s", "cores": 1,
+            "one_core": {"value": rate1, "unit": unit, "cores": 1,
                          "sample": f"{done1} EM iterations ({el1:.1f} s)"}}
 
 
@@ -133,6 +141,10 @@ def main(argv=None) -> int:
                          "'tile 64x16 W4 adjoint W1 Bauto') instead of autotuning")
     ap.add_argument("--no-sequential", action="store_true",
                     help="config 4: skip the 64 sequential single-frame solves")
+    ap.add_argument("--solver", choices=["em", "smart", "sart"], default="em",
+                    help="single-frame configs: the solver iterated (simultaneous MART or ART on the same "
+                         "projections; default EM)")
+    ap.add_argument("--relax", type=float, default=1.0, help="SART relaxation")
     ap.add_argument("--tile-path", action="store_true",
                     help="configs 1-3: EM on the tile path (64 x 16 FPA tiles read straight from f) instead "
                          "of the region path (16 x 16 regions read from a zero-bordered copy of f)")
@@ -171,6 +183,11 @@ def main(argv=None) -> int:
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": nbytes, "launches": 3}), flush=True)
         return 0
+    if args.solver != "em":
+        if args.config in (4, 5) or args.path == "fourier":
+            print("bench.py: --solver applies to the single-frame gather configs 1-3", file=sys.stderr)
+            return 2
+        return bench_solver(args, torch, ctis, W, dev)
     if args.config == 4:
         return bench_batched(args, torch, ctis, W, dev)
     if args.config == 5:
@@ -326,6 +343,88 @@ def main(argv=None) -> int:
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(case, g_host, K, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+    plan.close()
+    return 0
+
+
+def bench_solver(args, torch, ctis, W, dev) -> int:
+    """The single-frame solve with simultaneous MART or ART (ctis_solve_iterate)
+    in place of EM: the same projections with other epilogues, the same
+    iteration count, graph-launched.  The roofline position is that of one
+    iteration (forward and back projection together), from the graph-launched
+    solve's time per iteration."""
+    case = W.make_case(args.config)
+    cfg, geo, K = case.cfg, case.geometry, case.cfg.iters
+    progress(f"workload {cfg.name}: plan ({args.solver})")
+    plan = ctis.Plan.from_case(case, tile_path=args.tile_path)
+    info = plan.info
+    clean = plan.forward(torch.from_numpy(case.f_true.astype(np.float32)).to(dev)).double().cpu().numpy()
+    g_host = case.noisy(clean)
+    g = torch.from_numpy(g_host).to(dev)
+    f = torch.empty(plan.shape_f, dtype=torch.float32, device=dev)
+    ws = plan.solve_workspace()
+
+    def solve():
+        f.fill_(1.0)
+        plan.solve(g, K, solver=args.solver, relax=args.relax, f=f, workspace=ws)
+
+    gr = _graph_of(torch, solve)
+    for _ in range(args.warmup):
+        gr.replay()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        gr.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms = e0.elapsed_time(e1)
+    if not torch.isfinite(f).all() or (f < 0).any():
+        print("bench.py: the solve produced a negative or non-finite value", file=sys.stderr)
+        return 1
+    it_s = args.steps * K / (ms / 1e3)
+    t_it = 1.0 / it_s
+    m, n_supp = info.m, info.n_support
+    bytes_it = 4 * (m + 2 * n_supp) + 4 * (2 * m + n_supp)
+    flops_it = 4 * info.ell * info.nnz
+    if bytes_it / (HBM_PEAK_GBS * 1e9) >= flops_it / (FP32_VALU_PEAK_TFLOPS * 1e12):
+        achieved = bytes_it / t_it / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+    else:
+        achieved = flops_it / t_it / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP32_VALU_PEAK_TFLOPS, "traffic": None,
+                "frac_of_unpacked_fp32": achieved / FP32_VALU_UNPACKED_TFLOPS}
+    roof.update({"kernel": "one iteration (forward and back projection, graph launched)",
+                 "path": "region" if info.em_region_path else "tile", "avg_iteration_us": t_it * 1e6,
+                 "algorithmic_bytes_per_iteration": bytes_it, "algorithmic_flop_per_iteration": flops_it})
+    line = {
+        "metric": METRIC,
+        "value": it_s,
+        "unit": f"{args.solver.upper()} iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": cfg.name + f" ({args.solver.upper()} in place of EM)", "solver": args.solver,
+                   "relax": args.relax if args.solver == "sart" else None, "iters_per_step": K, "m": m, "n": geo.n,
+                   "forward_path": "region" if info.em_region_path else "tile"},
+        "voxel_updates_per_s": it_s * m,
+        "wall_s": wall,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(case, g_host, K, args.cpu_seconds, args.solver, args.relax)
     print(json.dumps(line), flush=True)
     plan.close()
     return 0
