@@ -143,3 +143,43 @@ def test_solver_error_paths(torch, ctis):
     torch.cuda.synchronize()
     with pytest.raises(ValueError):
         p.solve(g, 1, solver="mart")
+
+
+def test_solvers_degenerate_cases(torch, ctis, oracle_mod):
+    """An empty wavelength (h = 0: its voxels go to 0), a single-pixel field
+    stop, zero iterations (f untouched), and a frame of zeros (SMART keeps f,
+    SART drives it to 0 within rounding)."""
+    rng = np.random.default_rng(44)
+    geo = W.Geometry(9, 7, 3, 40, 30)
+    ptr, idx, val = W.random_kernels(geo, 6, rng)
+    # drop wavelength 1's entries: it has no calibration (h = 0)
+    ptr = ptr.copy()
+    n1 = int(ptr[2] - ptr[1])
+    keep = np.r_[np.arange(ptr[1]), np.arange(ptr[2], idx.size)]
+    idx, val = idx[keep], val[keep]
+    ptr[2:] -= n1
+    o = oracle_mod.Oracle(geo.a, geo.alpha, geo.w, geo.gamma, geo.xi, ptr, idx, val)
+    p = ctis.Plan(geo.a, geo.alpha, geo.w, geo.gamma, geo.xi, ptr, idx, val)
+    g = (o.forward(rng.uniform(0.2, 2.0, geo.m)) + 0.1).astype(np.float32)
+    gd = torch.from_numpy(g).cuda()
+    for solver in ("smart", "sart"):
+        f = p.solve(gd, 3, solver=solver).cpu().numpy()
+        assert np.all(f.reshape(geo.w, -1)[1] == 0.0)
+        assert rel_l2(f, oracle_run(o, solver, g, 3, 1.0)) <= TOL
+        f0 = torch.from_numpy(rng.uniform(0.5, 1.5, geo.m).astype(np.float32)).cuda()
+        assert torch.equal(p.solve(gd, 0, solver=solver, f0=f0), f0)
+    zeros = torch.zeros(geo.n, device="cuda")
+    ones = p.solve(zeros, 2, solver="smart").cpu().numpy().reshape(geo.w, -1)
+    assert np.all(ones[[0, 2]] == 1.0) and np.all(ones[1] == 0.0)
+    # SART: r = -H f / R = -1 at f = 1, so one step reaches 0, up to FP32
+    # rounding (H f and R = H 1 sum the same terms in different orders)
+    assert np.abs(p.solve(zeros, 2, solver="sart").cpu().numpy()).max() <= 1e-6
+    # a single-pixel field stop
+    geo1 = W.Geometry(1, 1, 2, 13, 11)
+    k1 = W.random_kernels(geo1, 5, rng)
+    o1 = oracle_mod.Oracle(geo1.a, geo1.alpha, geo1.w, geo1.gamma, geo1.xi, *k1)
+    p1 = ctis.Plan(geo1.a, geo1.alpha, geo1.w, geo1.gamma, geo1.xi, *k1)
+    g1 = (o1.forward(np.array([0.7, 1.9])) * rng.uniform(0.8, 1.2, geo1.n)).astype(np.float32)
+    for solver in ("smart", "sart"):
+        f = p1.solve(torch.from_numpy(g1).cuda(), 5, solver=solver).cpu().numpy()
+        assert rel_l2(f, oracle_run(o1, solver, g1, 5, 1.0)) <= TOL
