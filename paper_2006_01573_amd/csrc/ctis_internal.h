@@ -116,6 +116,7 @@ struct DevWork {
     size_t workspace_bytes = 0;  // u region + partial tiles + partial regions + padded f + diagnostics
     bool persistent = false;     // grid-stride workgroups instead of one per unit
     bool region_solo = false;    // region forward with a lane group per unit
+    bool adj_direct = false;     // every back-projection box takes the direct window
     // value gradients and value updates
     const int32_t *entry_slot = nullptr, *box_lam = nullptr, *lam_box0 = nullptr;
     const int32_t *lam_units_ptr = nullptr, *lam_units = nullptr;
@@ -148,6 +149,7 @@ struct HostWork {
     std::vector<float> box_w, box_wf, h;
     int64_t u_floats = 0;        // u region of the EM workspace
     int64_t g_floats = 0;        // extent of the g buffer
+    bool adj_direct = false;     // every back-projection record is direct
     int64_t f_floats = 0;        // extent of the f buffer
     // value tables (layout as in DevWork)
     std::vector<int32_t> entry_slot, box_lam, lam_box0, lam_units_ptr, lam_units, slot_entries_ptr, slot_entries;

@@ -136,6 +136,11 @@ __device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, unsigned off) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
 }
 
+// raw 128-bit buffer load at byte offset `off` (4-byte aligned)
+__device__ __forceinline__ float4 bload4(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+
 // raw 32-bit buffer load at byte offset voff + soff (soff wave-uniform: a
 // scalar register)
 __device__ __forceinline__ float bload2(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
@@ -327,6 +332,55 @@ __device__ __forceinline__ void load_adjoint_direct(Pending<B> &pd, __amdgpu_buf
 #pragma unroll
     for (int t = 0; t < Wn::NXT; ++t) pd.x[t] = bload2(ur, xo[t], s0);
     load_values<B>(pd, wtab, box, lane);
+}
+
+// Direct adjoint window in 16-byte pieces: piece k = lane + 64 t is row
+// k / SX4, column quad k % SX4 of the window (SX4 = SXP / 4 pieces per row),
+// at byte offset s0 + voff[t] of u with voff[t] = 4 gamma row + 16 quad
+// precomputed per unit; the whole offset goes in the vector operand, so
+// the range check covers the up to three floats a row's last piece reads
+// past the window.  A lane holds NQ pieces instead of one float per window
+// row: a quarter of the load instructions.
+template <int B>
+struct Pending4 {
+    static constexpr int SX4 = Win<B>::SXP / 4, NP = SX4 * Win<B>::SY, NQ = (NP + 63) / 64;
+    float4 q[NQ];
+    float wt;
+};
+
+template <int B>
+__device__ __forceinline__ void adjoint_piece_offsets(unsigned (&voff)[Pending4<B>::NQ], int lane, int gamma) {
+    using P4 = Pending4<B>;
+#pragma unroll
+    for (int t = 0; t < P4::NQ; ++t) {
+        const int k = lane + 64 * t;
+        voff[t] = k < P4::NP ? 4u * (unsigned)gamma * (unsigned)(k / P4::SX4) + 16u * (unsigned)(k % P4::SX4) : 0u;
+    }
+}
+
+template <int B>
+__device__ __forceinline__ void load_adjoint_direct4(Pending4<B> &pd, __amdgpu_buffer_rsrc_t ur,
+                                                     const float *__restrict__ wtab, const Geo &p, int Xs, int Ys,
+                                                     int box, int lane,
+                                                     const unsigned (&voff)[Pending4<B>::NQ]) {
+    const unsigned s0 = 4u * (unsigned)(Xs + p.gamma * Ys);
+#pragma unroll
+    for (int t = 0; t < Pending4<B>::NQ; ++t) pd.q[t] = bload4(ur, s0 + voff[t]);
+    pd.wt = lane < B * B ? wtab[(size_t)box * (B * B) + lane] : 0.0f;
+}
+
+// Pieces into S[0, REG) (piece k at float 4k: the row pitch is SX4 pieces),
+// box values into S[REG, REG + B*B).
+template <int B>
+__device__ __forceinline__ void store_window4(float *S, const Pending4<B> &pd, int lane) {
+    using P4 = Pending4<B>;
+    static_assert(Win<B>::SXP == 4 * P4::SX4 && Win<B>::REG == 4 * P4::NP, "pieces are packed row after row");
+#pragma unroll
+    for (int t = 0; t < P4::NQ; ++t) {
+        const int k = lane + 64 * t;
+        if (t + 1 < P4::NQ || k < P4::NP) *reinterpret_cast<float4 *>(S + 4 * k) = pd.q[t];
+    }
+    if (lane < B * B) S[Win<B>::REG + lane] = pd.wt;
 }
 
 // Window into S[0, REG), box values into S[REG, REG + B*B) (kValues).
@@ -605,10 +659,6 @@ struct RPend {
     float wt[RWin<B, GX>::NWT];
 };
 
-// raw 128-bit buffer load at byte offset `off` (4-byte aligned)
-__device__ __forceinline__ float4 bload4(__amdgpu_buffer_rsrc_t r, unsigned off) {
-    return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
-}
 
 // Window of one (region, box) item, rec = (origin, 0, 0, box): piece t of
 // this lane at byte offset 4*origin + poff[t] of the padded copy (poff: the
@@ -934,7 +984,7 @@ __global__ void __launch_bounds__(256) k_pad(const int4 *__restrict__ blocks, co
 }
 
 // Back projection (+ EM update).  Units: (frame, wavelength, field-stop tile).
-template <int B>
+template <int B, bool D4>
 __global__ void __launch_bounds__(64 * Win<B>::MAXW) k_adjoint(const int4 *__restrict__ meta,
                                                                const int4 *__restrict__ items, const int stride,
                                                                const int n_units, const float *__restrict__ box_w,
@@ -983,34 +1033,43 @@ __global__ void __launch_bounds__(64 * Win<B>::MAXW) k_adjoint(const int4 *__res
             for (int q = 0; q < 4; ++q) acc[a][q] = 0.0f;
 
         // byte offsets of this lane's extra window slots (column 64 + e, row
-        // yy) within a direct window
+        // yy) within a direct window; with D4 (every box of the list direct)
+        // the offsets of its 16-byte pieces instead
         unsigned xo[Wn::NXT > 0 ? Wn::NXT : 1];
+        unsigned voff[Pending4<B>::NQ];
+        if constexpr (D4) {
+            adjoint_piece_offsets<B>(voff, lane, geo.gamma);
+        } else {
 #pragma unroll
-        for (int t = 0; t < Wn::NXT; ++t) {
-            const int kk = lane + 64 * t;
-            xo[t] = kk < Wn::E * Wn::SY ? 4u * (unsigned)(TX + kk % Wn::ED) + 4u * (unsigned)geo.gamma *
-                                                                                   (unsigned)(kk / Wn::ED)
-                                        : 0u;
+            for (int t = 0; t < Wn::NXT; ++t) {
+                const int kk = lane + 64 * t;
+                xo[t] = kk < Wn::E * Wn::SY ? 4u * (unsigned)(TX + kk % Wn::ED) + 4u * (unsigned)geo.gamma *
+                                                                                       (unsigned)(kk / Wn::ED)
+                                            : 0u;
+            }
         }
 
         Pending<B> pa;
-        if (rec0.w >= 0) {
-            if (rec0.z)
-                load_adjoint_direct<B>(pa, ur, box_w, geo, rec0.x + x0, rec0.y + y0, rec0.w, lane, xo);
+        Pending4<B> pq;
+        auto fetch = [&](int4 rec) {
+            if (rec.w < 0) return;
+            if constexpr (D4)
+                load_adjoint_direct4<B>(pq, ur, box_w, geo, rec.x + x0, rec.y + y0, rec.w, lane, voff);
+            else if (rec.z)
+                load_adjoint_direct<B>(pa, ur, box_w, geo, rec.x + x0, rec.y + y0, rec.w, lane, xo);
             else
-                load_adjoint<B>(pa, ur, box_w, geo, rec0.x + x0, rec0.y + y0, rec0.w, lane);
-        }
+                load_adjoint<B>(pa, ur, box_w, geo, rec.x + x0, rec.y + y0, rec.w, lane);
+        };
+        fetch(rec0);
         while (rec0.w >= 0) {
-            store_window<B>(S, pa, lane);
+            if constexpr (D4)
+                store_window4<B>(S, pq, lane);
+            else
+                store_window<B>(S, pa, lane);
             wave_lds_sync();
             k += nw;
             const int4 rec3 = record(list, k + nw, stride);
-            if (rec1.w >= 0) {
-                if (rec1.z)
-                    load_adjoint_direct<B>(pa, ur, box_w, geo, rec1.x + x0, rec1.y + y0, rec1.w, lane, xo);
-                else
-                    load_adjoint<B>(pa, ur, box_w, geo, rec1.x + x0, rec1.y + y0, rec1.w, lane);
-            }
+            fetch(rec1);
             correlate<B, Win<B>::SXP, Win<B>::REG>(acc, S, lx, ly);
             wave_lds_sync();
             rec0 = rec1;
@@ -1161,7 +1220,7 @@ __global__ void __launch_bounds__(256) k_forward_solo(const int4 *__restrict__ m
     }
 }
 
-template <int B>
+template <int B, bool D4>
 __global__ void __launch_bounds__(256) k_adjoint_solo(const int4 *__restrict__ meta,
                                                       const int4 *__restrict__ items, const int stride,
                                                       const int n_units, const float *__restrict__ box_w,
@@ -1195,12 +1254,17 @@ __global__ void __launch_bounds__(256) k_adjoint_solo(const int4 *__restrict__ m
         int4 rec1 = record(list, 1, stride);
 
         unsigned xo[Wn::NXT > 0 ? Wn::NXT : 1];
+        unsigned voff[Pending4<B>::NQ];
+        if constexpr (D4) {
+            adjoint_piece_offsets<B>(voff, lane, geo.gamma);
+        } else {
 #pragma unroll
-        for (int t = 0; t < Wn::NXT; ++t) {
-            const int kk = lane + 64 * t;
-            xo[t] = kk < Wn::E * Wn::SY ? 4u * (unsigned)(TX + kk % Wn::ED) + 4u * (unsigned)geo.gamma *
-                                                                                   (unsigned)(kk / Wn::ED)
-                                        : 0u;
+            for (int t = 0; t < Wn::NXT; ++t) {
+                const int kk = lane + 64 * t;
+                xo[t] = kk < Wn::E * Wn::SY ? 4u * (unsigned)(TX + kk % Wn::ED) + 4u * (unsigned)geo.gamma *
+                                                                                       (unsigned)(kk / Wn::ED)
+                                            : 0u;
+            }
         }
 
         float acc[4][4];
@@ -1210,23 +1274,26 @@ __global__ void __launch_bounds__(256) k_adjoint_solo(const int4 *__restrict__ m
             for (int q = 0; q < 4; ++q) acc[a][q] = 0.0f;
 
         Pending<B> pa;
-        if (rec0.w >= 0) {
-            if (rec0.z)
-                load_adjoint_direct<B>(pa, ur, box_w, geo, rec0.x + x0, rec0.y + y0, rec0.w, lane, xo);
+        Pending4<B> pq;
+        auto fetch = [&](int4 rec) {
+            if (rec.w < 0) return;
+            if constexpr (D4)
+                load_adjoint_direct4<B>(pq, ur, box_w, geo, rec.x + x0, rec.y + y0, rec.w, lane, voff);
+            else if (rec.z)
+                load_adjoint_direct<B>(pa, ur, box_w, geo, rec.x + x0, rec.y + y0, rec.w, lane, xo);
             else
-                load_adjoint<B>(pa, ur, box_w, geo, rec0.x + x0, rec0.y + y0, rec0.w, lane);
-        }
+                load_adjoint<B>(pa, ur, box_w, geo, rec.x + x0, rec.y + y0, rec.w, lane);
+        };
+        fetch(rec0);
         while (rec0.w >= 0) {
-            store_window<B>(S, pa, lane);
+            if constexpr (D4)
+                store_window4<B>(S, pq, lane);
+            else
+                store_window<B>(S, pa, lane);
             wave_lds_sync();
             k += 1;
             const int4 rec3 = record(list, k + 1, stride);
-            if (rec1.w >= 0) {
-                if (rec1.z)
-                    load_adjoint_direct<B>(pa, ur, box_w, geo, rec1.x + x0, rec1.y + y0, rec1.w, lane, xo);
-                else
-                    load_adjoint<B>(pa, ur, box_w, geo, rec1.x + x0, rec1.y + y0, rec1.w, lane);
-            }
+            fetch(rec1);
             correlate<B, Win<B>::SXP, Win<B>::REG>(acc, S, lx, ly);
             wave_lds_sync();
             rec0 = rec1;
@@ -1599,7 +1666,11 @@ int enable_large_lds() {
         const int bytes = Win<B>::MAXW * Win<B>::WREG * (int)sizeof(float);
         err = hipFuncSetAttribute((const void *)k_forward<B>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         if (err == hipSuccess)
-            err = hipFuncSetAttribute((const void *)k_adjoint<B>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+            err = hipFuncSetAttribute((const void *)k_adjoint<B, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      bytes);
+        if (err == hipSuccess)
+            err = hipFuncSetAttribute((const void *)k_adjoint<B, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      bytes);
     });
     return (int)err;
 }
@@ -1724,7 +1795,8 @@ int adjoint_B(const DevWork &w, const float *r, const float *in1, const float *i
     if (L.waves == 1) {   // solo: four units per workgroup, a wave each
         const size_t lds = (size_t)kSoloWaves * Win<B>::WREG * sizeof(float);
         const int groups = solo_groups(L.n_units, kSoloWaves);
-        hipLaunchKernelGGL(k_adjoint_solo<B>, dim3(grid_for(groups, lds, kSoloWaves, w.persistent)),
+        auto kern = w.adj_direct ? k_adjoint_solo<B, true> : k_adjoint_solo<B, false>;
+        hipLaunchKernelGGL(kern, dim3(grid_for(groups, lds, kSoloWaves, w.persistent)),
                            dim3(64 * kSoloWaves), lds, st, L.meta, L.items, L.stride, L.n_units, w.box_w, w.h, r, in1,
                            in2, out, out2, flux, mode, fpad, w.halo_x, w.halo_y, relax);
         return (int)hipGetLastError();
@@ -1734,7 +1806,8 @@ int adjoint_B(const DevWork &w, const float *r, const float *in1, const float *i
         const int e = enable_large_lds<B>();
         if (e) return e;
     }
-    hipLaunchKernelGGL(k_adjoint<B>, dim3(grid_for(L.n_units, lds, L.waves, w.persistent)), dim3(64 * L.waves), lds, st,
+    auto kern = w.adj_direct ? k_adjoint<B, true> : k_adjoint<B, false>;
+    hipLaunchKernelGGL(kern, dim3(grid_for(L.n_units, lds, L.waves, w.persistent)), dim3(64 * L.waves), lds, st,
                        L.meta, L.items, L.stride, L.n_units, w.box_w, w.h, r, in1, in2, out, out2, flux, mode, fpad,
                        w.halo_x, w.halo_y, relax);
     return (int)hipGetLastError();

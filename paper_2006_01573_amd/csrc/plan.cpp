@@ -730,6 +730,9 @@ ctis_status build_work(const std::vector<FrameRef> &frames, bool with_full, Host
     }
     if (adj_units.size() > (size_t)INT32_MAX / ((size_t)A.stride * BB))
         return fail(CTIS_E_TOO_LARGE, "too many back-projection units");
+    hw.adj_direct = true;
+    for (size_t r = 0; r < A.items.size(); r += 4)
+        if (A.items[r + 3] >= 0 && A.items[r + 2] == 0) hw.adj_direct = false;
     adj_units = xcd_order(adj_units, frames.size(), [](const AdjRef &u) { return u.frame; },
                           [](const AdjRef &u) { return (int64_t)u.work; });
     std::vector<std::vector<int32_t>> units_of(lambda_base);
@@ -904,6 +907,7 @@ ctis_status upload_work(const HostWork &hw, DevWork &dw) {
     dw.hpart_off = L.hpart_off;
     dw.vg_off = L.vg_off;
     dw.vjp_workspace_bytes = L.vjp_bytes;
+    dw.adj_direct = hw.adj_direct;
     dw.solve_r_off = L.solve_r_off;
     dw.solve_ones_off = L.solve_ones_off;
     dw.solve_workspace_bytes = L.solve_bytes;
