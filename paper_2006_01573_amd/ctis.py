@@ -789,44 +789,6 @@ class Batch:
         _check(self._L, st, "ctis_batch_em_adjoint_update")
         return f_out
 
-    def diagnostics(self, g, f, workspace=None, out=None):
-        """(flux sum_j h_j f_j, sum g, Poisson log-likelihood, pixels with g > 0
-        and H f <= 0) of the iterate f, in double precision on the GPU; `out`
-        (device float64[4]) receives them without a host copy if given."""
-        self._need_device()
-        torch = _torch()
-        g = self._dev_tensor(g, self.sizes.n, "g")
-        f = self._dev_tensor(f, self.sizes.m, "f")
-        ret = out is None
-        if out is None:
-            out = torch.empty(4, dtype=torch.float64, device=self.device)
-        elif not (isinstance(out, torch.Tensor) and out.dtype == torch.float64 and out.numel() == 4
-                  and out.is_contiguous() and out.device == torch.device(self.device)):
-            raise ValueError("out must be a contiguous float64 tensor of 4 elements on the plan's device")
-        if workspace is None:
-            workspace = self.workspace()
-        wp, wb = self._ws(workspace)
-        st = self._L.ctis_em_diagnostics(self._handle, ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(f.data_ptr()),
-                                         ctypes.c_void_p(out.data_ptr()), wp, wb, _stream(torch, self.device))
-        _check(self._L, st, "ctis_em_diagnostics")
-        if ret:
-            v = out.cpu().tolist()
-            return v[0], v[1], v[2], int(v[3])
-        return out
-
-    def em_static(self, g, iters: int, f):
-        """EM iterations in place on ``f`` through ctis_em_iterate_static: the
-        library's static device scratch stands in for the workspace (no
-        allocation; calls on one device must not overlap)."""
-        self._need_device()
-        torch = _torch()
-        g = self._dev_tensor(g, self.sizes.n, "g")
-        need_tensor(f, self.sizes.m, "f", self.device)
-        st = self._L.ctis_em_iterate_static(self._handle, ctypes.c_void_p(g.data_ptr()),
-                                            ctypes.c_void_p(f.data_ptr()), int(iters), _stream(torch, self.device))
-        _check(self._L, st, "ctis_em_iterate_static")
-        return f
-
     # -- derivatives ------------------------------------------------------------------
     def vjp_workspace(self):
         torch = _torch()
