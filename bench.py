@@ -122,6 +122,20 @@ def cpu_baseline(case, g_host: np.ndarray, iters_per_step: int, seconds: float, 
                          "sample": f"{done1} EM iterations ({el1:.1f} s)"}}
 
 
+def region_arg(args, ctis):
+    """--region RXxRY as the plan's region shape (0: the plan's choice)."""
+    if not args.region:
+        return 0
+    try:
+        shape = tuple(int(x) for x in args.region.lower().split("x"))
+    except ValueError:
+        shape = ()
+    if shape not in ctis.REGION_SHAPES[1:]:
+        raise SystemExit(f"--region must be one of "
+                         f"{', '.join(f'{a}x{b}' for a, b in ctis.REGION_SHAPES[1:])}")
+    return shape
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,6 +162,9 @@ def main(argv=None) -> int:
     ap.add_argument("--tile-path", action="store_true",
                     help="configs 1-3: EM on the tile path (64 x 16 FPA tiles read straight from f) instead "
                          "of the region path (16 x 16 regions read from a zero-bordered copy of f)")
+    ap.add_argument("--region", default="", metavar="RXxRY",
+                    help="configs 1-3: region shape of the region path (pixels along gamma x xi: 8x32, 16x16, "
+                         "32x8, 16x8, 8x16 or 8x8; default the plan's choice)")
     ap.add_argument("--launch", choices=["graph", "stream"], default="graph",
                     help="graph: each step is one replay of a HIP graph holding the whole solve; "
                          "stream: the solve's kernels are launched one by one on the stream")
@@ -199,7 +216,7 @@ def main(argv=None) -> int:
     geo = case.geometry
     K = cfg.iters
     progress(f"workload {cfg.name}: plan")
-    plan = ctis.Plan.from_case(case, tile_path=args.tile_path)
+    plan = ctis.Plan.from_case(case, tile_path=args.tile_path, region=region_arg(args, ctis))
     info = plan.info
     # the frame: Poisson noise on H f_true, formed with the library's own forward
     f_true = torch.from_numpy(case.f_true.astype(np.float32)).to(dev)
@@ -331,6 +348,7 @@ def main(argv=None) -> int:
                    "gamma": geo.gamma, "xi": geo.xi, "m": m, "n": geo.n, "n_support": n_supp,
                    "nnz": info.nnz, "box": info.box, "em_iters_per_step": K,
                    "forward_path": "region" if info.em_region_path else "tile",
+                   **({"region": f"{info.region_fast}x{info.region_slow}"} if info.em_region_path else {}),
                    "forward_executed_madds_over_method": ((info.region_forward_madds if info.em_region_path
                                                            else info.tile_forward_madds) / info.method_madds),
                    "start": "all ones", "noise": f"Poisson, {cfg.noise} {cfg.photons:g}"},
@@ -357,7 +375,7 @@ def bench_solver(args, torch, ctis, W, dev) -> int:
     case = W.make_case(args.config)
     cfg, geo, K = case.cfg, case.geometry, case.cfg.iters
     progress(f"workload {cfg.name}: plan ({args.solver})")
-    plan = ctis.Plan.from_case(case, tile_path=args.tile_path)
+    plan = ctis.Plan.from_case(case, tile_path=args.tile_path, region=region_arg(args, ctis))
     info = plan.info
     clean = plan.forward(torch.from_numpy(case.f_true.astype(np.float32)).to(dev)).double().cpu().numpy()
     g_host = case.noisy(clean)
@@ -418,7 +436,8 @@ def bench_solver(args, torch, ctis, W, dev) -> int:
         "data": "synthetic",
         "config": {"workload": cfg.name + f" ({args.solver.upper()} in place of EM)", "solver": args.solver,
                    "relax": args.relax if args.solver == "sart" else None, "iters_per_step": K, "m": m, "n": geo.n,
-                   "forward_path": "region" if info.em_region_path else "tile"},
+                   "forward_path": "region" if info.em_region_path else "tile",
+                   **({"region": f"{info.region_fast}x{info.region_slow}"} if info.em_region_path else {})},
         "voxel_updates_per_s": it_s * m,
         "wall_s": wall,
         "roofline": roof,

@@ -80,11 +80,13 @@ typedef struct ctis_batch ctis_batch;
                                            1..8 (0 = chosen by the plan)         */
 #define CTIS_PLAN_TILE_PATH 0x4u        /* EM on the tile path even where the
                                            region path applies (comparisons) */
-#define CTIS_PLAN_REGION(k) (((uint32_t)(k) & 0x3u) << 12)
+#define CTIS_PLAN_REGION(k) (((uint32_t)(k) & 0x7u) << 12)
                                         /* region shape of the region path
                                            (pixels along gamma x xi): 1 = 8 x
-                                           32, 2 = 16 x 16, 3 = 32 x 8, 0 =
-                                           chosen by the plan                 */
+                                           32, 2 = 16 x 16, 3 = 32 x 8, 4 =
+                                           16 x 8, 5 = 8 x 16, 6 = 8 x 8, 0 =
+                                           chosen by the plan (16 x 16); 7 is
+                                           refused with CTIS_E_ARG            */
 #define CTIS_PLAN_KEEP_ZEROS 0x2u       /* the structure is the set of given
                                            positions, whatever their values:
                                            entries that merge to an exact zero
@@ -117,8 +119,9 @@ typedef struct {
                                     enough for ctis_em_iterate)                 */
     int32_t dropped;         /* 1 if some entry merged to an exact zero and was
                                 dropped (never with CTIS_PLAN_KEEP_ZEROS)       */
-    /* The EM path's forward projection.  Region path: FPA regions of 256
-     * pixels (region_fast x region_slow), four boxes per wavefront at a time,
+    /* The EM path's forward projection.  Region path: FPA regions of 64,
+     * 128 or 256 pixels (region_fast x region_slow; CTIS_PLAN_REGION), 16,
+     * 8 or 4 boxes per wavefront at a time (a lane group per box),
      * windows read from a zero-bordered copy of f; taken when the FPA leaves
      * region_fast + B - 2 pixels beside the field stop along gamma and
      * region_slow + B - 2 along xi (and CTIS_PLAN_TILE_PATH is not set).
@@ -348,10 +351,10 @@ ctis_status ctis_em_adjoint_update(const ctis_plan *plan, void *workspace, size_
                                           one workgroup per work unit                    */
 #define CTIS_BATCH_WAVES_REGION(n) (((uint32_t)(n) & 0xFu) << 11)  /* region forward, 0 = chosen */
 #define CTIS_BATCH_TILE_PATH 0x8000u   /* EM on the tile path even where the region path applies */
-#define CTIS_BATCH_REGION_SOLO 0x10000u /* region forward with a 16-lane group per region walking
-                                           all of its boxes (four regions per wavefront), for
-                                           batches of many short regions; the region waves
-                                           setting is then unused                          */
+#define CTIS_BATCH_REGION_SOLO 0x10000u /* region forward with a lane group per region walking
+                                           all of its boxes (4, 8 or 16 regions per wavefront
+                                           by region size), for batches of many short regions;
+                                           the region waves setting is then unused           */
 
 typedef struct {
     int32_t n_frames;

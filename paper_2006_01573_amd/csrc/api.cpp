@@ -180,8 +180,10 @@ ctis_status ctis_plan_create(ctis_plan **out, int32_t a, int32_t alpha, int32_t 
     if (!out) return fail(CTIS_E_ARG, "out is NULL");
     *out = nullptr;
     const uint32_t known =
-        CTIS_PLAN_HOST_ONLY | CTIS_PLAN_KEEP_ZEROS | CTIS_PLAN_TILE_PATH | CTIS_PLAN_BOX(0xF) | CTIS_PLAN_REGION(3);
+        CTIS_PLAN_HOST_ONLY | CTIS_PLAN_KEEP_ZEROS | CTIS_PLAN_TILE_PATH | CTIS_PLAN_BOX(0xF) | CTIS_PLAN_REGION(7);
     if (flags & ~known) return fail(CTIS_E_ARG, "unknown flag bits");
+    const int shape = (int)((flags >> 12) & 0x7u);
+    if (shape > kRegionShapes) return fail(CTIS_E_ARG, "region shape code must be in 0..6");
     const int forced_box = (int)((flags >> 8) & 0xFu);
     if (forced_box > kMaxBox) return fail(CTIS_E_ARG, "forced box side must be in 1..8");
     if (a < 1 || alpha < 1 || w < 1 || gamma < 1 || xi < 1)
@@ -216,9 +218,8 @@ ctis_status ctis_plan_create(ctis_plan **out, int32_t a, int32_t alpha, int32_t 
     p->m = m;
     ctis_status st;
     try {
-        const int shape = (int)((flags >> 12) & 0x3u);   // CTIS_PLAN_REGION: 1 -> 8 x 32, 2 -> 16 x 16, 3 -> 32 x 8
         st = build_host_tables(p, lambda_ptr, fpa_index, value, forced_box, (flags & CTIS_PLAN_KEEP_ZEROS) != 0,
-                               shape ? 1 << shape : 0);
+                               shape);
     } catch (const std::bad_alloc &) {
         st = fail(CTIS_E_NOMEM, "host allocation while building the plan");
     }
@@ -315,7 +316,7 @@ ctis_status ctis_plan_get_info(const ctis_plan *p, ctis_plan_info *info) {
     const int64_t BB = (int64_t)T.B * T.B;
     info->method_madds = p->ell * T.nnz;
     info->tile_forward_madds = (int64_t)T.tiles.item_box.size() * kTileFast * kTileSlow * BB;
-    info->region_forward_madds = (int64_t)T.regions.item_box.size() * kRegionPixels * BB;
+    info->region_forward_madds = (int64_t)T.regions.item_box.size() * T.regions.tf * T.regions.ts * BB;
     info->adjoint_madds = (int64_t)T.nbx * T.nby * kTileFast * kTileSlow * (int64_t)T.box_lambda.size() * BB;
     info->workspace_bytes = p->workspace_bytes;
     info->nonnegative = p->ht.nonneg ? 1 : 0;

@@ -21,24 +21,32 @@ namespace ctis {
 // micro-tile per lane (16 lanes x 4 lanes).
 constexpr int kTileFast = 64;
 constexpr int kTileSlow = 16;
-// Regions of the region forward projection (the EM path): a group of 16
-// lanes covers 256 FPA pixels, gx x (16 / gx) lanes with a 4 x 4 micro-tile
-// each, i.e. (4 gx) x (64 / gx) pixels along gamma x xi; four groups per
-// wavefront, each on another box.  gx is 2, 4 or 8 (8 x 32, 16 x 16, 32 x 8).
-constexpr int kRegionPixels = 256;
+// Regions of the region forward projection (the EM path): a group of gl
+// lanes covers 16 gl FPA pixels, gx x (gl / gx) lanes with a 4 x 4
+// micro-tile each, i.e. (4 gx) x (4 gl / gx) pixels along gamma x xi; 64 / gl
+// groups per wavefront, each on another box.  Shapes by code (the
+// CTIS_PLAN_REGION value): 1 = 8 x 32, 2 = 16 x 16, 3 = 32 x 8 (gl = 16),
+// 4 = 16 x 8, 5 = 8 x 16 (gl = 8), 6 = 8 x 8 (gl = 4).  Smaller regions
+// follow the edges of the box images more closely (fewer multiply-adds on
+// the zero border) at more set-up per output.
+constexpr int kRegionPixels = 256;   // the largest region: a partial region slot
+constexpr int kRegionShapes = 6;
+constexpr int kDefaultRegionShape = 2;
 constexpr int kFwdMaxWaves = 8;
 constexpr int kMaxBox = 8;
 // Work records of windows that run inside the FPA without wrapping carry
 // this flag (tile forward: in the f-offset field; back projection: the third
 // field is 1): the kernels then take scalar row offsets.
 constexpr int kDirectFlag = 1 << 30;
-constexpr int region_fast(int gx) { return 4 * gx; }
-constexpr int region_slow(int gx) { return 64 / gx; }
+constexpr int region_gx(int shape) { return shape == 3 ? 8 : (shape == 2 || shape == 4) ? 4 : 2; }
+constexpr int region_gl(int shape) { return shape <= 3 ? 16 : shape <= 5 ? 8 : 4; }
+constexpr int region_fast(int shape) { return 4 * region_gx(shape); }
+constexpr int region_slow(int shape) { return 4 * region_gl(shape) / region_gx(shape); }
 // Zero border of the padded copy of f the region forward reads, per axis: a
 // window of a region (region + B - 1 slots per side) that meets the field
 // stop lies inside [-hx, a + hx) x [-hy, alpha + hy).
-constexpr int halo_fast(int gx, int B) { return region_fast(gx) + B - 2; }
-constexpr int halo_slow(int gx, int B) { return region_slow(gx) + B - 2; }
+constexpr int halo_fast(int shape, int B) { return region_fast(shape) + B - 2; }
+constexpr int halo_slow(int shape, int B) { return region_slow(shape) + B - 2; }
 // 32-bit buffer offsets (in bytes) address the FPA, a wavelength block and
 // the whole f buffer (and its padded copy) of a plan or batch
 constexpr int64_t kMaxPixels = (int64_t(1) << 29) - 1;
@@ -99,7 +107,7 @@ struct DevWork {
     // region forward of the EM path (when pad_ok): regions with boxes, heavy
     // regions split; reads the padded copy of f in the workspace
     bool pad_ok = false;
-    int32_t region_gx = 4;       // region shape (lanes of a group along gamma)
+    int32_t region_shape = kDefaultRegionShape;   // region shape code (region_fast x region_slow)
     int32_t halo_x = 0, halo_y = 0;   // zero border of the padded copy
     DevList fwd_pad;
     const int4 *rsplit_meta = nullptr;
@@ -143,7 +151,7 @@ struct HostWork {
     std::vector<int32_t> split_meta, rsplit_meta, pad_blocks;
     int32_t n_split = 0, partial_slots = 0, n_rsplit = 0, rpartial_slots = 0;
     bool pad_ok = false;
-    int32_t region_gx = 4, halo_x = 0, halo_y = 0;
+    int32_t region_shape = kDefaultRegionShape, halo_x = 0, halo_y = 0;
     int64_t fp_floats = 0;       // padded copy of f (all frames)
     int32_t pad_rows = 0;
     std::vector<float> box_w, box_wf, h;
@@ -184,7 +192,7 @@ struct HostTables {
     std::vector<float> box_w, box_wf, h;
     WorkGrid tiles;              // 64 x 16 FPA tiles (plain projection, tile EM path)
     WorkGrid regions;            // FPA regions of the region EM path
-    int32_t region_gx = 4;       // their shape: region_fast(gx) x region_slow(gx)
+    int32_t region_shape = kDefaultRegionShape;   // their shape code: region_fast x region_slow
     // the region path reads f through a zero-bordered copy; exact when the
     // FPA leaves halo_fast / halo_slow pixels beside the field stop
     bool pad_ok = false;
@@ -238,7 +246,7 @@ ctis_status refresh_host_tables(const ctis_plan *p);
 
 // host plan builder (plan.cpp)
 ctis_status build_host_tables(ctis_plan *p, const int64_t *lambda_ptr, const int32_t *fpa_index,
-                              const float *value, int forced_box, bool keep_zeros, int region_gx);
+                              const float *value, int forced_box, bool keep_zeros, int region_shape);
 
 // One frame of a work description: its plan and buffer offsets (floats).
 struct FrameRef {

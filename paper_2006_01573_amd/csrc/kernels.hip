@@ -605,16 +605,17 @@ __global__ void __launch_bounds__(256) k_finish_split(const int4 *__restrict__ s
 }
 
 // ---------------------------------------------------------------------------
-// Region forward projection (the EM path).  A wavefront is four groups of 16
-// lanes.  A group owns an FPA region of 256 pixels, (4 GX) x (4 GY) with
-// GX * GY = 16 (GX x GY lanes with a 4 x 4 register micro-tile each), and
-// takes one box of the region's work list at a time, so the four groups of a
-// wave correlate four different boxes with the same region at once, and the
-// waves of a workgroup split the region's boxes.  At the end the groups are
-// summed with a fixed butterfly and the waves in LDS in a fixed order
-// (deterministic results).  The small region keeps the outputs computed per
-// box close to the box's shifted field-stop image: a larger output tile
-// spends its multiply-adds on the overhang, where the window holds zeros.
+// Region forward projection (the EM path).  A wavefront is G = 64 / GL
+// groups of GL lanes (GL = 16, 8 or 4 by region shape SH).  A group owns an
+// FPA region of 16 GL pixels, (4 GX) x (4 GY) with GX * GY = GL (GX x GY
+// lanes with a 4 x 4 register micro-tile each), and takes one box of the
+// region's work list at a time, so the G groups of a wave correlate G
+// different boxes with the same region at once, and the waves of a
+// workgroup split the region's boxes.  At the end the groups are summed with
+// a fixed butterfly and the waves in LDS in a fixed order (deterministic
+// results).  The small region keeps the outputs computed per box close to
+// the box's shifted field-stop image: a larger output tile spends its
+// multiply-adds on the overhang, where the window holds zeros.
 //
 // The windows come from a zero-bordered copy of f (per wavelength a block of
 // (a + 2 Hx) x (alpha + 2 Hy) floats, Hx = 4 GX + B - 2, Hy = 4 GY + B - 2,
@@ -623,14 +624,13 @@ __global__ void __launch_bounds__(256) k_finish_split(const int4 *__restrict__ s
 // 2-D rectangle of it, read in 16-byte pieces with no field-stop test and no
 // wrap arithmetic (exact when the FPA leaves Hx and Hy pixels beside the
 // field stop; the tile kernel serves other plans).
-constexpr int kRegion = 256;
-constexpr int kGroups = 4;
-constexpr int kGroupLanes = 64 / kGroups;
-
-template <int B, int GX>
+template <int B, int SH>
 struct RWin {
-    static constexpr int GY = kGroupLanes / GX;
+    static constexpr int GX = region_gx(SH), GL = region_gl(SH);
+    static constexpr int GROUPS = 64 / GL;         // lane groups per wavefront
+    static constexpr int GY = GL / GX;
     static constexpr int RX = 4 * GX, RY = 4 * GY;  // region (fast x slow)
+    static constexpr int NPIX = RX * RY;           // outputs of a region
     static constexpr int SX = RX + B - 1;          // window extent, fast axis
     static constexpr int SX4 = (SX + 3) / 4;       // 16-byte pieces per window row
     static constexpr int SXP = 4 * SX4;            // LDS row pitch
@@ -638,25 +638,28 @@ struct RWin {
     static constexpr int REG = SXP * SY;           // window floats per group
     static constexpr int BB = B * B;
     static constexpr int GREG = REG + ((BB + 3) & ~3);   // window + box values
-    static constexpr int WAVE = kGroups * GREG;    // LDS floats per wavefront
+    static constexpr int WAVE = GROUPS * GREG;     // LDS floats per wavefront
     static constexpr int NSLOT = SX4 * SY;         // 16-byte pieces per window
-    static constexpr int NT = (NSLOT + kGroupLanes - 1) / kGroupLanes;
-    static constexpr int NWT = (BB + kGroupLanes - 1) / kGroupLanes;
+    static constexpr int NT = (NSLOT + GL - 1) / GL;
+    static constexpr int NWT = (BB + GL - 1) / GL;
     static constexpr int MAXW = kFwdMaxWaves;
-    static_assert(RX * RY == kRegion && kGroupLanes % GX == 0, "a group covers 256 pixels");
-    static_assert(WAVE >= kRegion, "the reduction parks 256 floats per wave");
+    static_assert(SH >= 1 && SH <= kRegionShapes, "region shape code");
+    static_assert(GL % GX == 0 && 64 % GL == 0 && GROUPS >= 4, "whole groups, at least four per wave");
+    static_assert(NPIX == 16 * GL && NPIX <= kRegionPixels, "a group covers 16 GL pixels");
+    static_assert(RX == region_fast(SH) && RY == region_slow(SH), "the host's region shape");
+    static_assert(WAVE >= NPIX, "the reduction parks a region per wave");
     static_assert(REG % 4 == 0 && GREG % 4 == 0, "16-byte aligned group regions");
     static_assert(4 * (GX - 1) + 4 * ((4 + B - 1 + 3) / 4) <= SXP, "segment reads stay inside the row");
-    static_assert(halo_fast(GX, B) >= SX - 1 && halo_slow(GX, B) >= SY - 1,
+    static_assert(halo_fast(SH, B) >= SX - 1 && halo_slow(SH, B) >= SY - 1,
                   "a window meeting the field stop stays inside the padded block");
 };
 
 // One window in flight per group lane, in registers: its 16-byte pieces of
 // the window and its share of the box's values.
-template <int B, int GX>
+template <int B, int SH>
 struct RPend {
-    float4 v[RWin<B, GX>::NT];
-    float wt[RWin<B, GX>::NWT];
+    float4 v[RWin<B, SH>::NT];
+    float wt[RWin<B, SH>::NWT];
 };
 
 
@@ -666,54 +669,54 @@ struct RPend {
 // whose load is then not stored); box < 0 (an empty slot) reads zeros (the
 // out-of-range offset).  A piece may run up to three floats past the
 // window's last column (LDS pitch padding, never used).
-template <int B, int GX>
-__device__ __forceinline__ void load_region(RPend<B, GX> &pd, __amdgpu_buffer_rsrc_t fr, __amdgpu_buffer_rsrc_t wr,
-                                            int4 rec, int gl, const unsigned (&poff)[RWin<B, GX>::NT]) {
-    using Wn = RWin<B, GX>;
+template <int B, int SH>
+__device__ __forceinline__ void load_region(RPend<B, SH> &pd, __amdgpu_buffer_rsrc_t fr, __amdgpu_buffer_rsrc_t wr,
+                                            int4 rec, int gl, const unsigned (&poff)[RWin<B, SH>::NT]) {
+    using Wn = RWin<B, SH>;
     const bool ok = rec.w >= 0;
     const unsigned base = ok ? 4u * (unsigned)rec.x : kOutOfRange;
 #pragma unroll
     for (int t = 0; t < Wn::NT; ++t) pd.v[t] = bload4(fr, base + poff[t]);
 #pragma unroll
     for (int t = 0; t < Wn::NWT; ++t) {
-        const int k = gl + kGroupLanes * t;
+        const int k = gl + Wn::GL * t;
         pd.wt[t] = bload(wr, (ok && k < Wn::BB) ? 4u * (unsigned)(rec.w * Wn::BB + k) : kOutOfRange);
     }
 }
 
 // Window into S[0, REG), box values into S[REG, REG + B*B).  Piece k (row
 // k / SX4, column quad k % SX4) lands at float 4k: the row pitch is 4 SX4.
-template <int B, int GX>
-__device__ __forceinline__ void store_region(float *S, const RPend<B, GX> &pd, int gl) {
-    using Wn = RWin<B, GX>;
+template <int B, int SH>
+__device__ __forceinline__ void store_region(float *S, const RPend<B, SH> &pd, int gl) {
+    using Wn = RWin<B, SH>;
     static_assert(Wn::SXP == 4 * Wn::SX4, "pieces are packed row after row");
 #pragma unroll
     for (int t = 0; t < Wn::NT; ++t) {
-        const int k = gl + kGroupLanes * t;
+        const int k = gl + Wn::GL * t;
         if (t + 1 < Wn::NT || k < Wn::NSLOT) *reinterpret_cast<float4 *>(S + 4 * k) = pd.v[t];
     }
 #pragma unroll
     for (int t = 0; t < Wn::NWT; ++t) {
-        const int k = gl + kGroupLanes * t;
+        const int k = gl + Wn::GL * t;
         if (k < Wn::BB) S[Wn::REG + k] = pd.wt[t];
     }
 }
 
 // Byte offset, from the window origin in the padded copy (row pitch P
-// floats), of piece t of group lane gl: piece k = gl + 16 t sits at row
+// floats), of piece t of group lane gl: piece k = gl + GL t sits at row
 // k / SX4, column quad k % SX4, found from gl's own row and column by a
 // compile-time step and one carry; 0 for a lane without a piece t.
-template <int B, int GX>
-__device__ __forceinline__ void region_piece_offsets(unsigned int (&poff)[RWin<B, GX>::NT], int gl, int P) {
-    using Wn = RWin<B, GX>;
+template <int B, int SH>
+__device__ __forceinline__ void region_piece_offsets(unsigned int (&poff)[RWin<B, SH>::NT], int gl, int P) {
+    using Wn = RWin<B, SH>;
     const int row0 = gl / Wn::SX4, col0 = gl - row0 * Wn::SX4;
     const unsigned prow = 4u * (unsigned)P;
 #pragma unroll
     for (int t = 0; t < Wn::NT; ++t) {
-        const int dr = (kGroupLanes * t) / Wn::SX4, dc = (kGroupLanes * t) % Wn::SX4;
+        const int dr = (Wn::GL * t) / Wn::SX4, dc = (Wn::GL * t) % Wn::SX4;
         const bool carry = col0 + dc >= Wn::SX4;
         const int row = row0 + dr + (carry ? 1 : 0), col = col0 + dc - (carry ? Wn::SX4 : 0);
-        poff[t] = gl + kGroupLanes * t < Wn::NSLOT ? 16u * (unsigned)col + prow * (unsigned)row : 0u;
+        poff[t] = gl + Wn::GL * t < Wn::NSLOT ? 16u * (unsigned)col + prow * (unsigned)row : 0u;
     }
 }
 
@@ -721,26 +724,27 @@ __device__ __forceinline__ void region_piece_offsets(unsigned int (&poff)[RWin<B
 // chunk of the boxes meeting one FPA region of one frame (meta as the tile
 // list's, with the padded block's row pitch P in the third record).  A region
 // split into several units writes one partial region per unit to
-// `partials`; k_finish_regions sums them (next launch on the stream).
-template <int B, int GX>
+// `partials` (slots of kRegionPixels floats); k_finish_regions sums them
+// (next launch on the stream).
+template <int B, int SH>
 __global__ void __launch_bounds__(64 * kFwdMaxWaves) k_forward_region(
     const int4 *__restrict__ meta, const int4 *__restrict__ items, const int stride, const int n_units,
     const float *__restrict__ box_wf, const int n_wf, const float *__restrict__ fp, const int fp_floats,
     const float *__restrict__ g, const float *__restrict__ uaux, float *__restrict__ out,
     float *__restrict__ partials, const int mode) {
-    using Wn = RWin<B, GX>;
-    constexpr int RX = Wn::RX;
+    using Wn = RWin<B, SH>;
+    constexpr int RX = Wn::RX, GL = Wn::GL, NG = Wn::GROUPS, NPIX = Wn::NPIX;
     extern __shared__ float4 lds4[];
     float *lds = reinterpret_cast<float *>(lds4);
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nw = blockDim.x >> 6;
-    const int gi = lane >> 4, gl = lane & 15, lx = gl % GX, ly = gl / GX;
+    const int gi = lane / GL, gl = lane % GL, lx = gl % Wn::GX, ly = gl / Wn::GX;
     float *S = lds + wv * Wn::WAVE + gi * Wn::GREG;
     const __amdgpu_buffer_rsrc_t fr = rsrc(fp, fp_floats);
     const __amdgpu_buffer_rsrc_t wr = rsrc(box_wf, n_wf);
     const int tid = threadIdx.x, nt = blockDim.x;
-    constexpr int kOut = kRegion / 64;   // outputs per thread at one wave per workgroup
+    constexpr int kOut = NPIX / 64;   // outputs per thread at one wave per workgroup
 
     for (int unit = blockIdx.x; unit < n_units; unit += gridDim.x) {
         const int4 *list = items + (size_t)unit * stride;
@@ -750,9 +754,9 @@ __global__ void __launch_bounds__(64 * kFwdMaxWaves) k_forward_region(
         const bool whole = m0.z == 1;
         // byte offsets of this lane's window pieces from the window origin
         unsigned poff[Wn::NT];
-        region_piece_offsets<B, GX>(poff, gl, m2.z);
-        const int step = kGroups * nw;
-        int k = kGroups * wv + gi;
+        region_piece_offsets<B, SH>(poff, gl, m2.z);
+        const int step = NG * nw;
+        int k = NG * wv + gi;
         int4 rec0 = record(list, k, stride);
         int4 rec1 = record(list, k + step, stride);
 
@@ -767,7 +771,7 @@ __global__ void __launch_bounds__(64 * kFwdMaxWaves) k_forward_region(
             for (int j = 0; j < kOut; ++j) {
                 const int o = tid + nt * j;
                 const int r = r0 + o % RX, c = c0 + o / RX;
-                const bool in = o < kRegion && mode != kFwdPlain && whole && r < gamma && c < xi;
+                const bool in = o < NPIX && mode != kFwdPlain && whole && r < gamma && c < xi;
                 const size_t i = (size_t)r + (size_t)gamma * c;
                 gpre[j] = in ? g[(size_t)m2.x + i] : 0.0f;
                 upre[j] = (in && fwd_aux(mode)) ? uaux[fwd_aux_off(mode, m2.x, m2.y) + i] : 0.0f;
@@ -782,19 +786,19 @@ __global__ void __launch_bounds__(64 * kFwdMaxWaves) k_forward_region(
             for (int q = 0; q < 4; ++q) acc[a][q] = 0.0f;
 
         // one window in flight per group: while the groups correlate their
-        // items, the windows of the wave's next four items are fetched (an
+        // items, the windows of the wave's next NG items are fetched (an
         // empty record reads zeros); the work records run one pass further
         // ahead.  Lists are padded with empty records, so a wave is done once
         // its first group has none.
-        RPend<B, GX> pa;
-        load_region<B, GX>(pa, fr, wr, rec0, gl, poff);
+        RPend<B, SH> pa;
+        load_region<B, SH>(pa, fr, wr, rec0, gl, poff);
         if (__builtin_amdgcn_readfirstlane(rec0.w) >= 0) {
             do {
-                store_region<B, GX>(S, pa, gl);
+                store_region<B, SH>(S, pa, gl);
                 wave_lds_sync();
                 k += step;
                 const int4 rec3 = record(list, k + step, stride);
-                load_region<B, GX>(pa, fr, wr, rec1, gl, poff);
+                load_region<B, SH>(pa, fr, wr, rec1, gl, poff);
                 correlate<B, Wn::SXP, Wn::REG>(acc, S, lx, ly);
                 wave_lds_sync();
                 rec0 = rec1;
@@ -804,21 +808,22 @@ __global__ void __launch_bounds__(64 * kFwdMaxWaves) k_forward_region(
 
         if (!kEarly) fetch_operands();   // while the groups and waves are summed
 
-        // sum of the four groups (lanes l, l^16, l^32 and l^48 hold the same
-        // outputs): every group gets ((g0 + g1) + (g2 + g3))
+        // sum of the groups (lanes l, l ^ GL, l ^ 2 GL, ... hold the same
+        // outputs): a butterfly over the group index, every group ends with
+        // the same sum (for four groups ((g0 + g1) + (g2 + g3)))
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 float v = acc[a][q];
-                v += __shfl_xor(v, 16, 64);
-                v += __shfl_xor(v, 32, 64);
+#pragma unroll
+                for (int off = GL; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
                 acc[a][q] = v;
             }
-        // park the wave's region in LDS (group gi stores row gi of its
+        // park the wave's region in LDS (group gi < 4 stores row gi of its
         // lanes' micro-tiles), then sum the waves in order
         __syncthreads();   // every wave is done with its windows
-        {
+        if (gi < 4) {
             float4 row = make_float4(acc[0][0], acc[0][1], acc[0][2], acc[0][3]);
 #pragma unroll
             for (int a = 1; a < 4; ++a)
@@ -829,11 +834,11 @@ __global__ void __launch_bounds__(64 * kFwdMaxWaves) k_forward_region(
 #pragma unroll
         for (int j = 0; j < kOut; ++j) {
             const int o = tid + nt * j;
-            if (o >= kRegion) continue;
+            if (o >= NPIX) continue;
             float v = 0.0f;
             for (int w2 = 0; w2 < nw; ++w2) v += lds[w2 * Wn::WAVE + o];
             if (!whole) {
-                partials[(size_t)m0.w * kRegion + o] = v;
+                partials[(size_t)m0.w * kRegionPixels + o] = v;
             } else {
                 const int r = r0 + o % RX, c = c0 + o / RX;
                 if (r < gamma && c < xi)
@@ -844,44 +849,45 @@ __global__ void __launch_bounds__(64 * kFwdMaxWaves) k_forward_region(
     }
 }
 
-// Solo region forward: every group of 16 lanes owns a whole unit (one FPA
+// Solo region forward: every group of GL lanes owns a whole unit (one FPA
 // region, or one chunk of a split region) and walks all of its boxes, so a
-// wavefront advances four units side by side (neighbours in the work-sorted
-// unit list, so of about equal length; a group whose list has ended loads
-// zeros); no cross-group or cross-wave reduction, no workgroup barrier, each
-// group parks its region in its window area and writes it row by row.  For
-// batches of many short regions, where the cooperative kernel's set-up and
-// reductions outweigh a unit's few passes.
-template <int B, int GX>
+// wavefront advances 64 / GL units side by side (neighbours in the
+// work-sorted unit list, so of about equal length; a group whose list has
+// ended loads zeros); no cross-group or cross-wave reduction, no workgroup
+// barrier, each group parks its region in its window area and writes it row
+// by row.  For batches of many short regions, where the cooperative
+// kernel's set-up and reductions outweigh a unit's few passes.
+template <int B, int SH>
 __global__ void __launch_bounds__(64 * kSoloWaves) k_forward_region_solo(
     const int4 *__restrict__ meta, const int4 *__restrict__ items, const int stride, const int n_units,
     const float *__restrict__ box_wf, const int n_wf, const float *__restrict__ fp, const int fp_floats,
     const float *__restrict__ g, const float *__restrict__ uaux, float *__restrict__ out,
     float *__restrict__ partials, const int mode) {
-    using Wn = RWin<B, GX>;
-    constexpr int RX = Wn::RX;
+    using Wn = RWin<B, SH>;
+    constexpr int RX = Wn::RX, GL = Wn::GL, NG = Wn::GROUPS, NPIX = Wn::NPIX;
+    static_assert(Wn::REG >= NPIX, "a group parks its region in its window area");
     extern __shared__ float4 lds4[];
     float *lds = reinterpret_cast<float *>(lds4);
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nw = blockDim.x >> 6;
-    const int gi = lane >> 4, gl = lane & 15, lx = gl % GX, ly = gl / GX;
+    const int gi = lane / GL, gl = lane % GL, lx = gl % Wn::GX, ly = gl / Wn::GX;
     float *S = lds + wv * Wn::WAVE + gi * Wn::GREG;
     const __amdgpu_buffer_rsrc_t fr = rsrc(fp, fp_floats);
     const __amdgpu_buffer_rsrc_t wr = rsrc(box_wf, n_wf);
 
-    const int nv = solo_groups(n_units, nw * kGroups);
+    const int nv = solo_groups(n_units, nw * NG);
     for (int v = blockIdx.x; v < nv; v += gridDim.x) {
-        const int first = solo_unit(v, wv * kGroups, nw * kGroups);
-        if (first >= n_units) continue;   // so are the wave's other three
-        const int unit = solo_unit(v, wv * kGroups + gi, nw * kGroups);
+        const int first = solo_unit(v, wv * NG, nw * NG);
+        if (first >= n_units) continue;   // so are the wave's other groups
+        const int unit = solo_unit(v, wv * NG + gi, nw * NG);
         const bool active = unit < n_units;
         const int u = active ? unit : first;   // a valid unit for the loads; its results are dropped
         const int4 *list = items + (size_t)u * stride;
         const int4 m0 = meta[3 * u], m1 = meta[3 * u + 1], m2 = meta[3 * u + 2];
         const int gamma = m1.z, xi = m1.w;
         unsigned poff[Wn::NT];
-        region_piece_offsets<B, GX>(poff, gl, m2.z);
+        region_piece_offsets<B, SH>(poff, gl, m2.z);
         const int kend = active ? stride : 0;   // an inactive group reads empty records
         float acc[4][4];
 #pragma unroll
@@ -892,21 +898,21 @@ __global__ void __launch_bounds__(64 * kSoloWaves) k_forward_region_solo(
         int k = 0;
         int4 rec0 = record(list, k, kend);
         int4 rec1 = record(list, k + 1, kend);
-        RPend<B, GX> pa;
-        load_region<B, GX>(pa, fr, wr, rec0, gl, poff);
+        RPend<B, SH> pa;
+        load_region<B, SH>(pa, fr, wr, rec0, gl, poff);
         while (__builtin_amdgcn_ballot_w64(rec0.w >= 0) != 0) {
-            store_region<B, GX>(S, pa, gl);
+            store_region<B, SH>(S, pa, gl);
             wave_lds_sync();
             k += 1;
             const int4 rec3 = record(list, k + 1, kend);
-            load_region<B, GX>(pa, fr, wr, rec1, gl, poff);
+            load_region<B, SH>(pa, fr, wr, rec1, gl, poff);
             correlate<B, Wn::SXP, Wn::REG>(acc, S, lx, ly);
             wave_lds_sync();
             rec0 = rec1;
             rec1 = rec3;
         }
         // the group's region, parked row-major in its window area, leaves
-        // row by row (contiguous stores of 16 lanes)
+        // row by row (contiguous stores of the group's lanes)
 #pragma unroll
         for (int kq = 0; kq < 4; ++kq)
             *reinterpret_cast<float4 *>(S + (4 * ly + kq) * RX + 4 * lx) =
@@ -916,11 +922,11 @@ __global__ void __launch_bounds__(64 * kSoloWaves) k_forward_region_solo(
             const int r0 = m0.x, c0 = m0.y;
             const bool whole = m0.z == 1;
 #pragma unroll
-            for (int j = 0; j < kRegion / kGroupLanes; ++j) {
-                const int o = gl + kGroupLanes * j;
+            for (int j = 0; j < NPIX / GL; ++j) {
+                const int o = gl + GL * j;
                 const float v = S[o];
                 if (!whole) {   // a chunk of a split region: its partial region
-                    partials[(size_t)m0.w * kRegion + o] = v;
+                    partials[(size_t)m0.w * kRegionPixels + o] = v;
                     continue;
                 }
                 const int r = r0 + o % RX, c = c0 + o / RX;
@@ -936,15 +942,16 @@ __global__ void __launch_bounds__(64 * kSoloWaves) k_forward_region_solo(
     }
 }
 
-// Sum the partial regions (rx pixels wide) of every split FPA region in
-// chunk order and apply the forward epilogue.  One workgroup (a thread per
-// output) per split region.
-__global__ void __launch_bounds__(kRegion) k_finish_regions(const int4 *__restrict__ split_meta,
-                                                            const float *__restrict__ partials,
-                                                            const float *__restrict__ g,
-                                                            const float *__restrict__ uaux, float *__restrict__ out,
-                                                            int mode, int rx) {
+// Sum the partial regions (rx x ry pixels, slots of kRegionPixels floats) of
+// every split FPA region in chunk order and apply the forward epilogue.  One
+// workgroup (a thread per slot float) per split region.
+__global__ void __launch_bounds__(kRegionPixels) k_finish_regions(const int4 *__restrict__ split_meta,
+                                                                  const float *__restrict__ partials,
+                                                                  const float *__restrict__ g,
+                                                                  const float *__restrict__ uaux,
+                                                                  float *__restrict__ out, int mode, int rx, int ry) {
     const int o = threadIdx.x;
+    if (o >= rx * ry) return;
     const int4 s0 = split_meta[2 * blockIdx.x], s1 = split_meta[2 * blockIdx.x + 1];
     const int r = s0.x + o % rx, c = s0.y + o / rx;
     if (r >= s1.x || c >= s1.y) return;
@@ -952,7 +959,7 @@ __global__ void __launch_bounds__(kRegion) k_finish_regions(const int4 *__restri
     const float gv = mode != kFwdPlain ? g[(size_t)s1.z + i] : 0.0f;
     const float uv = fwd_aux(mode) ? uaux[fwd_aux_off(mode, s1.z, s1.w) + i] : 0.0f;
     float v = 0.0f;
-    for (int ch = 0; ch < s0.z; ++ch) v += partials[((size_t)s0.w + ch) * kRegion + o];
+    for (int ch = 0; ch < s0.z; ++ch) v += partials[((size_t)s0.w + ch) * kRegionPixels + o];
     out[(size_t)s1.w + i] = fwd_epilogue(mode, v, gv, uv);
 }
 
@@ -1738,51 +1745,59 @@ int forward_B(const DevWork &w, const float *x, const float *g, const float *u, 
     return (int)hipGetLastError();
 }
 
-template <int B, int GX>
+template <int B, int SH>
 int forward_region_B(const DevWork &w, const float *g, const float *u, float *out, int mode, void *workspace,
                      hipStream_t st) {
+    using Wn = RWin<B, SH>;
     const DevList &L = w.fwd_pad;
     if (L.n_units == 0) return 0;
-    const size_t lds = (size_t)L.waves * RWin<B, GX>::WAVE * sizeof(float);
-    if (!w.region_solo && lds > 65536) {
+    const int waves = w.region_solo ? kSoloWaves : L.waves;
+    const size_t lds = (size_t)waves * Wn::WAVE * sizeof(float);
+    if (lds > 65536) {   // both kernels may ask for more than 64 KiB of LDS (small regions, large B)
         static std::once_flag once;
         static hipError_t err = hipSuccess;
         std::call_once(once, []() {
-            err = hipFuncSetAttribute((const void *)k_forward_region<B, GX>,
+            err = hipFuncSetAttribute((const void *)k_forward_region<B, SH>,
                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      RWin<B, GX>::MAXW * RWin<B, GX>::WAVE * (int)sizeof(float));
+                                      Wn::MAXW * Wn::WAVE * (int)sizeof(float));
+            if (err == hipSuccess)
+                err = hipFuncSetAttribute((const void *)k_forward_region_solo<B, SH>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize,
+                                          kSoloWaves * Wn::WAVE * (int)sizeof(float));
         });
         if (err != hipSuccess) return (int)err;
     }
     const float *fp = (const float *)((const char *)workspace + w.fp_off);
     float *partials = w.n_rsplit > 0 ? (float *)((char *)workspace + w.rpartials_off) : nullptr;
-    if (w.region_solo) {   // a lane group per unit, four units per wave
-        const size_t slds = (size_t)kSoloWaves * RWin<B, GX>::WAVE * sizeof(float);
-        const int groups = solo_groups(L.n_units, kGroups * kSoloWaves);
-        hipLaunchKernelGGL((k_forward_region_solo<B, GX>), dim3(grid_for(groups, slds, kSoloWaves, w.persistent)),
-                           dim3(64 * kSoloWaves), slds, st, L.meta, L.items, L.stride, L.n_units, w.box_wf, w.n_wf,
+    if (w.region_solo) {   // a lane group per unit, 64 / GL units per wave
+        const int groups = solo_groups(L.n_units, Wn::GROUPS * kSoloWaves);
+        hipLaunchKernelGGL((k_forward_region_solo<B, SH>), dim3(grid_for(groups, lds, kSoloWaves, w.persistent)),
+                           dim3(64 * kSoloWaves), lds, st, L.meta, L.items, L.stride, L.n_units, w.box_wf, w.n_wf,
                            fp, w.fp_floats, g, u, out, partials, mode);
     } else {
-        hipLaunchKernelGGL((k_forward_region<B, GX>), dim3(grid_for(L.n_units, lds, L.waves, w.persistent)),
+        hipLaunchKernelGGL((k_forward_region<B, SH>), dim3(grid_for(L.n_units, lds, L.waves, w.persistent)),
                            dim3(64 * L.waves), lds, st, L.meta, L.items, L.stride, L.n_units, w.box_wf, w.n_wf, fp,
                            w.fp_floats, g, u, out, partials, mode);
     }
     if (partials) {
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return (int)e;
-        hipLaunchKernelGGL(k_finish_regions, dim3(w.n_rsplit), dim3(kRegion), 0, st, w.rsplit_meta,
-                           (const float *)partials, g, u, out, mode, RWin<B, GX>::RX);
+        hipLaunchKernelGGL(k_finish_regions, dim3(w.n_rsplit), dim3(kRegionPixels), 0, st, w.rsplit_meta,
+                           (const float *)partials, g, u, out, mode, Wn::RX, Wn::RY);
     }
     return (int)hipGetLastError();
 }
 
 template <int B>
-int forward_region_gx(const DevWork &w, const float *g, const float *u, float *out, int mode, void *workspace,
-                      hipStream_t st) {
-    switch (w.region_gx) {
+int forward_region_shape(const DevWork &w, const float *g, const float *u, float *out, int mode, void *workspace,
+                         hipStream_t st) {
+    switch (w.region_shape) {
+        case 1: return forward_region_B<B, 1>(w, g, u, out, mode, workspace, st);
         case 2: return forward_region_B<B, 2>(w, g, u, out, mode, workspace, st);
+        case 3: return forward_region_B<B, 3>(w, g, u, out, mode, workspace, st);
         case 4: return forward_region_B<B, 4>(w, g, u, out, mode, workspace, st);
-        case 8: return forward_region_B<B, 8>(w, g, u, out, mode, workspace, st);
+        case 5: return forward_region_B<B, 5>(w, g, u, out, mode, workspace, st);
+        case 6: return forward_region_B<B, 6>(w, g, u, out, mode, workspace, st);
     }
     return (int)hipErrorInvalidValue;
 }
@@ -1883,14 +1898,14 @@ int launch_forward_pad(const DevWork &w, const float *g, const float *u, float *
     if (!w.pad_ok) return (int)hipErrorInvalidValue;
     hipStream_t st = (hipStream_t)stream;
     switch (w.B) {
-        case 1: return forward_region_gx<1>(w, g, u, out, mode, workspace, st);
-        case 2: return forward_region_gx<2>(w, g, u, out, mode, workspace, st);
-        case 3: return forward_region_gx<3>(w, g, u, out, mode, workspace, st);
-        case 4: return forward_region_gx<4>(w, g, u, out, mode, workspace, st);
-        case 5: return forward_region_gx<5>(w, g, u, out, mode, workspace, st);
-        case 6: return forward_region_gx<6>(w, g, u, out, mode, workspace, st);
-        case 7: return forward_region_gx<7>(w, g, u, out, mode, workspace, st);
-        case 8: return forward_region_gx<8>(w, g, u, out, mode, workspace, st);
+        case 1: return forward_region_shape<1>(w, g, u, out, mode, workspace, st);
+        case 2: return forward_region_shape<2>(w, g, u, out, mode, workspace, st);
+        case 3: return forward_region_shape<3>(w, g, u, out, mode, workspace, st);
+        case 4: return forward_region_shape<4>(w, g, u, out, mode, workspace, st);
+        case 5: return forward_region_shape<5>(w, g, u, out, mode, workspace, st);
+        case 6: return forward_region_shape<6>(w, g, u, out, mode, workspace, st);
+        case 7: return forward_region_shape<7>(w, g, u, out, mode, workspace, st);
+        case 8: return forward_region_shape<8>(w, g, u, out, mode, workspace, st);
     }
     return (int)hipErrorInvalidValue;
 }

@@ -198,7 +198,7 @@ ctis_status build_grid(HostTables &T, const ctis_plan *p, int32_t tf, int32_t ts
 }
 
 ctis_status build_host_tables(ctis_plan *p, const int64_t *lambda_ptr, const int32_t *fpa_index,
-                              const float *value, int forced_box, bool keep_zeros, int region_gx) {
+                              const float *value, int forced_box, bool keep_zeros, int region_shape) {
     HostTables &T = p->ht;
     const int32_t w = p->w, gamma = p->gamma, xi = p->xi, a = p->a, alpha = p->alpha;
     const int64_t n = p->n;
@@ -342,10 +342,10 @@ ctis_status build_host_tables(ctis_plan *p, const int64_t *lambda_ptr, const int
     //       image, and whether the region path's padded copy of f is exact --
     ctis_status st = build_grid(T, p, kTileFast, kTileSlow, T.tiles);
     if (st != CTIS_OK) return st;
-    T.region_gx = region_gx ? region_gx : 4;
-    st = build_grid(T, p, region_fast(T.region_gx), region_slow(T.region_gx), T.regions);
+    T.region_shape = region_shape ? region_shape : kDefaultRegionShape;
+    st = build_grid(T, p, region_fast(T.region_shape), region_slow(T.region_shape), T.regions);
     if (st != CTIS_OK) return st;
-    T.pad_ok = (int64_t)gamma - a >= halo_fast(T.region_gx, B) && (int64_t)xi - alpha >= halo_slow(T.region_gx, B);
+    T.pad_ok = (int64_t)gamma - a >= halo_fast(T.region_shape, B) && (int64_t)xi - alpha >= halo_slow(T.region_shape, B);
 
     // -- 7. field-stop tiling of the back projection ----------------------------
     T.nbx = (int32_t)ceil_div(a, kTileFast);
@@ -393,15 +393,16 @@ int32_t forward_waves(int64_t units, int64_t items, int32_t max_items, int B) {
     return std::max(min_waves(), std::min<int32_t>(max_waves(B), (int32_t)((avg + 2) / 4)));
 }
 
-// Region forward: a wave takes four boxes of its region at a time (one per
-// lane group), so a workgroup of W waves takes 4W per pass.  About one wave
-// per five boxes of the average unit, 1 to 4: more waves per workgroup leave
-// fewer workgroups resident per compute unit (measured on the 512^2 and
-// 1024^2 frames with 15 and 46 boxes per region: 3 and 4 waves best, 5 or
-// more a third slower).
-int32_t region_waves(int64_t units, int64_t items) {
+// Region forward: a wave takes G boxes of its region at a time (one per
+// lane group; G = 4 for regions of 256 pixels), so a workgroup of W waves
+// takes G W per pass.  About one wave per 5 G / 4 boxes of the average unit,
+// 1 to 4: more waves per workgroup leave fewer workgroups resident per
+// compute unit (measured on the 512^2 and 1024^2 frames with 15 and 46
+// boxes per 16 x 16 region: 3 and 4 waves best, 5 or more a third slower).
+int32_t region_waves(int64_t units, int64_t items, int shape) {
     const int64_t avg = units > 0 ? (items + units - 1) / units : 0;
-    return (int32_t)std::max<int64_t>(1, std::min<int64_t>(4, (avg + 4) / 5));
+    const int64_t g = 64 / region_gl(shape);
+    return (int32_t)std::max<int64_t>(1, std::min<int64_t>(4, (4 * avg + 5 * g - 1) / (5 * g)));
 }
 
 void push4(std::vector<int32_t> &v, int32_t a, int32_t b, int32_t c, int32_t d) {
@@ -528,16 +529,16 @@ ctis_status build_work(const std::vector<FrameRef> &frames, bool with_full, Host
     // padded copy of f for the region path: per frame and wavelength a block
     // of (a + 2 Hx) x (alpha + 2 Hy) floats, frames back to back.  The path
     // needs every frame to allow it, with one region shape.
-    const int gx = frames[0].plan->ht.region_gx;
-    const int Hx = halo_fast(gx, B), Hy = halo_slow(gx, B);
-    hw.region_gx = gx;
+    const int shape = frames[0].plan->ht.region_shape;
+    const int Hx = halo_fast(shape, B), Hy = halo_slow(shape, B);
+    hw.region_shape = shape;
     hw.halo_x = Hx;
     hw.halo_y = Hy;
     std::vector<int64_t> fp_base(frames.size(), 0);
     hw.pad_ok = true;
     for (size_t k = 0; k < frames.size(); ++k) {
         const ctis_plan *pl = frames[k].plan;
-        hw.pad_ok = hw.pad_ok && pl->ht.pad_ok && pl->ht.region_gx == gx;
+        hw.pad_ok = hw.pad_ok && pl->ht.pad_ok && pl->ht.region_shape == shape;
         fp_base[k] = hw.fp_floats;
         hw.fp_floats += (int64_t)pl->w * (pl->a + 2 * Hx) * (pl->alpha + 2 * Hy);
         hw.pad_rows = std::max(hw.pad_rows, pl->alpha + 2 * Hy);
@@ -672,7 +673,7 @@ ctis_status build_work(const std::vector<FrameRef> &frames, bool with_full, Host
     if (hw.pad_ok) {
         st = build_fwd(hw.fwd_pad, true, true, rchunk, hw.rsplit_meta, hw.n_rsplit, hw.rpartial_slots);
         if (st != CTIS_OK) return st;
-        hw.fwd_pad.waves = region_waves(hw.fwd_pad.n_units, count_items(hw.fwd_pad));
+        hw.fwd_pad.waves = region_waves(hw.fwd_pad.n_units, count_items(hw.fwd_pad), shape);
         for (size_t k = 0; k < frames.size(); ++k) {
             const ctis_plan *pl = frames[k].plan;
             const int64_t PB = (int64_t)(pl->a + 2 * Hx) * (pl->alpha + 2 * Hy);
@@ -878,7 +879,7 @@ ctis_status upload_work(const HostWork &hw, DevWork &dw) {
     dw.slot_entries_ptr = (const int32_t *)at(15);
     dw.slot_entries = (const int32_t *)at(16);
     dw.pad_ok = hw.pad_ok;
-    dw.region_gx = hw.region_gx;
+    dw.region_shape = hw.region_shape;
     dw.halo_x = hw.halo_x;
     dw.halo_y = hw.halo_y;
     if (hw.pad_ok) {

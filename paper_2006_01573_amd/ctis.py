@@ -21,7 +21,7 @@ CTIS_PLAN_HOST_ONLY = 0x1
 CTIS_PLAN_KEEP_ZEROS = 0x2
 CTIS_PLAN_TILE_PATH = 0x4
 # region shapes of the region EM path (pixels along gamma, xi), by CTIS_PLAN_REGION code
-REGION_SHAPES = [None, (8, 32), (16, 16), (32, 8)]
+REGION_SHAPES = [None, (8, 32), (16, 16), (32, 8), (16, 8), (8, 16), (8, 8)]
 CTIS_BATCH_PERSISTENT = 0x400
 CTIS_BATCH_TILE_PATH = 0x8000
 CTIS_BATCH_REGION_SOLO = 0x10000
@@ -626,7 +626,7 @@ class Batch:
     waves_region: waves per workgroup of the region forward; persistent:
     workgroups walk the unit list; tile_path: EM forward on FPA tiles even
     where the region path applies; region_solo: region forward with a lane
-    group per region (four regions per wavefront)."""
+    group per region (4, 8 or 16 regions per wavefront by region size)."""
 
     def __init__(self, plans, waves_forward: int = 0, waves_adjoint: int = 0, persistent: bool = False,
                  waves_region: int = 0, tile_path: bool = False, region_solo: bool = False):

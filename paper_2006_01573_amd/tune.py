@@ -2,12 +2,17 @@
 
 Candidate configurations of a batch:
 
-* forward projection: the region path with each region shape (16 x 16,
-  32 x 8 and 8 x 32 FPA pixels per lane group, i.e. two fast-axis widths and
-  two slow-axis heights around the square one) and 2, 3 or 4 wavefronts per
-  workgroup sharing each region's boxes, or with a lane group per region
-  ("solo": four regions per wavefront), or the tile path (64 x 16 FPA tiles)
-  with 1 (a wavefront per tile), 4, 8 or 16;
+* forward projection: the region path with each region shape of a group of
+  16 lanes (16 x 16, 32 x 8 and 8 x 32 FPA pixels, i.e. two fast-axis widths
+  and two slow-axis heights around the square one) and 2, 3 or 4 wavefronts
+  per workgroup sharing each region's boxes; or with a lane group per
+  region ("solo"), in those shapes (four regions per wavefront) and in the
+  smaller ones of groups of 8 and 4 lanes (16 x 8, 8 x 16: eight regions
+  per wavefront; 8 x 8: sixteen), which follow the edges of small box
+  images more closely; or the tile path (64 x 16 FPA tiles) with 1 (a
+  wavefront per tile), 4, 8 or 16.  (The cooperative kernel is not tried
+  with the smaller regions: with 8 or 16 groups per wavefront the short box
+  lists of a batch leave most of a pass's groups on empty records.)
 * one workgroup per work unit, or a persistent grid whose workgroups walk
   the unit list;
 * then, with the winning forward setup, the back projection's waves per
@@ -33,6 +38,7 @@ import numpy as np
 from . import ctis
 
 REGION_SHAPES = ((16, 16), (32, 8), (8, 32))
+SOLO_SHAPES = REGION_SHAPES + ((16, 8), (8, 16), (8, 8))
 REGION_WAVES = (2, 3, 4)
 TILE_WAVES = (1, 4, 8, 16)
 ADJOINT_WAVES = (1, 4, 8)
@@ -116,7 +122,7 @@ def _candidates(region_ok: bool, box: int):
     for pe in (False, True):
         if region_ok:
             out += [Choice("region", sh, w, pe, 0) for sh in REGION_SHAPES for w in REGION_WAVES]
-            out += [Choice("solo", sh, 4, pe, 0) for sh in REGION_SHAPES]
+            out += [Choice("solo", sh, 4, pe, 0) for sh in SOLO_SHAPES]
         out += [Choice("tile", None, w, pe, 0) for w in TILE_WAVES if w <= (16 if box <= 5 else 8)]
     return out
 

@@ -47,9 +47,9 @@ def test_status_strings_and_version(lib):
     assert re.fullmatch(r"\d+\.\d+\.\d+", lib.ctis_version().decode())
 
 
-def host_plan(geo, ptr, idx, val, box=0):
+def host_plan(geo, ptr, idx, val, box=0, region=0):
     return ctis.Plan(geo.a, geo.alpha, geo.w, geo.gamma, geo.xi, ptr, idx, val,
-                     box=box, host_only=True)
+                     box=box, host_only=True, region=region)
 
 
 def expect_status(code, fn, *a, **kw):
@@ -85,6 +85,10 @@ def test_validation_errors(lib):
     st = lib.ctis_plan_create(ctypes.byref(h), 3, 2, 2, 5, 4, ctypes.c_void_p(ptr.ctypes.data),
                               ctypes.c_void_p(idx.ctypes.data), ctypes.c_void_p(val.ctypes.data), 0x10000)
     assert st == 1 and not h.value
+    # region shape code 7 (CTIS_PLAN_REGION(7)) names no shape
+    st = lib.ctis_plan_create(ctypes.byref(h), 3, 2, 2, 5, 4, ctypes.c_void_p(ptr.ctypes.data),
+                              ctypes.c_void_p(idx.ctypes.data), ctypes.c_void_p(val.ctypes.data), 0x1 | (7 << 12))
+    assert st == 1 and not h.value and "region shape" in lib.ctis_last_error().decode()
     assert lib.ctis_plan_create(None, 3, 2, 2, 5, 4, None, None, None, 1) == 1
 
 
@@ -205,18 +209,20 @@ def test_worklist_matches_brute_force(oracle_mod, lib, name, geo, nnz, clustered
         assert got[t], f"support pixel {i} in an inactive tile"
 
 
+@pytest.mark.parametrize("region", [0] + ctis.REGION_SHAPES[1:], ids=lambda r: f"{r[0]}x{r[1]}" if r else "default")
 @pytest.mark.parametrize("name,geo,nnz,clustered", CASES + [
     ("margins", W.Geometry(23, 11, 3, 60, 44), 7, False),
     ("margins-clustered", W.Geometry(16, 12, 4, 64, 48), 9, True)])
-def test_region_grid_matches_brute_force(oracle_mod, lib, name, geo, nnz, clustered):
-    """The region path's 16 x 16 grid: the same cover rule as the tiles."""
+def test_region_grid_matches_brute_force(oracle_mod, lib, name, geo, nnz, clustered, region):
+    """The region path's grid (16 x 16 by default, every shape on request):
+    the same cover rule as the tiles."""
     rng = np.random.default_rng(zlib.crc32(name.encode()) % 10_000 + 7)
     ptr, idx, val = W.random_kernels(geo, nnz, rng, clustered=clustered)
-    p = host_plan(geo, ptr, idx, val)
+    p = host_plan(geo, ptr, idx, val, region=region)
     inf = p.info
     _, rc, _ = p.boxes()
     rp, ib = p.regions()
-    assert (inf.region_fast, inf.region_slow) == (16, 16)
+    assert (inf.region_fast, inf.region_slow) == (tuple(region) if region else (16, 16))
     assert rp[0] == 0 and rp[-1] == inf.n_region_items and np.all(np.diff(rp) >= 0)
     got = {t: set(ib[rp[t]:rp[t + 1]].tolist()) for t in range(inf.n_regions)}
     want = {t: set() for t in range(inf.n_regions)}
@@ -227,7 +233,7 @@ def test_region_grid_matches_brute_force(oracle_mod, lib, name, geo, nnz, cluste
     assert inf.n_active_regions == sum(1 for t in want if want[t])
     # executed multiply-adds: B*B per box slot and output of every item
     BB = inf.box ** 2
-    assert inf.region_forward_madds == inf.n_region_items * 256 * BB
+    assert inf.region_forward_madds == inf.n_region_items * inf.region_fast * inf.region_slow * BB
     assert inf.tile_forward_madds == inf.n_items * inf.tile_fast * inf.tile_slow * BB
     assert inf.method_madds == geo.ell * inf.nnz
 

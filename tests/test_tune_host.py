@@ -16,6 +16,15 @@ def test_every_candidate_label_round_trips():
             assert tune.Choice.parse(ch.label()) == ch
 
 
+def test_candidate_region_shapes_are_plan_shapes():
+    # every shape the tuner tries is one the plan accepts; the smaller regions
+    # (groups of 8 and 4 lanes) only on the solo kernel
+    from paper_2006_01573_amd import ctis
+    cands = tune._candidates(True, 3)
+    assert {c.shape for c in cands if c.path == "solo"} == set(ctis.REGION_SHAPES[1:])
+    assert {c.shape for c in cands if c.path == "region"} == {(16, 16), (32, 8), (8, 32)}
+
+
 def test_candidates_respect_the_box_side():
     # more than 8 waves per workgroup only for B <= 5
     assert max(c.waves for c in tune._candidates(False, 5)) == 16
