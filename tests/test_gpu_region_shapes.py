@@ -160,3 +160,24 @@ def test_region_shape_c2_frame(torch, ctis, oracle_mod, shape):
     e, es = rel_l2(f, ref), rel_l2(fs, ref)
     log(f"  cooperative {e:.2e}, solo {es:.2e}")
     assert e <= EM_TOL and es <= EM_TOL
+
+
+def test_batch_of_mixed_region_shapes_takes_the_tile_path(torch, ctis, oracle_mod):
+    """Frames of one batch share the padded copy's border, so plans of
+    different region shapes put the batch on the tile path; with one shape
+    throughout it stays on the region path.  Both against the oracle."""
+    geo = geometry((16, 16), 3, 5)
+    rng = np.random.default_rng(77)
+    kern = W.random_kernels(geo, 7, rng, clustered=True)
+    o, g = frame(oracle_mod, geo, kern, rng)
+    ref = o.em(g, 3)
+    p16 = ctis.Plan(geo.a, geo.alpha, geo.w, geo.gamma, geo.xi, *kern, box=3, region=(16, 16))
+    p8 = ctis.Plan(geo.a, geo.alpha, geo.w, geo.gamma, geo.xi, *kern, box=3, region=(8, 8))
+    assert p16.info.em_region_path and p8.info.em_region_path
+    for plans, region in (([p16, p8], 0), ([p8, p8], 1)):
+        b = ctis.Batch(plans)
+        assert b.info["em_region_path"] == region
+        f = b.em(b.pack_g([g, g]), 3).cpu().numpy()
+        fo = b.f_offsets
+        for k in range(2):
+            assert rel_l2(f[fo[k]:fo[k + 1]], ref) <= EM_TOL
