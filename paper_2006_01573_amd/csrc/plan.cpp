@@ -395,13 +395,20 @@ int32_t forward_waves(int64_t units, int64_t items, int32_t max_items, int B) {
 
 // Region forward: a wave takes G boxes of its region at a time (one per
 // lane group; G = 4 for regions of 256 pixels), so a workgroup of W waves
-// takes G W per pass.  About one wave per 5 G / 4 boxes of the average unit,
-// 1 to 4: more waves per workgroup leave fewer workgroups resident per
-// compute unit (measured on the 512^2 and 1024^2 frames with 15 and 46
-// boxes per 16 x 16 region: 3 and 4 waves best, 5 or more a third slower).
-int32_t region_waves(int64_t units, int64_t items, int shape) {
-    const int64_t avg = units > 0 ? (items + units - 1) / units : 0;
+// takes G W per pass.  In the latency-bound regime (the units fit on the
+// chip at once) enough waves for the heaviest unit's boxes in one pass, up to
+// the workgroup's cap (a 128^2 frame with up to 17 boxes per 16 x 16 region:
+// 2 waves 10.6 us per EM iteration, 4 waves 10.0 us, 6 waves 9.7 us).
+// Otherwise about one
+// wave per 5 G / 4 boxes of the average unit, 1 to 4: more waves per
+// workgroup leave fewer workgroups resident per compute unit (measured on
+// the 512^2 and 1024^2 frames with 15 and 46 boxes per 16 x 16 region: 3
+// and 4 waves best, 5 or more a third slower).
+int32_t region_waves(int64_t units, int64_t items, int32_t max_items, int shape) {
     const int64_t g = 64 / region_gl(shape);
+    if (units <= kChipCUs)
+        return (int32_t)std::max<int64_t>(1, std::min<int64_t>(kFwdMaxWaves, (max_items + g - 1) / g));
+    const int64_t avg = units > 0 ? (items + units - 1) / units : 0;
     return (int32_t)std::max<int64_t>(1, std::min<int64_t>(4, (4 * avg + 5 * g - 1) / (5 * g)));
 }
 
@@ -659,6 +666,16 @@ ctis_status build_work(const std::vector<FrameRef> &frames, bool with_full, Host
         for (size_t k = 3; k < L.items.size(); k += 4) n += L.items[k] >= 0;
         return n;
     };
+    auto max_unit_items = [](const HostList &L) {   // most boxes of one unit
+        int32_t best = 0;
+        const size_t per = 4 * (size_t)L.stride;
+        for (size_t u = 0; u + per <= L.items.size(); u += per) {
+            int32_t n = 0;
+            for (size_t k = u + 3; k < u + per; k += 4) n += L.items[k] >= 0;
+            best = std::max(best, n);
+        }
+        return best;
+    };
     ctis_status st = CTIS_OK;
     if (with_full) {
         std::vector<int32_t> no_split;
@@ -673,7 +690,7 @@ ctis_status build_work(const std::vector<FrameRef> &frames, bool with_full, Host
     if (hw.pad_ok) {
         st = build_fwd(hw.fwd_pad, true, true, rchunk, hw.rsplit_meta, hw.n_rsplit, hw.rpartial_slots);
         if (st != CTIS_OK) return st;
-        hw.fwd_pad.waves = region_waves(hw.fwd_pad.n_units, count_items(hw.fwd_pad), shape);
+        hw.fwd_pad.waves = region_waves(hw.fwd_pad.n_units, count_items(hw.fwd_pad), max_unit_items(hw.fwd_pad), shape);
         for (size_t k = 0; k < frames.size(); ++k) {
             const ctis_plan *pl = frames[k].plan;
             const int64_t PB = (int64_t)(pl->a + 2 * Hx) * (pl->alpha + 2 * Hy);
