@@ -47,10 +47,11 @@ def kernel_source_sha() -> str:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def measured_traffic(config_id: int, kernel: str, choice: str | None = None):
+def measured_traffic(config_id: int, kernel: str, choice: str | None = None, split: int = 1):
     """HBM bytes per launch from committed rocprofv3 FETCH_SIZE / WRITE_SIZE
     counters, if they were taken on the current kernel source (and, for the
-    batch, with the same launch choice)."""
+    batch, with the same launch choice and number of concurrent batches,
+    whose launches of the kernel are then summed)."""
     try:
         with open(TRAFFIC_FILE) as fh:
             d = json.load(fh)
@@ -60,7 +61,7 @@ def measured_traffic(config_id: int, kernel: str, choice: str | None = None):
         return None
     w = d.get("workloads", {}).get(str(config_id), {})
     e = w.get(kernel)
-    if not e or (choice is not None and w.get("choice") != choice):
+    if not e or (choice is not None and (w.get("choice") != choice or int(w.get("split", 1)) != split)):
         return None
     return float(e["bytes_per_launch"])
 
@@ -153,6 +154,9 @@ def main(argv=None) -> int:
     ap.add_argument("--c4-choice", default="", metavar="LABEL",
                     help="config 4: one batch with this launch choice (as the tuner labels it, e.g. "
                          "'tile 64x16 W4 adjoint W1 Bauto') instead of autotuning")
+    ap.add_argument("--c4-split", type=int, default=1, metavar="N",
+                    help="config 4 with --c4-choice: the frames in N batches of about equal work, run "
+                         "concurrently on streams of their own (1..4; default 1: one batch)")
     ap.add_argument("--no-sequential", action="store_true",
                     help="config 4: skip the 64 sequential single-frame solves")
     ap.add_argument("--solver", choices=["em", "smart", "sart"], default="em",
@@ -465,9 +469,11 @@ def bench_batched(args, torch, ctis, W, dev) -> int:
         clean = p.forward(torch.from_numpy(c.f_true.astype(np.float32)).to(dev)).double().cpu().numpy()
         images.append(c.noisy(clean))
     if args.c4_choice:
-        progress(f"c4: one batch with the given launch choice ({args.c4_choice})")
+        if not 1 <= args.c4_split <= tune.MAX_CONCURRENT:
+            raise SystemExit(f"--c4-split must be in 1..{tune.MAX_CONCURRENT}")
+        progress(f"c4: the given launch choice ({args.c4_choice}), {args.c4_split} batch(es)")
         tuned = None
-        b = tune.fixed_frames(cases, tune.Choice.parse(args.c4_choice))
+        b = tune.fixed_frames(cases, tune.Choice.parse(args.c4_choice), split=args.c4_split)
     else:
         progress("c4: autotuning per frame shape")
         tuned = tune.autotune_frames(cases, images, iters=4, reps=3)
@@ -591,7 +597,10 @@ def bench_batched(args, torch, ctis, W, dev) -> int:
     t_hbm = bytes_[dom] / (HBM_PEAK_GBS * 1e9)
     t_alu = flops / (FP32_VALU_PEAK_TFLOPS * 1e12)
     groups = b.report()
-    traffic = measured_traffic(4, dom, groups[0]["choice"]) if len(groups) == 1 else None
+    # counters recorded for this launch choice and split (bytes of all of an
+    # iteration's launches of the kernel: one per batch)
+    same = len({g["choice"] for g in groups}) == 1 and (len(groups) == 1 or b.concurrent)
+    traffic = measured_traffic(4, dom, groups[0]["choice"], len(groups)) if same else None
     if t_hbm >= t_alu:
         achieved = bytes_[dom] / avg[dom] / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -615,7 +624,8 @@ def bench_batched(args, torch, ctis, W, dev) -> int:
                       "ms_per_iter_of_arrangements": tuned.ms_per_iter, "per_shape": tuned.classes,
                       "candidates_timed": len(tuned.table)}
     else:
-        tuned_info = {"arrangement": "given", "batches": b.report()}
+        tuned_info = {"arrangement": "given" + (f", {len(b.groups)} concurrent" if b.concurrent else ""),
+                      "batches": b.report()}
     line = {
         "metric": METRIC,
         "value": batched_fps,

@@ -21,13 +21,18 @@ Candidate configurations of a batch:
 * then the calibration box side B (the window halo is B - 1 pixels) one
   below and one above the plan's own choice, with the winning launch setup.
 
-Two arrangements are tuned and timed whole: every frame in one batch with
-one configuration (one launch per kernel and EM iteration), and a
-configuration per frame shape (field stop, wavelengths, FPA), each tuned on
-its shape's frames, with one batch per distinct winner run back to back.  The
-faster arrangement is kept (`TunedBatch`).  Timing uses HIP events on the
-current stream.  Nothing here changes results beyond the summation order of
-the projections.
+Arrangements are tuned and timed whole: every frame in one batch with one
+configuration (one launch per kernel and EM iteration); a configuration per
+frame shape (field stop, wavelengths, FPA), each tuned on its shape's
+frames, with one batch per distinct winner run back to back; and the same
+two run as concurrent groups -- the uniform configuration over two batches
+of about equal work, or the per-shape batches -- each group on a stream of
+its own (default priority) with its own slice of the workspace, so that one
+group's forward projection runs beside another's back projection and each
+fills the other's waits on memory (frames are independent: no exchange).
+The fastest arrangement is kept (`TunedBatch`).  Timing uses HIP events on
+the current stream.  Nothing here changes results beyond the summation order
+of the projections.
 """
 from __future__ import annotations
 
@@ -77,19 +82,34 @@ class Choice:
             raise ValueError(f"not a launch choice: {label!r}") from None
 
 
-def _time_em(torch, batch, g_all, iters: int, reps: int) -> float:
+def _time_em(torch, batch, g_all, iters: int, reps: int, graph: bool = False) -> float:
     """Best time (ms) of one EM iteration of the batch over `reps` runs of
-    `iters` iterations."""
+    `iters` iterations, launched from the stream or (``graph``) replayed from
+    a HIP graph of the run, as a solve is launched in production (concurrent
+    arrangements only pay off there: launched one by one, the host's launch
+    rate bounds them)."""
     ws = batch.workspace()
     f = torch.ones(batch.m_total, dtype=torch.float32, device=batch.device)
     batch.em(g_all, 1, f_all=f, workspace=ws)          # warm-up (code objects, caches)
+    run = lambda: batch.em(g_all, iters, f_all=f, workspace=ws)
+    if graph:
+        s = torch.cuda.Stream(device=batch.device)
+        s.wait_stream(torch.cuda.current_stream(batch.device))
+        with torch.cuda.stream(s):
+            run()                                      # outside the capture first
+        torch.cuda.current_stream(batch.device).wait_stream(s)
+        torch.cuda.synchronize()
+        gr = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gr):
+            run()
+        run = gr.replay
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     best = float("inf")
     for _ in range(reps):
         f.fill_(1.0)
         e0.record()
-        batch.em(g_all, iters, f_all=f, workspace=ws)
+        run()
         e1.record()
         torch.cuda.synchronize()
         best = min(best, e0.elapsed_time(e1) / iters)
@@ -172,14 +192,21 @@ def tune_frames(torch, cases, images, iters: int, reps: int, table: list, cls: s
     return best[1], best[0]
 
 
-class TunedBatch:
-    """Frames of uneven shapes, reconstructed as one batch per distinct tuned
-    configuration.  Buffers are packed in the tuned frame order: frame k
-    (original index) holds f_all[f_offsets[pos[k]] : ...] with pos the
-    inverse of `order`."""
+MAX_CONCURRENT = 4   # streams of concurrent groups (the hardware queues a process gets by default)
 
-    def __init__(self, cases, groups):
+
+class TunedBatch:
+    """Frames of uneven shapes, reconstructed as one batch per group (a tuned
+    configuration and its frames), the groups one after another or, with
+    ``concurrent``, side by side on streams of their own.  Buffers are packed
+    in the tuned frame order: frame k (original index) holds
+    f_all[f_offsets[pos[k]] : ...] with pos the inverse of `order`."""
+
+    def __init__(self, cases, groups, concurrent: bool = False):
         # groups: list of (choice, [original frame indices])
+        if concurrent and not 1 <= len(groups) <= MAX_CONCURRENT:
+            raise ValueError(f"concurrent arrangements take 1 to {MAX_CONCURRENT} groups")
+        self.concurrent = bool(concurrent) and len(groups) > 1
         self.groups = []
         self.order = [k for _, idx in groups for k in idx]
         self.pos = np.empty(len(self.order), np.int64)
@@ -201,6 +228,18 @@ class TunedBatch:
         self.f_offsets = np.array(self.f_offsets, np.int64)
         self.g_offsets = np.array(self.g_offsets, np.int64)
         self.device = self.groups[0][3].device
+        # workspace slices: one shared by sequential groups, one per group
+        # (256-byte aligned) for concurrent ones
+        need = [b.info["workspace_bytes"] for _, _, _, b, _, _ in self.groups]
+        if self.concurrent:
+            self.ws_offsets = list(np.cumsum([0] + [(n + 255) // 256 * 256 for n in need[:-1]]))
+            self.ws_bytes = int(self.ws_offsets[-1] + need[-1])
+            torch = ctis._torch()
+            self.streams = [torch.cuda.Stream(device=self.device) for _ in self.groups]
+        else:
+            self.ws_offsets = [0] * len(need)
+            self.ws_bytes = max(need)
+            self.streams = None
 
     @property
     def m_total(self) -> int:
@@ -218,10 +257,14 @@ class TunedBatch:
         return f_all[self.f_offsets[j]:self.f_offsets[j + 1]]
 
     def workspace(self):
-        """One workspace for every group (the groups run one after another)."""
+        """One workspace for every group: shared when the groups run one after
+        another, a slice per group when they run concurrently."""
         torch = ctis._torch()
-        nbytes = max(b.info["workspace_bytes"] for _, _, _, b, _, _ in self.groups)
-        return torch.empty(max(nbytes // 4, 64), dtype=torch.float32, device=self.device)
+        return torch.empty(max((self.ws_bytes + 3) // 4, 64), dtype=torch.float32, device=self.device)
+
+    def _ws_slice(self, workspace, j):
+        off = int(self.ws_offsets[j]) // 4
+        return workspace[off:off + (self.groups[j][3].info["workspace_bytes"] + 3) // 4]
 
     def em(self, g_all, iters: int, f_all=None, workspace=None):
         torch = ctis._torch()
@@ -229,8 +272,24 @@ class TunedBatch:
             f_all = torch.ones(self.m_total, dtype=torch.float32, device=self.device)
         if workspace is None:
             workspace = self.workspace()
-        for _, _, _, b, f0, g0 in self.groups:
-            b.em(g_all[g0:g0 + b.n_total], iters, f_all=f_all[f0:f0 + b.m_total], workspace=workspace)
+        if workspace.numel() * 4 < self.ws_bytes:
+            raise ValueError(f"workspace of {workspace.numel() * 4} bytes; the arrangement needs {self.ws_bytes}")
+        if not self.concurrent:
+            for _, _, _, b, f0, g0 in self.groups:
+                b.em(g_all[g0:g0 + b.n_total], iters, f_all=f_all[f0:f0 + b.m_total], workspace=workspace)
+            return f_all
+        # fork: every group's stream waits for the work queued so far, runs
+        # its batch, and the current stream waits for all of them (HIP graph
+        # capture records the branches as parallel nodes)
+        cur = torch.cuda.current_stream(self.device)
+        for st in self.streams:
+            st.wait_stream(cur)
+        for j, (st, (_, _, _, b, f0, g0)) in enumerate(zip(self.streams, self.groups)):
+            with torch.cuda.stream(st):
+                b.em(g_all[g0:g0 + b.n_total], iters, f_all=f_all[f0:f0 + b.m_total],
+                     workspace=self._ws_slice(workspace, j))
+        for st in self.streams:
+            cur.wait_stream(st)
         return f_all
 
     def report(self):
@@ -250,16 +309,34 @@ class TunedBatch:
 @dataclasses.dataclass
 class TuneResult:
     batch: TunedBatch
-    arrangement: str              # "uniform" or "per shape"
-    ms_per_iter: dict             # whole-batch EM iteration time of both arrangements
+    arrangement: str              # "uniform", "per shape", "uniform, 2 concurrent" or "per shape, concurrent"
+    ms_per_iter: dict             # whole-batch EM iteration time of every arrangement (graph-launched)
     uniform: str                  # the uniform arrangement's configuration
     classes: list                 # per frame shape: its frames and the configuration tuned on them
     table: list                   # every timing
 
 
-def fixed_frames(cases, choice: Choice) -> TunedBatch:
-    """Every frame in one batch with a given configuration (no tuning)."""
-    return TunedBatch(cases, [(choice, list(range(len(cases))))])
+def balanced_split(cases, n: int):
+    """The frames in n groups of about equal work (one EM iteration's
+    multiply-adds, a alpha w times the calibration entries per wavelength):
+    heaviest first, each to the lightest group so far; original order inside
+    a group."""
+    work = [c.geometry.a * c.geometry.alpha * int(c.lambda_ptr[-1]) for c in cases]
+    load = [0] * n
+    groups = [[] for _ in range(n)]
+    for k in sorted(range(len(cases)), key=lambda k: (-work[k], k)):
+        j = min(range(n), key=lambda j: (load[j], j))
+        groups[j].append(k)
+        load[j] += work[k]
+    return [sorted(g) for g in groups if g]
+
+
+def fixed_frames(cases, choice: Choice, split: int = 1) -> TunedBatch:
+    """The frames with a given configuration (no tuning): one batch, or
+    `split` concurrent batches of about equal work."""
+    if split <= 1:
+        return TunedBatch(cases, [(choice, list(range(len(cases))))])
+    return TunedBatch(cases, [(choice, idx) for idx in balanced_split(cases, split)], concurrent=True)
 
 
 def autotune_frames(cases, images, iters: int = 4, reps: int = 3) -> TuneResult:
@@ -282,12 +359,16 @@ def autotune_frames(cases, images, iters: int = 4, reps: int = 3) -> TuneResult:
     merged = {}
     for _, ch, idx in chosen:
         merged.setdefault(ch, []).extend(idx)
-    arrangements = {"uniform": [(uni, everything)],
-                    "per shape": [(ch, sorted(idx)) for ch, idx in merged.items()]}
+    per_shape = [(ch, sorted(idx)) for ch, idx in merged.items()]
+    arrangements = {"uniform": ([(uni, everything)], False),
+                    "per shape": (per_shape, False),
+                    "uniform, 2 concurrent": ([(uni, idx) for idx in balanced_split(cases, 2)], True)}
+    if 1 < len(per_shape) <= MAX_CONCURRENT:
+        arrangements["per shape, concurrent"] = (per_shape, True)
     timed = {}
-    for name, groups in arrangements.items():
-        tb = TunedBatch(cases, groups)
-        timed[name] = (_time_em(torch, tb, tb.pack_g(images), iters, reps), tb)
+    for name, (groups, conc) in arrangements.items():
+        tb = TunedBatch(cases, groups, concurrent=conc)
+        timed[name] = (_time_em(torch, tb, tb.pack_g(images), max(iters, 20), reps, graph=True), tb)
     keep = min(timed, key=lambda k: timed[k][0])
     for name, (_, tb) in timed.items():
         if name != keep:

@@ -235,3 +235,55 @@ def test_batch_em_in_a_hip_graph(torch, ctis, c4):
         torch.cuda.synchronize()
         assert torch.equal(f_all, ref), f"replay {rep} differs"
         del junk
+
+
+@pytest.mark.parametrize("split", [2, 4])
+def test_concurrent_batches_match_oracle_and_graph_replays(torch, ctis, c4, split):
+    """The 64 frames as `split` batches of about equal work run side by side on
+    streams of their own (one slice of the workspace each): every frame
+    against its oracle, bit for bit the same batches run one after another,
+    and the concurrent solve captured in a HIP graph reproduces the eager
+    result on every replay (eager work and synchronisations in between)."""
+    from paper_2006_01573_amd import tune
+    cfgs, cases, plans, images, expected = c4
+    K = cfgs[0].iters
+    choice = tune.Choice.parse("solo 32x8 W4 adjoint W1 Bauto")
+    tb = tune.fixed_frames(cases, choice, split=split)
+    assert tb.concurrent and len(tb.groups) == split
+    groups = [(ch, idx) for ch, idx, _, _, _, _ in tb.groups]
+    seq = tune.TunedBatch(cases, groups, concurrent=False)
+    assert seq.order == tb.order
+    g_all = tb.pack_g(images)
+    ws = tb.workspace()
+    f_all = tb.em(g_all, K, workspace=ws)
+    torch.cuda.synchronize()
+    f_seq = seq.em(g_all, K)
+    assert torch.equal(f_all, f_seq)
+    worst = max(rel_l2(tb.frame_f(f_all, k).cpu().numpy(), expected[k]) for k in range(len(cases)))
+    log(f"c4 {split} concurrent batches: worst rel-L2 {worst:.2e}")
+    assert worst <= EM_TOL
+    ref = f_all.clone()
+    f_g = torch.ones_like(ref)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        tb.em(g_all, 3, f_all=f_g, workspace=ws)           # warm-up outside the capture
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    ref3 = tb.em(g_all, 3, f_all=torch.ones_like(ref), workspace=ws).clone()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        f_g.fill_(1.0)
+        tb.em(g_all, 3, f_all=f_g, workspace=ws)
+    for rep in range(3):
+        junk = torch.rand(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(f_g, ref3), f"replay {rep} differs"
+        del junk
+    with pytest.raises(ValueError):
+        tb.em(g_all, 1, workspace=torch.empty(16, device="cuda"))
+    tb.close()
+    seq.close()

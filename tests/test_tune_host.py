@@ -37,3 +37,24 @@ def test_candidates_respect_the_box_side():
 def test_malformed_labels_are_refused(label):
     with pytest.raises(ValueError):
         tune.Choice.parse(label)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4])
+def test_balanced_split_covers_every_frame_once(n):
+    from paper_2006_01573_amd import workloads as W
+    cfgs = W.batched_configs(64)
+    cases = [W.make_case(4, frame=k, cfg=c) for k, c in enumerate(cfgs)]
+    groups = tune.balanced_split(cases, n)
+    assert len(groups) == n
+    assert sorted(k for g in groups for k in g) == list(range(64))
+    assert all(g == sorted(g) for g in groups)
+    work = [c.geometry.a * c.geometry.alpha * int(c.lambda_ptr[-1]) for c in cases]
+    loads = [sum(work[k] for k in g) for g in groups]
+    # greedy heaviest-first: no group exceeds another by more than the heaviest frame
+    assert max(loads) - min(loads) <= max(work)
+
+
+def test_concurrent_arrangements_are_bounded():
+    assert tune.MAX_CONCURRENT == 4
+    with pytest.raises(ValueError):
+        tune.TunedBatch([], [(None, [])] * 5, concurrent=True)
