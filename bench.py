@@ -618,7 +618,12 @@ def bench_batched(args, torch, ctis, W, dev) -> int:
                  "other_kernel": {k: {"avg_launch_us": avg[k] * 1e6, "achieved_GBps": bytes_[k] / avg[k] / 1e9,
                                       "achieved_TFLOPs": flops / avg[k] / 1e12}
                                   for k in avg if k != dom},
-                 "hbm_GBps_per_iteration": (bytes_["forward_ratio"] + bytes_["adjoint_update"]) / it_s_total / 1e9})
+                 "hbm_GBps_per_iteration": (bytes_["forward_ratio"] + bytes_["adjoint_update"]) / it_s_total / 1e9,
+                 # the same bytes over the solve's own time per iteration (graph-launched, every batch of
+                 # the arrangement; concurrent batches overlap their kernels, which the per-kernel times
+                 # above, taken one batch at a time, do not show)
+                 "hbm_GBps_per_solve_iteration": (bytes_["forward_ratio"] + bytes_["adjoint_update"])
+                 / (ms * 1e-3 / (args.steps * K)) / 1e9})
     if tuned is not None:
         tuned_info = {"arrangement": tuned.arrangement, "batches": b.report(), "uniform_choice": tuned.uniform,
                       "ms_per_iter_of_arrangements": tuned.ms_per_iter, "per_shape": tuned.classes,
