@@ -287,3 +287,31 @@ def test_concurrent_batches_match_oracle_and_graph_replays(torch, ctis, c4, spli
         tb.em(g_all, 1, workspace=torch.empty(16, device="cuda"))
     tb.close()
     seq.close()
+
+
+def test_concurrent_batches_of_different_launch_choices(torch, ctis, c4):
+    """Per-shape groups with different kernels side by side (the 512^2 frames
+    on the tile path, the 256^2 frames on the solo region path, a third group
+    on the cooperative region path): every frame against its oracle and bit
+    for bit the same groups run one after another."""
+    from paper_2006_01573_amd import tune
+    cfgs, cases, plans, images, expected = c4
+    K = cfgs[0].iters
+    small = [k for k, c in enumerate(cases) if c.geometry.gamma == 256]
+    large = [k for k, c in enumerate(cases) if c.geometry.gamma != 256]
+    groups = [(tune.Choice.parse("tile 64x16 W4 adjoint W1 Bauto"), large[::2]),
+              (tune.Choice.parse("solo 32x8 W4 adjoint W1 Bauto"), small),
+              (tune.Choice.parse("region 16x16 W3 adjoint Wauto Bauto"), large[1::2])]
+    tb = tune.TunedBatch(cases, groups, concurrent=True)
+    seq = tune.TunedBatch(cases, groups, concurrent=False)
+    assert tb.concurrent and not seq.concurrent
+    g_all = tb.pack_g(images)
+    f_all = tb.em(g_all, K)
+    f_seq = seq.em(g_all, K)
+    torch.cuda.synchronize()
+    assert torch.equal(f_all, f_seq)
+    worst = max(rel_l2(tb.frame_f(f_all, k).cpu().numpy(), expected[k]) for k in range(len(cases)))
+    log(f"c4 mixed concurrent groups: worst rel-L2 {worst:.2e}")
+    assert worst <= EM_TOL
+    tb.close()
+    seq.close()
