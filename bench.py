@@ -859,7 +859,7 @@ def bench_differentiable(args, torch, ctis, W, dev) -> int:
         "vjp_call_all_frames_us": vjp_us,
         "vjp_vs_em_iteration": vjp_us / em_us,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(5, "derivative_call"),
                      "kernel": "one derivative call of all frames (4 projections + value partials + sums)",
                      "algorithmic_bytes_per_call": bytes_vjp},
     }
