@@ -399,11 +399,10 @@ int32_t forward_waves(int64_t units, int64_t items, int32_t max_items, int B) {
 // chip at once) enough waves for the heaviest unit's boxes in one pass, up to
 // the workgroup's cap (a 128^2 frame with up to 17 boxes per 16 x 16 region:
 // 2 waves 10.6 us per EM iteration, 4 waves 10.0 us, 6 waves 9.7 us).
-// Otherwise about one
-// wave per 5 G / 4 boxes of the average unit, 1 to 4: more waves per
-// workgroup leave fewer workgroups resident per compute unit (measured on
-// the 512^2 and 1024^2 frames with 15 and 46 boxes per 16 x 16 region: 3
-// and 4 waves best, 5 or more a third slower).
+// Otherwise about one wave per 5 G / 4 boxes of the average unit, 1 to 4:
+// more waves per workgroup leave fewer workgroups resident per compute unit
+// (measured on the 512^2 and 1024^2 frames with 15 and 46 boxes per 16 x 16
+// region: 3 and 4 waves best, 5 or more a third slower).
 int32_t region_waves(int64_t units, int64_t items, int32_t max_items, int shape) {
     const int64_t g = 64 / region_gl(shape);
     if (units <= kChipCUs)
