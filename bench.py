@@ -124,7 +124,8 @@ def cpu_baseline(case, g_host: np.ndarray, iters_per_step: int, seconds: float, 
 
 
 def region_arg(args, ctis):
-    """--region RXxRY as the plan's region shape (0: the plan's choice)."""
+    """--region RXxRY as the plan's region shape (0: the plan's choice);
+    ValueError for a shape the plan does not take."""
     if not args.region:
         return 0
     try:
@@ -132,8 +133,7 @@ def region_arg(args, ctis):
     except ValueError:
         shape = ()
     if shape not in ctis.REGION_SHAPES[1:]:
-        raise SystemExit(f"--region must be one of "
-                         f"{', '.join(f'{a}x{b}' for a, b in ctis.REGION_SHAPES[1:])}")
+        raise ValueError(f"--region must be one of {', '.join(f'{a}x{b}' for a, b in ctis.REGION_SHAPES[1:])}")
     return shape
 
 
@@ -185,6 +185,16 @@ def main(argv=None) -> int:
         return 2
     if args.steps < 1 or args.warmup < 0:
         print("bench.py: --steps must be >= 1 and --warmup >= 0", file=sys.stderr)
+        return 2
+    # options checked before anything touches a device
+    from paper_2006_01573_amd import ctis as _ctis, tune as _tune
+    try:
+        region_arg(args, _ctis)
+    except ValueError as exc:
+        print(f"bench.py: {exc}", file=sys.stderr)
+        return 2
+    if not 1 <= args.c4_split <= _tune.MAX_CONCURRENT or (args.c4_split > 1 and not args.c4_choice):
+        print(f"bench.py: --c4-split takes 1..{_tune.MAX_CONCURRENT} and goes with --c4-choice", file=sys.stderr)
         return 2
 
     import torch
@@ -469,8 +479,6 @@ def bench_batched(args, torch, ctis, W, dev) -> int:
         clean = p.forward(torch.from_numpy(c.f_true.astype(np.float32)).to(dev)).double().cpu().numpy()
         images.append(c.noisy(clean))
     if args.c4_choice:
-        if not 1 <= args.c4_split <= tune.MAX_CONCURRENT:
-            raise SystemExit(f"--c4-split must be in 1..{tune.MAX_CONCURRENT}")
         progress(f"c4: the given launch choice ({args.c4_choice}), {args.c4_split} batch(es)")
         tuned = None
         b = tune.fixed_frames(cases, tune.Choice.parse(args.c4_choice), split=args.c4_split)

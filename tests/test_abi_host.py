@@ -348,6 +348,23 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.stdout == ""
 
 
+@pytest.mark.parametrize("args,msg", [(["--region", "12x12"], "--region must be one of"),
+                                      (["--region", "wide"], "--region must be one of"),
+                                      (["--config", "4", "--c4-split", "5", "--c4-choice",
+                                        "solo 32x8 W4 adjoint W1 Bauto"], "--c4-split takes"),
+                                      (["--config", "4", "--c4-split", "2"], "--c4-split takes")])
+def test_bench_refuses_bad_options_before_the_gpu(args, msg):
+    """Malformed launch options exit with a message before anything touches a
+    device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *args],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2, r.stderr
+    assert msg in r.stderr
+    assert r.stdout == ""
+
+
 def test_tensor_arguments_are_checked_before_any_launch():
     """Every tensor the binding passes to the library by pointer goes through
     one validator (float32, contiguous, on the plan's device, exact element
