@@ -367,7 +367,8 @@ typedef struct {
     int64_t n_entries;             /* calibration entries of the distinct plans  */
     size_t vjp_workspace_bytes;    /* workspace of ctis_batch_em_vjp             */
     int32_t em_region_path;        /* 1 if EM takes the region path (every plan
-                                      allows it, CTIS_BATCH_TILE_PATH not set)  */
+                                      allows it, all with one region shape,
+                                      CTIS_BATCH_TILE_PATH not set)             */
     int32_t waves_region;
     int64_t region_units;
     size_t solve_workspace_bytes;  /* workspace of ctis_batch_solve_iterate with
