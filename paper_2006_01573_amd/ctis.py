@@ -302,6 +302,8 @@ class Plan:
             raise ValueError("lambda_ptr must have w+1 entries")
         if ptr.size and ptr[-1] > min(idx.size, val.size):
             raise ValueError("fpa_index/value shorter than lambda_ptr[w]")
+        if region and tuple(region) not in REGION_SHAPES[1:]:
+            raise ValueError(f"region must be one of {REGION_SHAPES[1:]} (pixels along gamma, xi) or 0")
         flags = (CTIS_PLAN_BOX(box) | (CTIS_PLAN_HOST_ONLY if host_only else 0)
                  | (CTIS_PLAN_KEEP_ZEROS if keep_zeros else 0) | (CTIS_PLAN_TILE_PATH if tile_path else 0)
                  | (REGION_SHAPES.index(tuple(region)) << 12 if region else 0))

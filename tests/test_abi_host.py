@@ -336,6 +336,19 @@ def test_fourier_rejects_host_only_plans(lib):
     assert b"host-only" in lib.ctis_last_error()
 
 
+def test_plan_refuses_an_unknown_region_shape(lib):
+    geo = W.Geometry(3, 2, 2, 40, 40)
+    ptr = np.array([0, 1, 2], np.int64)
+    idx = np.array([0, 7], np.int32)
+    val = np.array([1.0, 0.5], np.float32)
+    for bad in [(12, 12), (16, 32), (4, 4)]:
+        with pytest.raises(ValueError, match="region must be one of"):
+            host_plan(geo, ptr, idx, val, region=bad)
+    for good in ctis.REGION_SHAPES[1:]:
+        assert (host_plan(geo, ptr, idx, val, region=good).info.region_fast,
+                host_plan(geo, ptr, idx, val, region=good).info.region_slow) == good
+
+
 def test_bench_refuses_more_than_one_gpu():
     """The measurement covers one GPU; asking for more exits with a message
     before anything touches a device."""
